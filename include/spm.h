@@ -1,0 +1,162 @@
+/*
+ * spm.h -- C ABI of libspm, a GPU builder of multi-source shortest path maps
+ * (SPMs) for polygonal scenes, after Farias & Kallmann, "Improved Shortest
+ * Path Maps with GPU Shaders".
+ *
+ * Problem (Section 3 and Section 4 of the paper): a rectangular domain
+ * [0,W] x [0,H] covered by a W x H pixel grid, polygonal obstacles with n
+ * vertices in total, point sources and segment sources.  For every pixel
+ * centre p the map stores lambda*(p), the length of the shortest
+ * obstacle-avoiding path from p to the closest source (a source point or any
+ * point of a segment source), and the parent: the first point that path turns
+ * at (an obstacle vertex) or the source itself.  Following parents gives the
+ * whole path (Section 1: grid lookup, then a walk linear in the path length).
+ *
+ * Units and conventions used by every entry point:
+ *   - coordinates are int32 domain units (1 unit = 1 pixel), 0 <= x <= W,
+ *     0 <= y <= H, with 1 <= W, H <= SPM_MAX_SIDE;
+ *   - pixel (i, j) has its centre at (i + 1/2, j + 1/2) and is stored at
+ *     row-major index j * W + i;
+ *   - obstacles are simple polygons given as counter-clockwise loops (the
+ *     obstacle lies to the left of every directed edge), without repeated or
+ *     collinear consecutive vertices, pairwise disjoint as closed sets;
+ *   - point sources lie strictly outside every closed obstacle; a segment
+ *     source has distinct endpoints and the closed segment meets no closed
+ *     obstacle;
+ *   - generators (the paper's DataArray entries, Section 3) are numbered in a
+ *     canonical order: point sources, then segment sources, then every
+ *     obstacle corner whose interior angle is below 180 degrees (the only
+ *     corners a shortest path can bend at), by polygon and vertex order.
+ *     Parent ids index this order.
+ *
+ * Errors: every entry point returns SPM_OK or a negative spm_status; no
+ * exception or abort crosses the ABI.  spm_last_error() gives a message for
+ * the calling thread's last failure.  Validation that can fail runs on the
+ * host before any device work is queued.
+ */
+#ifndef SPM_H
+#define SPM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SPM_MAX_SIDE 8192      /* largest W or H (keeps exact predicates in 32/64-bit integers) */
+#define SPM_N_STAGES 8         /* stages reported by spm_timer_elapsed */
+
+typedef enum {
+  SPM_OK = 0,
+  SPM_ERR_INVALID_ARG = -1,  /* null pointer, negative count, bad size */
+  SPM_ERR_GEOMETRY = -2,     /* polygon not simple/CCW, obstacles meet, source not free */
+  SPM_ERR_RANGE = -3,        /* a coordinate outside [0,W]x[0,H] or a side above SPM_MAX_SIDE */
+  SPM_ERR_CAPACITY = -4,     /* workspace or output buffer too small */
+  SPM_ERR_HIP = -5,          /* the HIP runtime reported an error */
+  SPM_ERR_UNREACHABLE = -6   /* spm_query_path: the query point has no path */
+} spm_status;
+
+enum { SPM_GEN_POINT = 0, SPM_GEN_SEGMENT = 1, SPM_GEN_VERTEX = 2 };
+
+/* A scene.  For spm_validate the arrays are host memory; for spm_build and
+ * spm_backward they are device memory.  The counts are always host values.
+ * Borrowed for the duration of the call only (device reads are complete when
+ * the queued work completes). */
+typedef struct {
+  int32_t width, height;     /* W, H */
+  int32_t n_polys;           /* number of obstacle polygons */
+  int32_t n_vertices;        /* total obstacle vertices = poly_start[n_polys] */
+  int32_t n_points;          /* point sources */
+  int32_t n_segs;            /* segment sources */
+  const int32_t* poly_start; /* [n_polys + 1] offsets into vx/vy, poly_start[0] = 0 */
+  const int32_t* vx;         /* [n_vertices] */
+  const int32_t* vy;         /* [n_vertices] */
+  const int32_t* pts;        /* [n_points * 2] (x, y) */
+  const int32_t* segs;       /* [n_segs * 4] (ax, ay, bx, by) */
+} spm_scene;
+
+/* Outputs of a build: device memory owned by the caller.  max_gen comes from
+ * spm_query_sizes. */
+typedef struct {
+  float* dist;          /* [H * W] lambda* in domain units; +inf inside or on an obstacle, or unreachable */
+  int32_t* parent;      /* [H * W] generator id of the winning cone; -1 where dist is +inf */
+  int32_t* gen_kind;    /* [max_gen] SPM_GEN_* */
+  int32_t* gen_xy;      /* [max_gen * 4] x, y (and x2, y2 for segments; else repeated) */
+  double* gen_cost;     /* [max_gen] lambda* of the generator (0 for sources, +inf unreachable) */
+  int32_t* gen_parent;  /* [max_gen] next generator toward the source; a source stores its own id; -1 unreachable */
+  int32_t* n_gen;       /* [1] number of generators G */
+} spm_out;
+
+const char* spm_last_error(void);
+
+/* Exact host-side check of a host-memory scene against the conventions above
+ * (O(n^2) in the vertex count).  Returns SPM_OK, SPM_ERR_INVALID_ARG,
+ * SPM_ERR_RANGE or SPM_ERR_GEOMETRY.  spm_build does not repeat this check. */
+int spm_validate(const spm_scene* host_scene);
+
+/* Capacities for a scene's counts (only the scalar fields are read):
+ * max_gen = n_points + n_segs + n_vertices, and the device workspace bytes a
+ * build needs.  Returns SPM_ERR_INVALID_ARG / SPM_ERR_RANGE for bad counts. */
+int spm_query_sizes(const spm_scene* scene, int32_t* max_gen, size_t* workspace_bytes);
+
+/* Build the map (all steps on the device, queued on `stream`, a hipStream_t;
+ * NULL = the null stream).  Returns after queueing; no host synchronisation
+ * and no device allocation happen inside, so the call can be captured in a
+ * HIP graph.  d_ws must hold workspace_bytes from spm_query_sizes and stays
+ * owned by the caller; it must not be shared by builds that can run
+ * concurrently.  The scene must satisfy spm_validate (unchecked here). */
+int spm_build(const spm_scene* dev_scene, const spm_out* out, void* d_ws, size_t ws_bytes, void* stream);
+
+/* Optional per-stage timing: a timer records HIP events around each build
+ * stage on the build's stream.  spm_timer_elapsed synchronises on the last
+ * recorded event and returns the per-stage milliseconds summed over every
+ * build recorded since the last reset (stage order: ingest, edge sort,
+ * inside mask, generator visibility, relaxation, generator sort, pixel
+ * propagation, total) and the number of builds. */
+typedef struct spm_timer spm_timer;
+int spm_timer_create(spm_timer** t);
+int spm_timer_destroy(spm_timer* t);
+int spm_timer_reset(spm_timer* t);
+int spm_timer_elapsed(spm_timer* t, float* ms /* [SPM_N_STAGES] */, int32_t* n_builds);
+
+/* Build options.  tile_w x tile_h is the pixel tile one wavefront owns
+ * (8x8, 16x4 or 4x16; 0 = 8x8).  d_stats, when not NULL, selects the
+ * instrumented pixel kernel, which adds its work counters (unsigned 64-bit:
+ * [0] tiles, [1] generator batches, [2] lane bound tests, [3] wave
+ * visibility tests, [4] edge relevance tests, [5] lane edge tests,
+ * [6] occluded tiles, [7] accepted candidates) to the 8 device counters. */
+typedef struct {
+  int32_t tile_w, tile_h;
+  spm_timer* timer;
+  uint64_t* d_stats;
+} spm_build_opts;
+int spm_build_ex(const spm_scene* dev_scene, const spm_out* out, void* d_ws, size_t ws_bytes, void* stream,
+                 const spm_build_opts* opts);
+
+/* Host copy of a built map for path queries. */
+typedef struct {
+  int32_t width, height;
+  const int32_t* parent;     /* [H * W] */
+  int32_t n_gen;
+  const int32_t* gen_kind;   /* [n_gen] */
+  const int32_t* gen_xy;     /* [n_gen * 4] */
+  const int32_t* gen_parent; /* [n_gen] */
+  const double* gen_cost;    /* [n_gen] */
+} spm_map_host;
+
+/* Shortest path from the query point q (domain units, inside the domain) to
+ * its closest source, read from the map (Section 1: constant-time grid
+ * lookup of the parent, then the chain of parents, linear in the path
+ * length).  Writes the polyline q, parent, ..., source point (the last point
+ * is the closest point of a segment source when the path ends on one) as
+ * float pairs to out_xy[2 * cap], its vertex count to *n_out and its length
+ * to *out_len.  Host memory only; no device work.  SPM_ERR_UNREACHABLE when
+ * q's pixel has no parent, SPM_ERR_CAPACITY when cap is too small. */
+int spm_query_path(const spm_map_host* map, float qx, float qy, float* out_xy, int32_t cap, int32_t* n_out,
+                   float* out_len);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SPM_H */

@@ -1,0 +1,417 @@
+// spm_api.cpp -- the C ABI of libspm (declared in include/spm.h).
+//
+// Host responsibilities only: argument checks, exact scene validation,
+// workspace layout, stage timing and kernel queueing.  Every step of the map
+// computation runs in the HIP kernels of k_ingest.hip, k_graph.hip and
+// k_pixel.hip; spm_query_path walks a host copy of a built map.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "spm_internal.hpp"
+
+using namespace spm;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+int ok() {
+  g_err.clear();
+  return SPM_OK;
+}
+
+int check_counts(const spm_scene* s) {
+  if (!s) return fail(SPM_ERR_INVALID_ARG, "scene is NULL");
+  if (s->width < 1 || s->height < 1 || s->width > SPM_MAX_SIDE || s->height > SPM_MAX_SIDE)
+    return fail(SPM_ERR_RANGE, "width/height %d x %d outside [1, %d]", s->width, s->height, SPM_MAX_SIDE);
+  if (s->n_polys < 0 || s->n_vertices < 0 || s->n_points < 0 || s->n_segs < 0)
+    return fail(SPM_ERR_INVALID_ARG, "negative count");
+  if (s->n_polys == 0 && s->n_vertices != 0) return fail(SPM_ERR_INVALID_ARG, "vertices without polygons");
+  if (s->n_polys > 0 && s->n_vertices < 3 * s->n_polys)
+    return fail(SPM_ERR_INVALID_ARG, "fewer than 3 vertices per polygon");
+  if ((long long)s->n_points + s->n_segs + s->n_vertices > (1ll << 30))
+    return fail(SPM_ERR_INVALID_ARG, "too many generators");
+  if (s->n_points + s->n_segs == 0) return fail(SPM_ERR_INVALID_ARG, "no source");
+  return SPM_OK;
+}
+
+int check_ptrs(const spm_scene* s) {
+  if (s->n_polys > 0 && (!s->poly_start || !s->vx || !s->vy))
+    return fail(SPM_ERR_INVALID_ARG, "polygon arrays are NULL");
+  if (s->n_points > 0 && !s->pts) return fail(SPM_ERR_INVALID_ARG, "pts is NULL");
+  if (s->n_segs > 0 && !s->segs) return fail(SPM_ERR_INVALID_ARG, "segs is NULL");
+  return SPM_OK;
+}
+
+// ---------------------------------------------------------------- validation
+typedef long long ll;
+
+struct P2 {
+  ll x, y;
+};
+
+inline ll cross(P2 o, P2 a, P2 b) { return (a.x - o.x) * (b.y - o.y) - (a.y - o.y) * (b.x - o.x); }
+inline int sgn(ll v) { return (v > 0) - (v < 0); }
+
+inline bool on_seg(P2 a, P2 b, P2 p) {  // p on closed segment [a,b], given collinear
+  return std::min(a.x, b.x) <= p.x && p.x <= std::max(a.x, b.x) && std::min(a.y, b.y) <= p.y &&
+         p.y <= std::max(a.y, b.y);
+}
+
+bool seg_meet(P2 a, P2 b, P2 c, P2 d) {  // closed segments share a point
+  int d1 = sgn(cross(c, d, a)), d2 = sgn(cross(c, d, b)), d3 = sgn(cross(a, b, c)), d4 = sgn(cross(a, b, d));
+  if (d1 * d2 < 0 && d3 * d4 < 0) return true;
+  if (d1 == 0 && on_seg(c, d, a)) return true;
+  if (d2 == 0 && on_seg(c, d, b)) return true;
+  if (d3 == 0 && on_seg(a, b, c)) return true;
+  if (d4 == 0 && on_seg(a, b, d)) return true;
+  return false;
+}
+
+// p inside or on the boundary of polygon [a, b) of the vertex arrays
+bool in_closed_poly(const int* vx, const int* vy, int a, int b, P2 p) {
+  bool in = false;
+  for (int i = a; i < b; ++i) {
+    int k = (i + 1 < b) ? i + 1 : a;
+    P2 u{vx[i], vy[i]}, v{vx[k], vy[k]};
+    ll c = cross(u, v, p);
+    if (c == 0 && on_seg(u, v, p)) return true;
+    if ((u.y > p.y) != (v.y > p.y)) {
+      if ((c > 0) == (v.y > u.y)) in = !in;
+    }
+  }
+  return in;
+}
+
+struct Seg {
+  P2 a, b;
+  int poly, idx;  // idx: position within the polygon, -1 for a source segment
+  ll x0, x1;
+};
+
+}  // namespace
+
+extern "C" {
+
+const char* spm_last_error(void) { return g_err.c_str(); }
+
+int spm_validate(const spm_scene* s) {
+  int rc = check_counts(s);
+  if (rc) return rc;
+  if ((rc = check_ptrs(s))) return rc;
+  const int W = s->width, H = s->height;
+  if (s->n_polys > 0) {
+    if (s->poly_start[0] != 0) return fail(SPM_ERR_INVALID_ARG, "poly_start[0] != 0");
+    for (int p = 0; p < s->n_polys; ++p)
+      if (s->poly_start[p + 1] - s->poly_start[p] < 3)
+        return fail(SPM_ERR_GEOMETRY, "polygon %d has fewer than 3 vertices", p);
+    if (s->poly_start[s->n_polys] != s->n_vertices)
+      return fail(SPM_ERR_INVALID_ARG, "poly_start[n_polys] != n_vertices");
+  }
+  for (int i = 0; i < s->n_vertices; ++i)
+    if (s->vx[i] < 0 || s->vx[i] > W || s->vy[i] < 0 || s->vy[i] > H)
+      return fail(SPM_ERR_RANGE, "vertex %d (%d,%d) outside the domain", i, s->vx[i], s->vy[i]);
+  for (int i = 0; i < s->n_points; ++i)
+    if (s->pts[2 * i] < 0 || s->pts[2 * i] > W || s->pts[2 * i + 1] < 0 || s->pts[2 * i + 1] > H)
+      return fail(SPM_ERR_RANGE, "point source %d outside the domain", i);
+  for (int i = 0; i < s->n_segs; ++i)
+    for (int k = 0; k < 2; ++k)
+      if (s->segs[4 * i + 2 * k] < 0 || s->segs[4 * i + 2 * k] > W || s->segs[4 * i + 2 * k + 1] < 0 ||
+          s->segs[4 * i + 2 * k + 1] > H)
+        return fail(SPM_ERR_RANGE, "segment source %d outside the domain", i);
+  // per polygon: distinct consecutive vertices, no collinear triple, counter-clockwise
+  for (int p = 0; p < s->n_polys; ++p) {
+    const int a = s->poly_start[p], b = s->poly_start[p + 1];
+    ll area2 = 0;
+    for (int i = a; i < b; ++i) {
+      const int ip = (i == a) ? b - 1 : i - 1, in = (i + 1 < b) ? i + 1 : a;
+      P2 u{s->vx[ip], s->vy[ip]}, w{s->vx[i], s->vy[i]}, v{s->vx[in], s->vy[in]};
+      if (w.x == v.x && w.y == v.y) return fail(SPM_ERR_GEOMETRY, "polygon %d repeats vertex %d", p, i - a);
+      if (cross(u, w, v) == 0) return fail(SPM_ERR_GEOMETRY, "polygon %d: collinear corner at vertex %d", p, i - a);
+      area2 += w.x * v.y - v.x * w.y;
+    }
+    if (area2 <= 0) return fail(SPM_ERR_GEOMETRY, "polygon %d is not counter-clockwise", p);
+  }
+  // all edges (obstacles and source segments), swept by min x
+  std::vector<Seg> segs;
+  segs.reserve((size_t)s->n_vertices + s->n_segs);
+  for (int p = 0; p < s->n_polys; ++p) {
+    const int a = s->poly_start[p], b = s->poly_start[p + 1];
+    for (int i = a; i < b; ++i) {
+      const int in = (i + 1 < b) ? i + 1 : a;
+      Seg e{{s->vx[i], s->vy[i]}, {s->vx[in], s->vy[in]}, p, i - a, 0, 0};
+      e.x0 = std::min(e.a.x, e.b.x);
+      e.x1 = std::max(e.a.x, e.b.x);
+      segs.push_back(e);
+    }
+  }
+  for (int k = 0; k < s->n_segs; ++k) {
+    Seg e{{s->segs[4 * k], s->segs[4 * k + 1]}, {s->segs[4 * k + 2], s->segs[4 * k + 3]}, -1 - k, -1, 0, 0};
+    if (e.a.x == e.b.x && e.a.y == e.b.y) return fail(SPM_ERR_GEOMETRY, "segment source %d has zero length", k);
+    e.x0 = std::min(e.a.x, e.b.x);
+    e.x1 = std::max(e.a.x, e.b.x);
+    segs.push_back(e);
+  }
+  std::vector<int> order(segs.size());
+  for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
+  std::sort(order.begin(), order.end(), [&](int x, int y) { return segs[x].x0 < segs[y].x0; });
+  for (size_t oi = 0; oi < order.size(); ++oi) {
+    const Seg& e = segs[order[oi]];
+    for (size_t oj = oi + 1; oj < order.size(); ++oj) {
+      const Seg& f = segs[order[oj]];
+      if (f.x0 > e.x1) break;
+      if (e.poly < 0 && f.poly < 0) continue;  // two sources may cross
+      if (std::max(std::min(e.a.y, e.b.y), std::min(f.a.y, f.b.y)) >
+          std::min(std::max(e.a.y, e.b.y), std::max(f.a.y, f.b.y)))
+        continue;
+      if (e.poly == f.poly && e.poly >= 0) {
+        const int n = s->poly_start[e.poly + 1] - s->poly_start[e.poly];
+        const int d = std::abs(e.idx - f.idx);
+        if (d == 1 || d == n - 1) continue;  // neighbours share exactly one vertex (no collinear corner)
+      }
+      if (seg_meet(e.a, e.b, f.a, f.b)) {
+        if (e.poly >= 0 && f.poly >= 0) {
+          if (e.poly == f.poly) return fail(SPM_ERR_GEOMETRY, "polygon %d is not simple", e.poly);
+          return fail(SPM_ERR_GEOMETRY, "obstacles %d and %d meet", e.poly, f.poly);
+        }
+        return fail(SPM_ERR_GEOMETRY, "segment source %d meets an obstacle", e.poly < 0 ? -1 - e.poly : -1 - f.poly);
+      }
+    }
+  }
+  // nesting between polygons (edges are disjoint, so test one vertex)
+  for (int p = 0; p < s->n_polys; ++p) {
+    const int a = s->poly_start[p], b = s->poly_start[p + 1];
+    for (int q = 0; q < s->n_polys; ++q) {
+      if (q == p) continue;
+      const int c = s->poly_start[q], d = s->poly_start[q + 1];
+      if (in_closed_poly(s->vx, s->vy, c, d, P2{s->vx[a], s->vy[a]}))
+        return fail(SPM_ERR_GEOMETRY, "obstacle %d lies inside obstacle %d", p, q);
+      (void)b;
+    }
+  }
+  for (int k = 0; k < s->n_points; ++k) {
+    P2 p{s->pts[2 * k], s->pts[2 * k + 1]};
+    for (int q = 0; q < s->n_polys; ++q)
+      if (in_closed_poly(s->vx, s->vy, s->poly_start[q], s->poly_start[q + 1], p))
+        return fail(SPM_ERR_GEOMETRY, "point source %d is inside or on obstacle %d", k, q);
+  }
+  for (int k = 0; k < s->n_segs; ++k) {
+    P2 p{s->segs[4 * k], s->segs[4 * k + 1]};
+    for (int q = 0; q < s->n_polys; ++q)
+      if (in_closed_poly(s->vx, s->vy, s->poly_start[q], s->poly_start[q + 1], p))
+        return fail(SPM_ERR_GEOMETRY, "segment source %d is inside obstacle %d", k, q);
+  }
+  return ok();
+}
+
+int spm_query_sizes(const spm_scene* s, int32_t* max_gen, size_t* workspace_bytes) {
+  int rc = check_counts(s);
+  if (rc) return rc;
+  Layout L = make_layout(s->width, s->height, s->n_polys, s->n_vertices, s->n_points, s->n_segs);
+  if (max_gen) *max_gen = L.Gmax;
+  if (workspace_bytes) *workspace_bytes = L.total;
+  return ok();
+}
+
+// ---------------------------------------------------------------- timer
+struct spm_timer {
+  int cap = 0;
+  int n = 0;
+  std::vector<hipEvent_t> ev;  // cap * (SPM_N_STAGES) events: boundaries of the 7 stages + 1
+};
+
+int spm_timer_create(spm_timer** t) {
+  if (!t) return fail(SPM_ERR_INVALID_ARG, "timer out pointer is NULL");
+  spm_timer* x = new (std::nothrow) spm_timer();
+  if (!x) return fail(SPM_ERR_INVALID_ARG, "out of host memory");
+  x->cap = 256;
+  x->ev.resize((size_t)x->cap * SPM_N_STAGES);
+  for (auto& e : x->ev) {
+    if (hipEventCreate(&e) != hipSuccess) {
+      delete x;
+      return fail(SPM_ERR_HIP, "hipEventCreate failed");
+    }
+  }
+  *t = x;
+  return ok();
+}
+
+int spm_timer_destroy(spm_timer* t) {
+  if (!t) return ok();
+  for (auto& e : t->ev) (void)hipEventDestroy(e);
+  delete t;
+  return ok();
+}
+
+int spm_timer_reset(spm_timer* t) {
+  if (!t) return fail(SPM_ERR_INVALID_ARG, "timer is NULL");
+  t->n = 0;
+  return ok();
+}
+
+int spm_timer_elapsed(spm_timer* t, float* ms, int32_t* n_builds) {
+  if (!t || !ms) return fail(SPM_ERR_INVALID_ARG, "timer or output is NULL");
+  for (int k = 0; k < SPM_N_STAGES; ++k) ms[k] = 0.0f;
+  const int n = std::min(t->n, t->cap);
+  if (n_builds) *n_builds = n;
+  if (n == 0) return ok();
+  if (hipEventSynchronize(t->ev[(size_t)(n - 1) * SPM_N_STAGES + SPM_N_STAGES - 1]) != hipSuccess)
+    return fail(SPM_ERR_HIP, "hipEventSynchronize failed");
+  for (int b = 0; b < n; ++b) {
+    hipEvent_t* e = &t->ev[(size_t)b * SPM_N_STAGES];
+    for (int k = 0; k + 1 < SPM_N_STAGES; ++k) {
+      float x = 0.0f;
+      if (hipEventElapsedTime(&x, e[k], e[k + 1]) != hipSuccess) return fail(SPM_ERR_HIP, "hipEventElapsedTime failed");
+      ms[k] += x;
+    }
+    float tot = 0.0f;
+    if (hipEventElapsedTime(&tot, e[0], e[SPM_N_STAGES - 1]) != hipSuccess)
+      return fail(SPM_ERR_HIP, "hipEventElapsedTime failed");
+    ms[SPM_N_STAGES - 1] += tot;
+  }
+  return ok();
+}
+
+// ---------------------------------------------------------------- build
+int spm_build_ex(const spm_scene* s, const spm_out* out, void* d_ws, size_t ws_bytes, void* stream,
+                 const spm_build_opts* opts) {
+  int rc = check_counts(s);
+  if (rc) return rc;
+  if ((rc = check_ptrs(s))) return rc;
+  if (!out || !out->dist || !out->parent || !out->gen_kind || !out->gen_xy || !out->gen_cost || !out->gen_parent ||
+      !out->n_gen)
+    return fail(SPM_ERR_INVALID_ARG, "an output pointer is NULL");
+  Layout L = make_layout(s->width, s->height, s->n_polys, s->n_vertices, s->n_points, s->n_segs);
+  if (!d_ws) return fail(SPM_ERR_INVALID_ARG, "workspace is NULL");
+  if (ws_bytes < L.total) return fail(SPM_ERR_CAPACITY, "workspace has %zu bytes, needs %zu", ws_bytes, L.total);
+  int tw = 8;
+  if (opts && opts->tile_w) {
+    tw = opts->tile_w;
+    if (!((tw == 8 && opts->tile_h == 8) || (tw == 16 && opts->tile_h == 4) || (tw == 4 && opts->tile_h == 16)))
+      return fail(SPM_ERR_INVALID_ARG, "unsupported tile %d x %d", opts->tile_w, opts->tile_h);
+  }
+  char* ws = (char*)d_ws;
+  Dev d{};
+  d.W = L.W; d.H = L.H; d.nv = L.nv; d.np = L.np; d.ns = L.ns; d.n_polys = s->n_polys;
+  d.E = L.E; d.NC = L.NC; d.Gmax = L.Gmax; d.RW = L.RW; d.W32 = L.W32;
+  d.poly_start = s->poly_start; d.vx = s->vx; d.vy = s->vy; d.pts = s->pts; d.segs = s->segs;
+  d.edges_raw = (EdgeRec*)(ws + L.off_edges_raw);
+  d.ext_raw = (EdgeExt*)(ws + L.off_ext_raw);
+  d.keys = (u64*)(ws + L.off_keys);
+  d.edges = (EdgeRec*)(ws + L.off_edges);
+  d.ext = (EdgeExt*)(ws + L.off_ext);
+  d.chunks = (int4*)(ws + L.off_chunks);
+  d.convex = (int*)(ws + L.off_convex);
+  d.gens = (GenRec*)(ws + L.off_gens);
+  d.vis = (u64*)(ws + L.off_vis);
+  d.sgen = (GenRec*)(ws + L.off_sgen);
+  d.sgcost = (float*)(ws + L.off_sgcost);
+  d.sgbb = (int4*)(ws + L.off_sgbb);
+  d.inside = (unsigned*)(ws + L.off_inside);
+  d.cost64 = (double*)(ws + L.off_cost64);
+  d.misc = (int*)(ws + L.off_misc);
+  d.dist = out->dist; d.parent = out->parent; d.gen_kind = out->gen_kind; d.gen_xy = out->gen_xy;
+  d.gen_cost = out->gen_cost; d.gen_parent = out->gen_parent; d.n_gen = out->n_gen;
+  d.tile_w = tw; d.tile_h = 64 / tw;
+  d.stats = opts ? (u64*)opts->d_stats : nullptr;
+  hipStream_t st = (hipStream_t)stream;
+  spm_timer* tm = opts ? opts->timer : nullptr;
+  hipEvent_t* ev = nullptr;
+  if (tm && tm->n < tm->cap) ev = &tm->ev[(size_t)tm->n * SPM_N_STAGES];
+  auto mark = [&](int k) -> int {
+    if (ev && hipEventRecord(ev[k], st) != hipSuccess) return fail(SPM_ERR_HIP, "hipEventRecord failed");
+    return SPM_OK;
+  };
+  typedef hipError_t (*Stage)(const Dev&, hipStream_t);
+  static const Stage stages[7] = {launch_ingest, launch_edge_sort, launch_inside, launch_genvis,
+                                  launch_relax,  launch_gsort,     launch_pixel};
+  static const char* names[7] = {"ingest", "edge sort", "inside mask", "generator visibility", "relaxation",
+                                 "generator sort", "pixel propagation"};
+  if ((rc = mark(0))) return rc;
+  for (int k = 0; k < 7; ++k) {
+    hipError_t e = stages[k](d, st);
+    if (e != hipSuccess) return fail(SPM_ERR_HIP, "%s launch failed: %s", names[k], hipGetErrorString(e));
+    if ((rc = mark(k + 1))) return rc;
+  }
+  if (ev) tm->n++;
+  return ok();
+}
+
+int spm_build(const spm_scene* s, const spm_out* out, void* d_ws, size_t ws_bytes, void* stream) {
+  return spm_build_ex(s, out, d_ws, ws_bytes, stream, nullptr);
+}
+
+// ---------------------------------------------------------------- path query
+int spm_query_path(const spm_map_host* m, float qx, float qy, float* out_xy, int32_t cap, int32_t* n_out,
+                   float* out_len) {
+  if (!m || !m->parent || !m->gen_kind || !m->gen_xy || !m->gen_parent || !out_xy || !n_out || !out_len)
+    return fail(SPM_ERR_INVALID_ARG, "NULL argument");
+  if (m->width < 1 || m->height < 1 || m->n_gen < 0) return fail(SPM_ERR_INVALID_ARG, "bad map sizes");
+  if (!(qx >= 0.0f && qy >= 0.0f && qx <= (float)m->width && qy <= (float)m->height))
+    return fail(SPM_ERR_RANGE, "query point outside the domain");
+  if (cap < 2) return fail(SPM_ERR_CAPACITY, "capacity below 2");
+  int i = std::min((int)std::floor(qx), m->width - 1), j = std::min((int)std::floor(qy), m->height - 1);
+  int g = m->parent[(size_t)j * m->width + i];
+  if (g < 0 || g >= m->n_gen) return fail(SPM_ERR_UNREACHABLE, "pixel (%d,%d) has no path", i, j);
+  int n = 0;
+  double len = 0.0, cx = qx, cy = qy;
+  out_xy[2 * n] = qx;
+  out_xy[2 * n + 1] = qy;
+  ++n;
+  int steps = 0;
+  while (m->gen_kind[g] == SPM_GEN_VERTEX) {
+    if (n >= cap) return fail(SPM_ERR_CAPACITY, "path longer than capacity %d", cap);
+    const double x = m->gen_xy[4 * g], y = m->gen_xy[4 * g + 1];
+    len += std::hypot(x - cx, y - cy);
+    cx = x;
+    cy = y;
+    out_xy[2 * n] = (float)x;
+    out_xy[2 * n + 1] = (float)y;
+    ++n;
+    const int nxt = m->gen_parent[g];
+    if (nxt < 0 || nxt >= m->n_gen || ++steps > m->n_gen) return fail(SPM_ERR_UNREACHABLE, "broken parent chain");
+    g = nxt;
+  }
+  if (n >= cap) return fail(SPM_ERR_CAPACITY, "path longer than capacity %d", cap);
+  double ex, ey;
+  if (m->gen_kind[g] == SPM_GEN_POINT) {
+    ex = m->gen_xy[4 * g];
+    ey = m->gen_xy[4 * g + 1];
+  } else {
+    // closest point of the segment source (Section 4: endpoint or projection)
+    const double ax = m->gen_xy[4 * g], ay = m->gen_xy[4 * g + 1], bx = m->gen_xy[4 * g + 2],
+                 by = m->gen_xy[4 * g + 3];
+    const double dx = bx - ax, dy = by - ay;
+    double t = ((cx - ax) * dx + (cy - ay) * dy) / (dx * dx + dy * dy);
+    t = std::min(1.0, std::max(0.0, t));
+    ex = ax + t * dx;
+    ey = ay + t * dy;
+  }
+  len += std::hypot(ex - cx, ey - cy);
+  out_xy[2 * n] = (float)ex;
+  out_xy[2 * n + 1] = (float)ey;
+  ++n;
+  *n_out = n;
+  *out_len = (float)len;
+  return ok();
+}
+
+}  // extern "C"

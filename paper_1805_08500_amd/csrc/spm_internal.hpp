@@ -1,0 +1,404 @@
+// spm_internal.hpp -- records, workspace layout and device helpers shared by
+// the libspm kernels (HIP, gfx950).  Not part of the public ABI.
+//
+// Geometry is carried in "doubled" integer coordinates: every domain
+// coordinate times 2, so the pixel centre (i + 1/2, j + 1/2) is the integer
+// point (2i + 1, 2j + 1).  With W, H <= 8192 every doubled coordinate is at
+// most 2^14, every coordinate difference fits in 15 signed bits, every
+// orientation determinant of three lattice points fits in 30 bits, and the
+// 24-bit integer multiply-add of the VALU is exact for all of them.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "../../include/spm.h"
+
+namespace spm {
+
+typedef unsigned long long u64;
+
+constexpr int kWave = 64;
+constexpr int kChunk = 64;        // edges per spatial chunk
+constexpr int kRelaxThreads = 1024;
+constexpr int kRelaxLdsMaxGen = 7680;   // keeps the relaxation LDS (costs + change masks) under 64 KB
+
+// One obstacle edge w -> v (obstacle on the left), with its line function
+// E(x, y) = a x + b y + c, positive on the obstacle side.
+struct EdgeRec {
+  int wx, wy, vx, vy;
+  int a, b, c, id;  // id: index of w in the input vertex order
+};
+// Neighbours needed by the vertex rule: prev(w) and next(v).
+struct EdgeExt {
+  int ux, uy, nx, ny;
+};
+
+// Generator record (canonical order and cost-sorted order share the layout).
+struct GenRec {
+  int kind, id;       // SPM_GEN_*; canonical id
+  int x, y;           // point / segment A / vertex (doubled)
+  int x2, y2;         // segment B (doubled); else = x, y
+  int ux, uy;         // VERTEX: previous vertex (doubled)
+  int nx, ny;         // VERTEX: next vertex (doubled)
+  float costf;        // cost rounded to float (sorted table only)
+  int vtx;            // VERTEX: input vertex index; else -1
+  int pad0, pad1, pad2, pad3;
+};
+static_assert(sizeof(GenRec) == 64, "GenRec must be 64 bytes");
+
+// misc ints in the workspace
+enum { MISC_G = 0, MISC_REACHED = 1, MISC_ROUNDS = 2, MISC_N = 16 };
+
+struct Layout {
+  int W, H, nv, np, ns, np_polys;
+  int E, NC, Gmax, RW, W32;
+  size_t off_edges_raw, off_ext_raw, off_keys, off_edges, off_ext, off_chunks, off_convex;
+  size_t off_gens, off_vis, off_sgen, off_sgcost, off_sgbb, off_inside, off_cost64, off_misc;
+  size_t total;
+};
+
+inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+inline Layout make_layout(int W, int H, int n_polys, int nv, int np, int ns) {
+  Layout L{};
+  L.W = W; L.H = H; L.nv = nv; L.np = np; L.ns = ns; L.np_polys = n_polys;
+  L.E = nv;
+  L.NC = (nv + kChunk - 1) / kChunk;
+  L.Gmax = np + ns + nv;
+  L.RW = (L.Gmax + 63) / 64;
+  L.W32 = (W + 31) / 32;
+  size_t o = 0;
+  auto take = [&](size_t bytes) { size_t r = o; o = align_up(o + (bytes ? bytes : 1), 256); return r; };
+  size_t E1 = (size_t)(L.E > 0 ? L.E : 1);
+  size_t G1 = (size_t)(L.Gmax > 0 ? L.Gmax : 1);
+  L.off_edges_raw = take(E1 * sizeof(EdgeRec));
+  L.off_ext_raw = take(E1 * sizeof(EdgeExt));
+  L.off_keys = take(E1 * sizeof(u64));
+  L.off_edges = take(E1 * sizeof(EdgeRec));
+  L.off_ext = take(E1 * sizeof(EdgeExt));
+  L.off_chunks = take((size_t)(L.NC > 0 ? L.NC : 1) * 16);
+  L.off_convex = take(E1 * sizeof(int));
+  L.off_gens = take(G1 * sizeof(GenRec));
+  L.off_vis = take(G1 * (size_t)(L.RW > 0 ? L.RW : 1) * sizeof(u64));
+  L.off_sgen = take(G1 * sizeof(GenRec));
+  L.off_sgcost = take(G1 * sizeof(float));
+  L.off_sgbb = take(G1 * 16);
+  L.off_inside = take((size_t)H * L.W32 * sizeof(unsigned));
+  L.off_cost64 = take(G1 * sizeof(double));
+  L.off_misc = take(MISC_N * sizeof(int));
+  L.total = o;
+  return L;
+}
+
+// Device view of one build's workspace and outputs.
+struct Dev {
+  int W, H, nv, np, ns, n_polys;
+  int E, NC, Gmax, RW, W32;
+  // inputs (device)
+  const int* poly_start;
+  const int* vx;
+  const int* vy;
+  const int* pts;
+  const int* segs;
+  // workspace
+  EdgeRec* edges_raw;
+  EdgeExt* ext_raw;
+  u64* keys;
+  EdgeRec* edges;
+  EdgeExt* ext;
+  int4* chunks;
+  int* convex;
+  GenRec* gens;
+  u64* vis;
+  GenRec* sgen;
+  float* sgcost;
+  int4* sgbb;
+  unsigned* inside;
+  double* cost64;
+  int* misc;
+  // outputs
+  float* dist;
+  int* parent;
+  int* gen_kind;
+  int* gen_xy;
+  double* gen_cost;
+  int* gen_parent;
+  int* n_gen;
+  // options
+  int tile_w, tile_h;
+  u64* stats;
+};
+
+// Read-only geometry view handed to the device helpers.  Kernels build it from
+// __restrict__ arguments so the compiler may serve uniform reads from the
+// scalar cache.
+struct Geo {
+  const EdgeRec* edges;
+  const EdgeExt* ext;
+  const int4* chunks;
+  int E, NC;
+};
+
+// host launchers (each queues kernels on the stream and returns hipError_t)
+hipError_t launch_ingest(const Dev& d, hipStream_t s);
+hipError_t launch_edge_sort(const Dev& d, hipStream_t s);
+hipError_t launch_inside(const Dev& d, hipStream_t s);
+hipError_t launch_genvis(const Dev& d, hipStream_t s);
+hipError_t launch_relax(const Dev& d, hipStream_t s);
+hipError_t launch_gsort(const Dev& d, hipStream_t s);
+hipError_t launch_pixel(const Dev& d, hipStream_t s);
+
+#ifdef __HIPCC__
+// ------------------------------------------------------------------------
+// device helpers
+// ------------------------------------------------------------------------
+__device__ __forceinline__ int lane_id() { return (int)__lane_id(); }
+__device__ __forceinline__ u64 ballot(bool p) { return (u64)__ballot(p); }
+__device__ __forceinline__ int first_bit(u64 m) { return __builtin_ctzll(m); }
+__device__ __forceinline__ int uni(int x) { return __builtin_amdgcn_readfirstlane(x); }
+__device__ __forceinline__ float unif(float x) {
+  return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(x)));
+}
+__device__ __forceinline__ int mul24(int a, int b) { return __mul24(a, b); }
+__device__ __forceinline__ int mad24(int a, int b, int c) { return __mul24(a, b) + c; }
+__device__ __forceinline__ int sgn3(int x) { return min(max(x, -1), 1); }
+
+__device__ __forceinline__ float wave_max(float v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = fmaxf(v, __shfl_xor(v, off, 64));
+  return v;
+}
+__device__ __forceinline__ int wave_min_i(int v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = min(v, __shfl_xor(v, off, 64));
+  return v;
+}
+__device__ __forceinline__ int wave_max_i(int v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = max(v, __shfl_xor(v, off, 64));
+  return v;
+}
+
+// Direction (dx, dy) leaving corner w strictly into the obstacle's interior
+// angle; u = previous and n = next vertex of w (counter-clockwise loop).
+__device__ __forceinline__ bool into_interior(int ux, int uy, int wx, int wy, int nx, int ny, int dx, int dy) {
+  int turn = (wx - ux) * (ny - wy) - (wy - uy) * (nx - wx);
+  int c1 = (wx - ux) * dy - (wy - uy) * dx;
+  int c2 = (nx - wx) * dy - (ny - wy) * dx;
+  return turn > 0 ? (c1 > 0 && c2 > 0) : (c1 > 0 || c2 > 0);
+}
+__device__ __forceinline__ bool into_interior64(int ux, int uy, int wx, int wy, int nx, int ny, long long dx,
+                                                long long dy) {
+  long long turn = (long long)(wx - ux) * (ny - wy) - (long long)(wy - uy) * (nx - wx);
+  long long c1 = (long long)(wx - ux) * dy - (long long)(wy - uy) * dx;
+  long long c2 = (long long)(nx - wx) * dy - (long long)(ny - wy) * dx;
+  return turn > 0 ? (c1 > 0 && c2 > 0) : (c1 > 0 || c2 > 0);
+}
+
+// Closest point of segment A-B to the integer point P (Section 4: endpoint or
+// projection), as a homogeneous point (qx/qw, qy/qw), qw > 0.
+struct RPt {
+  long long x, y, w;
+};
+__device__ __forceinline__ RPt seg_closest(int ax, int ay, int bx, int by, int px, int py, int* clamp) {
+  long long ex = bx - ax, ey = by - ay;
+  long long L = ex * ex + ey * ey;
+  long long num = (long long)(px - ax) * ex + (long long)(py - ay) * ey;
+  RPt q;
+  if (num <= 0) { q.x = ax; q.y = ay; q.w = 1; *clamp = 0; }
+  else if (num >= L) { q.x = bx; q.y = by; q.w = 1; *clamp = 1; }
+  else { q.x = (long long)ax * L + num * ex; q.y = (long long)ay * L + num * ey; q.w = L; *clamp = 2; }
+  return q;
+}
+
+// Per-lane visibility of the closed segment [P, Q] for an integer point P and
+// a rational point Q (used for segment sources, whose closest point varies per
+// lane).  Exact 64-bit predicates over every edge of the chunks whose bounding
+// box meets the box (cx0..cy1), which must contain P and Q.  P may be an
+// obstacle corner (pv = 1 with its neighbours), Q is free.
+__device__ __forceinline__ bool lane_visible_rational(const Geo& d, int px, int py, bool pv, int pux, int puy,
+                                                      int pnx, int pny, RPt q, bool need, int cx0, int cy0,
+                                                      int cx1, int cy1) {
+  bool blocked = false;
+  long long dqx = q.x - (long long)px * q.w, dqy = q.y - (long long)py * q.w;
+  if (dqx == 0 && dqy == 0) return true;
+  if (need && pv && into_interior64(pux, puy, px, py, pnx, pny, dqx, dqy)) blocked = true;
+  for (int cb = 0; cb < d.NC; cb += kWave) {
+    int ci = cb + lane_id();
+    bool hit = false;
+    if (ci < d.NC) {
+      int4 bb = d.chunks[ci];
+      hit = bb.x <= cx1 && bb.z >= cx0 && bb.y <= cy1 && bb.w >= cy0;
+    }
+    u64 cm = ballot(hit);
+    while (cm) {
+      int k = first_bit(cm);
+      cm &= cm - 1;
+      int e0 = (cb + k) * kChunk;
+      int e1 = min(e0 + kChunk, d.E);
+      if (ballot(need && !blocked) == 0) return false;
+      for (int e = e0; e < e1; ++e) {
+        EdgeRec r = d.edges[e];
+        if (need && !blocked) {
+          long long o1 = dqx * (r.wy - py) - dqy * (r.wx - px);
+          long long o2 = dqx * (r.vy - py) - dqy * (r.vx - px);
+          if ((o1 > 0 && o2 < 0) || (o1 < 0 && o2 > 0)) {
+            long long o3 = (long long)r.a * px + (long long)r.b * py + r.c;
+            long long o4 = (long long)r.a * q.x + (long long)r.b * q.y + (long long)r.c * q.w;
+            if ((o3 > 0 && o4 < 0) || (o3 < 0 && o4 > 0)) blocked = true;
+          }
+          if (o1 == 0 && !blocked) {
+            // w on the line PQ: strictly between P and Q?
+            long long tw, tl;
+            if (dqx != 0) { tw = (long long)(r.wx - px) * q.w; tl = dqx; }
+            else { tw = (long long)(r.wy - py) * q.w; tl = dqy; }
+            if (tl < 0) { tw = -tw; tl = -tl; }
+            if (tw > 0 && tw < tl) {
+              EdgeExt x = d.ext[e];
+              if (into_interior64(x.ux, x.uy, r.wx, r.wy, r.vx, r.vy, px - r.wx, py - r.wy) ||
+                  into_interior64(x.ux, x.uy, r.wx, r.wy, r.vx, r.vy, q.x - (long long)r.wx * q.w,
+                                  q.y - (long long)r.wy * q.w))
+                blocked = true;
+            }
+          }
+        }
+      }
+    }
+  }
+  return !blocked;
+}
+
+// Wave-level visibility between per-lane integer points P (lanes in `need`)
+// and one wave-uniform integer point g.  (bx0..by1) is a box containing every
+// needed P.  Returns the mask of needed lanes whose closed segment [P, g]
+// meets an obstacle's open interior.
+//
+//   * Only edges front-facing to g (g strictly outside the edge line) can be
+//     entered on the way from g to P; an entry at an edge interior is a proper
+//     crossing of such an edge with P strictly on its obstacle side, and an
+//     entry at a vertex happens at an endpoint of such an edge.
+//   * Lane-parallel culling: chunk boxes against the box of the cone (box + g),
+//     then edge relevance against the box: an edge whose endpoints stay
+//     strictly on one side of every line P-g, or whose obstacle side contains
+//     no point of the box, cannot block any lane.  An edge that properly
+//     crosses every such segment hides the whole box at once.
+//   * Per-lane test for relevant edges: endpoints strictly on opposite sides
+//     of line P-g and P strictly on the obstacle side (a proper crossing).  An
+//     endpoint exactly on line P-g flags the lane for the exact vertex rule.
+//   * g being a corner: the direction toward P must not enter g's own
+//     interior angle; P being a corner (pv): likewise toward g.
+template <bool STATS>
+__device__ __forceinline__ u64 wave_blocked_uniform(const Geo& d, int px, int py, u64 need, int gx, int gy, bool gvert,
+                                                    int gux, int guy, int gnx, int gny, bool pv, int pux, int puy,
+                                                    int pnx, int pny, int bx0, int by0, int bx1, int by1,
+                                                    u64* st) {
+  const int lane = lane_id();
+  const bool me = (need >> lane) & 1ull;
+  bool blk = false;
+  if (me && gvert && into_interior(gux, guy, gx, gy, gnx, gny, px - gx, py - gy)) blk = true;
+  if (me && pv && into_interior(pux, puy, px, py, pnx, pny, gx - px, gy - py)) blk = true;
+  u64 blocked = ballot(blk) & need;
+  if (blocked == need) return need;
+  // line through P and g: o(x) = A x + B y + C = cross(g - P, x - P)
+  const int A = py - gy, B = gx - px;
+  const int C = -(mul24(A, px) + mul24(B, py));
+  bool dg = false;
+  const int cx0 = min(bx0, gx), cy0 = min(by0, gy), cx1 = max(bx1, gx), cy1 = max(by1, gy);
+  const int rx0 = bx0 - gx, rx1 = bx1 - gx, ry0 = by0 - gy, ry1 = by1 - gy;
+  for (int cb = 0; cb < d.NC; cb += kWave) {
+    int ci = cb + lane;
+    bool hit = false;
+    if (ci < d.NC) {
+      int4 bb = d.chunks[ci];
+      hit = bb.x <= cx1 && bb.z >= cx0 && bb.y <= cy1 && bb.w >= cy0;
+    }
+    u64 cm = ballot(hit);
+    while (cm) {
+      const int chunk = cb + first_bit(cm);
+      cm &= cm - 1;
+      const int e = chunk * kChunk + lane;
+      bool rel = false, occ = false;
+      if (e < d.E) {
+        EdgeRec r = d.edges[e];
+        int Eg = mad24(r.a, gx, mad24(r.b, gy, r.c));
+        if (Eg < 0) {
+          int hiE = mad24(r.a, r.a > 0 ? bx1 : bx0, mad24(r.b, r.b > 0 ? by1 : by0, r.c));
+          int loE = mad24(r.a, r.a > 0 ? bx0 : bx1, mad24(r.b, r.b > 0 ? by0 : by1, r.c));
+          // f_w(P) = cross(w - g, P - g), affine in P; range over the box
+          int aw = gy - r.wy, bw = r.wx - gx;
+          int hiw = mul24(aw, aw > 0 ? rx1 : rx0) + mul24(bw, bw > 0 ? ry1 : ry0);
+          int low = mul24(aw, aw > 0 ? rx0 : rx1) + mul24(bw, bw > 0 ? ry0 : ry1);
+          int av = gy - r.vy, bv = r.vx - gx;
+          int hiv = mul24(av, av > 0 ? rx1 : rx0) + mul24(bv, bv > 0 ? ry1 : ry0);
+          int lov = mul24(av, av > 0 ? rx0 : rx1) + mul24(bv, bv > 0 ? ry0 : ry1);
+          bool same = (low > 0 && lov > 0) || (hiw < 0 && hiv < 0);
+          rel = hiE > 0 && !same;
+          occ = loE > 0 && ((low > 0 && hiv < 0) || (hiw < 0 && lov > 0));
+        }
+      }
+      if (STATS) st[4] += 1;
+      if (ballot(occ)) {
+        if (STATS) st[6] += 1;
+        return need;
+      }
+      u64 rm = ballot(rel);
+      while (rm) {
+        const int q = chunk * kChunk + first_bit(rm);
+        rm &= rm - 1;
+        const int wx = d.edges[q].wx, wy = d.edges[q].wy, vx = d.edges[q].vx, vy = d.edges[q].vy;
+        const int ea = d.edges[q].a, eb = d.edges[q].b, ec = d.edges[q].c;
+        if (STATS) st[5] += (u64)__popcll(need & ~blocked);
+        int ow = mad24(A, wx, mad24(B, wy, C));
+        int ov = mad24(A, vx, mad24(B, vy, C));
+        int prod = mul24(sgn3(ow), sgn3(ov));
+        int ep = mad24(ea, px, mul24(eb, py));
+        blk = blk || (prod < 0 && ep > -ec);
+        dg = dg || (prod == 0);
+      }
+      blocked = ballot(blk) & need;
+      if (blocked == need) return need;
+    }
+  }
+  // exact vertex rule for lanes with an endpoint exactly on their line P-g
+  u64 slow = ballot(dg) & need & ~blocked;
+  if (slow) {
+    const bool mine = (slow >> lane) & 1ull;
+    const int len2 = mul24(gx - px, gx - px) + mul24(gy - py, gy - py);
+    for (int cb = 0; cb < d.NC; cb += kWave) {
+      int ci = cb + lane;
+      bool hit = false;
+      if (ci < d.NC) {
+        int4 bb = d.chunks[ci];
+        hit = bb.x <= cx1 && bb.z >= cx0 && bb.y <= cy1 && bb.w >= cy0;
+      }
+      u64 cm = ballot(hit);
+      while (cm) {
+        const int chunk = cb + first_bit(cm);
+        cm &= cm - 1;
+        const int e0 = chunk * kChunk, e1 = min(e0 + kChunk, d.E);
+        for (int e = e0; e < e1; ++e) {
+          EdgeRec r = d.edges[e];
+          if (mine && !blk) {
+            int ow = mad24(A, r.wx, mad24(B, r.wy, C));
+            if (ow == 0) {
+              int dot = mul24(r.wx - px, gx - px) + mul24(r.wy - py, gy - py);
+              if (dot > 0 && dot < len2) {
+                EdgeExt x = d.ext[e];
+                if (into_interior(x.ux, x.uy, r.wx, r.wy, r.vx, r.vy, px - r.wx, py - r.wy) ||
+                    into_interior(x.ux, x.uy, r.wx, r.wy, r.vx, r.vy, gx - r.wx, gy - r.wy))
+                  blk = true;
+              }
+            }
+          }
+        }
+      }
+    }
+    blocked = ballot(blk) & need;
+  }
+  return blocked;
+}
+#endif  // __HIPCC__
+
+}  // namespace spm

@@ -1,0 +1,176 @@
+"""Python face of libspm: device scenes, builds, timers and path queries.
+
+PyTorch supplies device memory and streams; every step of a build runs in the
+library's HIP kernels (see include/spm.h for the contract of each call).
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+from . import _lib as C
+
+
+def _host_scene_struct(flat: dict, keep: list) -> C.SpmScene:
+    arrs = {k: np.ascontiguousarray(flat[k], np.int32) for k in ("poly_start", "vx", "vy", "pts", "segs")}
+    keep.append(arrs)
+
+    def p(a):
+        return a.ctypes.data if a.size else None
+
+    n_polys = len(arrs["poly_start"]) - 1
+    return C.SpmScene(int(flat["width"]), int(flat["height"]), n_polys, int(arrs["vx"].size),
+                      int(arrs["pts"].size // 2), int(arrs["segs"].size // 4), p(arrs["poly_start"]),
+                      p(arrs["vx"]), p(arrs["vy"]), p(arrs["pts"]), p(arrs["segs"]))
+
+
+def validate(scene) -> None:
+    """Exact host-side check of a scene (raises SpmError with the reason)."""
+    keep = []
+    s = _host_scene_struct(scene.flat(), keep)
+    C.check(C.lib().spm_validate(ctypes.byref(s)))
+
+
+def query_sizes(width, height, n_polys, n_vertices, n_points, n_segs):
+    s = C.SpmScene(width, height, n_polys, n_vertices, n_points, n_segs, None, None, None, None, None)
+    mg = C.c_i32(0)
+    ws = ctypes.c_size_t(0)
+    C.check(C.lib().spm_query_sizes(ctypes.byref(s), ctypes.byref(mg), ctypes.byref(ws)))
+    return int(mg.value), int(ws.value)
+
+
+class DeviceScene:
+    """A scene uploaded to device memory (int32 tensors) plus its C descriptor."""
+
+    def __init__(self, scene, device="cuda", check: bool = True):
+        if check:
+            validate(scene)
+        f = scene.flat()
+        self.width, self.height = int(f["width"]), int(f["height"])
+        self.scene = scene
+
+        def up(a):
+            a = np.ascontiguousarray(a, np.int32)
+            return torch.from_numpy(a if a.size else np.zeros(1, np.int32)).to(device)
+
+        self.t = {k: up(f[k]) for k in ("poly_start", "vx", "vy", "pts", "segs")}
+        self.n_polys = len(f["poly_start"]) - 1
+        self.n_vertices = int(f["vx"].size)
+        self.n_points = int(f["pts"].size // 2)
+        self.n_segs = int(f["segs"].size // 4)
+        self.c = C.SpmScene(self.width, self.height, self.n_polys, self.n_vertices, self.n_points, self.n_segs,
+                            self.t["poly_start"].data_ptr(), self.t["vx"].data_ptr(), self.t["vy"].data_ptr(),
+                            self.t["pts"].data_ptr(), self.t["segs"].data_ptr())
+
+    @property
+    def sizes(self):
+        return query_sizes(self.width, self.height, self.n_polys, self.n_vertices, self.n_points, self.n_segs)
+
+
+@dataclass
+class Map:
+    dist: torch.Tensor        # (H, W) float32
+    parent: torch.Tensor      # (H, W) int32
+    gen_kind: torch.Tensor    # (max_gen,) int32
+    gen_xy: torch.Tensor      # (max_gen, 4) int32
+    gen_cost: torch.Tensor    # (max_gen,) float64
+    gen_parent: torch.Tensor  # (max_gen,) int32
+    n_gen: torch.Tensor       # (1,) int32
+
+    def host(self) -> dict:
+        G = int(self.n_gen.item())
+        return {
+            "dist": self.dist.cpu().numpy(), "parent": self.parent.cpu().numpy(), "n_gen": G,
+            "gen_kind": self.gen_kind[:G].cpu().numpy(), "gen_xy": self.gen_xy[:G].cpu().numpy(),
+            "gen_cost": self.gen_cost[:G].cpu().numpy(), "gen_parent": self.gen_parent[:G].cpu().numpy(),
+        }
+
+
+class Timer:
+    """Per-stage HIP-event timing of builds (stage names in _lib.STAGES)."""
+
+    def __init__(self):
+        h = ctypes.c_void_p()
+        C.check(C.lib().spm_timer_create(ctypes.byref(h)))
+        self.h = h
+
+    def reset(self):
+        C.check(C.lib().spm_timer_reset(self.h))
+
+    def elapsed(self):
+        ms = (ctypes.c_float * C.SPM_N_STAGES)()
+        n = C.c_i32(0)
+        C.check(C.lib().spm_timer_elapsed(self.h, ms, ctypes.byref(n)))
+        return {name: float(ms[k]) for k, name in enumerate(C.STAGES)}, int(n.value)
+
+    def __del__(self):
+        try:
+            C.lib().spm_timer_destroy(self.h)
+        except Exception:
+            pass
+
+
+class Builder:
+    """Owns the outputs and workspace of one scene's builds."""
+
+    def __init__(self, dscene: DeviceScene, tile=(8, 8)):
+        self.ds = dscene
+        dev = dscene.t["vx"].device
+        self.max_gen, self.ws_bytes = dscene.sizes
+        H, W = dscene.height, dscene.width
+        G = max(self.max_gen, 1)
+        self.map = Map(
+            dist=torch.empty((H, W), dtype=torch.float32, device=dev),
+            parent=torch.empty((H, W), dtype=torch.int32, device=dev),
+            gen_kind=torch.empty((G,), dtype=torch.int32, device=dev),
+            gen_xy=torch.empty((G, 4), dtype=torch.int32, device=dev),
+            gen_cost=torch.empty((G,), dtype=torch.float64, device=dev),
+            gen_parent=torch.empty((G,), dtype=torch.int32, device=dev),
+            n_gen=torch.empty((1,), dtype=torch.int32, device=dev),
+        )
+        self.ws = torch.empty((self.ws_bytes,), dtype=torch.uint8, device=dev)
+        m = self.map
+        self.out = C.SpmOut(m.dist.data_ptr(), m.parent.data_ptr(), m.gen_kind.data_ptr(), m.gen_xy.data_ptr(),
+                            m.gen_cost.data_ptr(), m.gen_parent.data_ptr(), m.n_gen.data_ptr())
+        self.tile = tuple(tile)
+
+    def build(self, stream=None, timer: Timer = None, stats: torch.Tensor = None) -> Map:
+        """Queue one build on `stream` (default: torch's current stream)."""
+        if stream is None:
+            stream = torch.cuda.current_stream(self.ws.device)
+        opts = C.SpmBuildOpts(self.tile[0], self.tile[1], timer.h if timer is not None else None,
+                              stats.data_ptr() if stats is not None else None)
+        C.check(C.lib().spm_build_ex(ctypes.byref(self.ds.c), ctypes.byref(self.out), self.ws.data_ptr(),
+                                     self.ws_bytes, ctypes.c_void_p(stream.cuda_stream), ctypes.byref(opts)))
+        return self.map
+
+
+def build(scene, device="cuda", tile=(8, 8)) -> Map:
+    """Upload, build and return the map (device tensors; the build is queued on the current stream)."""
+    b = Builder(DeviceScene(scene, device), tile=tile)
+    return b.build()
+
+
+def query_path(host_map: dict, qx: float, qy: float, cap: int = 4096):
+    """Path from (qx, qy) to its closest source from a host copy of a map (Map.host()).
+    Returns (points (n, 2) float32, length)."""
+    keep = {k: np.ascontiguousarray(host_map[k]) for k in ("parent", "gen_kind", "gen_xy", "gen_parent",
+                                                           "gen_cost")}
+    keep["parent"] = keep["parent"].astype(np.int32, copy=False)
+    keep["gen_kind"] = keep["gen_kind"].astype(np.int32, copy=False)
+    keep["gen_xy"] = keep["gen_xy"].astype(np.int32, copy=False)
+    keep["gen_parent"] = keep["gen_parent"].astype(np.int32, copy=False)
+    keep["gen_cost"] = keep["gen_cost"].astype(np.float64, copy=False)
+    H, W = keep["parent"].shape
+    m = C.SpmMapHost(W, H, keep["parent"].ctypes.data, int(host_map["n_gen"]), keep["gen_kind"].ctypes.data,
+                     keep["gen_xy"].ctypes.data, keep["gen_parent"].ctypes.data, keep["gen_cost"].ctypes.data)
+    out = np.zeros(2 * cap, np.float32)
+    n = C.c_i32(0)
+    L = ctypes.c_float(0)
+    C.check(C.lib().spm_query_path(ctypes.byref(m), float(qx), float(qy),
+                                   out.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), cap, ctypes.byref(n),
+                                   ctypes.byref(L)))
+    return out[:2 * n.value].reshape(-1, 2), float(L.value)

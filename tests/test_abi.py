@@ -1,0 +1,168 @@
+"""CPU-only checks of the C ABI: symbols, host validation errors, sizes, path queries.
+
+Nothing here launches device work: every call either is host-only
+(spm_validate, spm_query_sizes, spm_query_path, spm_last_error) or fails its
+argument checks before any HIP call.
+"""
+import ctypes
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+from scenegen import Scene, config1, config2, random_small
+from scenegen.scenes import _rect_poly
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def C():
+    from paper_1805_08500_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        from paper_1805_08500_amd import build
+        build.build()
+    _lib.lib()
+    return _lib
+
+
+def _declared_functions():
+    src = open(os.path.join(ROOT, "include", "spm.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(spm_[a-z_]+)\s*\(", src)))
+
+
+def test_exports_every_declared_symbol(C):
+    names = _declared_functions()
+    assert len(names) >= 10
+    L = ctypes.CDLL(C.LIB_PATH)
+    for n in names:
+        assert hasattr(L, n), n
+
+
+def test_validate_accepts_generated_scenes(C):
+    from paper_1805_08500_amd import validate
+    validate(config1(1))
+    validate(config2(1))
+    for s in range(12):
+        validate(random_small(s))
+
+
+def _code(scene):
+    from paper_1805_08500_amd import validate
+    from paper_1805_08500_amd._lib import SpmError
+    try:
+        validate(scene)
+    except SpmError as e:
+        return e.code
+    return 0
+
+
+def test_validate_error_codes(C):
+    ok = Scene(40, 40, [_rect_poly(10, 10, 20, 20)], np.asarray([[2, 2]]), None)
+    assert _code(ok) == 0
+    cw = Scene(40, 40, [_rect_poly(10, 10, 20, 20)[::-1]], np.asarray([[2, 2]]), None)
+    assert _code(cw) == C.SPM_ERR_GEOMETRY
+    overlap = Scene(40, 40, [_rect_poly(10, 10, 20, 20), _rect_poly(20, 12, 30, 18)], np.asarray([[2, 2]]), None)
+    assert _code(overlap) == C.SPM_ERR_GEOMETRY              # touching counts as meeting
+    nested = Scene(40, 40, [_rect_poly(5, 5, 35, 35), _rect_poly(10, 10, 20, 20)], np.asarray([[2, 2]]), None)
+    assert _code(nested) == C.SPM_ERR_GEOMETRY
+    bowtie = Scene(40, 40, [np.asarray([(10, 10), (20, 20), (20, 10), (10, 20)])], np.asarray([[2, 2]]), None)
+    assert _code(bowtie) == C.SPM_ERR_GEOMETRY
+    collinear = Scene(40, 40, [np.asarray([(10, 10), (15, 10), (20, 10), (20, 20), (10, 20)])], np.asarray([[2, 2]]),
+                      None)
+    assert _code(collinear) == C.SPM_ERR_GEOMETRY
+    src_in = Scene(40, 40, [_rect_poly(10, 10, 20, 20)], np.asarray([[15, 15]]), None)
+    assert _code(src_in) == C.SPM_ERR_GEOMETRY
+    src_on = Scene(40, 40, [_rect_poly(10, 10, 20, 20)], np.asarray([[10, 15]]), None)
+    assert _code(src_on) == C.SPM_ERR_GEOMETRY
+    seg_hit = Scene(40, 40, [_rect_poly(10, 10, 20, 20)], None, np.asarray([[0, 15, 30, 15]]))
+    assert _code(seg_hit) == C.SPM_ERR_GEOMETRY
+    seg_zero = Scene(40, 40, [], None, np.asarray([[3, 3, 3, 3]]))
+    assert _code(seg_zero) == C.SPM_ERR_GEOMETRY
+    out_of_range = Scene(40, 40, [_rect_poly(10, 10, 50, 20)], np.asarray([[2, 2]]), None)
+    assert _code(out_of_range) == C.SPM_ERR_RANGE
+    too_big = Scene(9000, 10, [], np.asarray([[2, 2]]), None)
+    assert _code(too_big) == C.SPM_ERR_RANGE
+    no_source = Scene(40, 40, [_rect_poly(10, 10, 20, 20)], None, None)
+    assert _code(no_source) == C.SPM_ERR_INVALID_ARG
+
+
+def test_query_sizes_and_bad_counts(C):
+    from paper_1805_08500_amd import query_sizes
+    from paper_1805_08500_amd._lib import SpmError
+    mg, ws = query_sizes(1024, 1024, 60, 336, 3, 2)
+    assert mg == 341 and ws > 0
+    mg2, ws2 = query_sizes(2048, 2048, 60, 336, 3, 2)
+    assert ws2 > ws
+    with pytest.raises(SpmError) as e:
+        query_sizes(0, 10, 0, 0, 1, 0)
+    assert e.value.code == C.SPM_ERR_RANGE
+    with pytest.raises(SpmError) as e:
+        query_sizes(10, 10, 1, 2, 1, 0)
+    assert e.value.code == C.SPM_ERR_INVALID_ARG
+
+
+def test_build_rejects_null_arguments_before_device_work(C):
+    L = C.lib()
+    s = C.SpmScene(10, 10, 0, 0, 1, 0, None, None, None, None, None)
+    out = C.SpmOut()
+    rc = L.spm_build(ctypes.byref(s), ctypes.byref(out), None, 0, None)
+    assert rc == C.SPM_ERR_INVALID_ARG          # pts NULL with one point
+    assert b"NULL" in L.spm_last_error()
+    pts = (ctypes.c_int32 * 2)(1, 1)
+    s.pts = ctypes.cast(pts, ctypes.c_void_p)
+    rc = L.spm_build(ctypes.byref(s), ctypes.byref(out), None, 0, None)
+    assert rc == C.SPM_ERR_INVALID_ARG          # outputs NULL
+    rc = L.spm_build(None, ctypes.byref(out), None, 0, None)
+    assert rc == C.SPM_ERR_INVALID_ARG
+
+
+def _oracle_host_map(O, scene):
+    m = O.full_map(scene)
+    kind, ref, xy = O.generators(scene)
+    return m, {"parent": m["parent"], "n_gen": len(kind), "gen_kind": kind, "gen_xy": xy,
+               "gen_parent": m["gparent"], "gen_cost": m["cost"]}
+
+
+def test_query_path_chain_invariants(oracle_mod, C):
+    from paper_1805_08500_amd import query_path
+    from paper_1805_08500_amd._lib import SpmError
+    scene = random_small(4)
+    m, hm = _oracle_host_map(oracle_mod, scene)
+    H, W = m["dist"].shape
+    checked = 0
+    for j in range(0, H, 3):
+        for i in range(0, W, 3):
+            if not np.isfinite(m["dist64"][j, i]):
+                with pytest.raises(SpmError) as e:
+                    query_path(hm, i + 0.5, j + 0.5)
+                assert e.value.code == C.SPM_ERR_UNREACHABLE
+                continue
+            pts, L = query_path(hm, i + 0.5, j + 0.5)
+            assert abs(L - m["dist64"][j, i]) <= 1e-4 * max(1.0, m["dist64"][j, i])
+            # every leg is visible
+            for a, b in zip(pts[:-1], pts[1:]):
+                ha = (int(round(2 * a[0] * 1024)), int(round(2 * a[1] * 1024)), 1024)
+                hb = (int(round(2 * b[0] * 1024)), int(round(2 * b[1] * 1024)), 1024)
+                if np.all(np.abs(np.asarray(a) * 1024 - np.round(np.asarray(a) * 1024)) < 1e-3) and \
+                        np.all(np.abs(np.asarray(b) * 1024 - np.round(np.asarray(b) * 1024)) < 1e-3):
+                    assert oracle_mod.visible(scene, ha, hb)
+            checked += 1
+    assert checked > 20
+
+
+def test_query_path_errors(oracle_mod, C):
+    from paper_1805_08500_amd import query_path
+    from paper_1805_08500_amd._lib import SpmError
+    scene = config1(1)
+    m, hm = _oracle_host_map(oracle_mod, scene)
+    with pytest.raises(SpmError) as e:
+        query_path(hm, -1.0, 3.0)
+    assert e.value.code == C.SPM_ERR_RANGE
+    j, i = np.argwhere(np.isfinite(m["dist64"]))[0]
+    with pytest.raises(SpmError) as e:
+        query_path(hm, i + 0.5, j + 0.5, cap=1)
+    assert e.value.code == C.SPM_ERR_CAPACITY

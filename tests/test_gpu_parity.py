@@ -1,0 +1,131 @@
+"""GPU parity: libspm (through its C ABI) against the CPU oracle, element by element."""
+import sys
+
+import numpy as np
+import pytest
+
+from scenegen import Scene, config1, config2, config3, random_small
+from scenegen.scenes import _rect_poly
+from tests.spm_compare import compare, compare_generators
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def spm():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1805_08500_amd as m
+    return m
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _gpu(spm, scene, tile=(8, 8)):
+    import torch
+    b = spm.Builder(spm.DeviceScene(scene), tile=tile)
+    b.build()
+    torch.cuda.synchronize()
+    return b.map.host()
+
+
+def _full(O, spm, scene, label, tile=(8, 8)):
+    _say(f"[parity] {label} {scene.width}x{scene.height} V={scene.n_vertices} tile={tile}")
+    h = _gpu(spm, scene, tile)
+    ref = O.full_map(scene)
+    st = compare(h["dist"], h["parent"], ref, label)
+    same = compare_generators(h, ref["cost"], ref["gparent"], label)
+    assert same == 1.0, f"{label}: generator parents differ ({same})"
+    _say(f"[parity] {label} ok ambiguous={st['ambiguous_frac']:.2e} max_rel={st['max_rel']:.2e}")
+    return h, ref
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_config1_full(oracle_mod, spm, seed):
+    _full(oracle_mod, spm, config1(seed), f"rect256-s{seed}")
+
+
+@pytest.mark.parametrize("seed", range(0, 48))
+def test_fuzz_small_full(oracle_mod, spm, seed):
+    _full(oracle_mod, spm, random_small(seed), f"fuzz-{seed}")
+
+
+def test_config2_full_seed1(oracle_mod, spm):
+    _full(oracle_mod, spm, config2(1), "convex1024-s1")
+
+
+@pytest.mark.parametrize("seed", [2, 3])
+def test_config2_sampled(oracle_mod, spm, seed):
+    scene = config2(seed)
+    _say(f"[parity] convex1024-s{seed} sampled")
+    h = _gpu(spm, scene)
+    cost, gpar = oracle_mod.costs(scene)
+    compare_generators(h, cost, gpar, f"convex1024-s{seed}")
+    rng = np.random.default_rng(seed)
+    pix = np.unique(rng.integers(0, scene.width * scene.height, 60000))
+    r = oracle_mod.pixels(scene, cost, pix)
+    d = h["dist"].reshape(-1)[pix]
+    p = h["parent"].reshape(-1)[pix]
+    st = compare(d, p, r, f"convex1024-s{seed}")
+    _say(f"[parity] convex1024-s{seed} ok ambiguous={st['ambiguous_frac']:.2e}")
+
+
+def test_config3_maze_sampled(oracle_mod, spm):
+    scene = config3(1)
+    _say("[parity] maze2048-s1 sampled")
+    h = _gpu(spm, scene)
+    cost, gpar = oracle_mod.costs(scene)
+    same = compare_generators(h, cost, gpar, "maze")
+    rng = np.random.default_rng(5)
+    pix = np.unique(rng.integers(0, scene.width * scene.height, 3000))
+    r = oracle_mod.pixels(scene, cost, pix)
+    st = compare(h["dist"].reshape(-1)[pix], h["parent"].reshape(-1)[pix], r, "maze")
+    _say(f"[parity] maze ok gparent_same={same:.4f} ambiguous={st['ambiguous_frac']:.2e}")
+
+
+@pytest.mark.parametrize("tile", [(16, 4), (4, 16)])
+def test_tile_shapes_bitwise(spm, tile):
+    scene = config2(1)
+    a = _gpu(spm, scene, (8, 8))
+    b = _gpu(spm, scene, tile)
+    assert np.array_equal(a["dist"], b["dist"]) and np.array_equal(a["parent"], b["parent"])
+
+
+def test_deterministic(spm):
+    scene = config2(2)
+    a = _gpu(spm, scene)
+    b = _gpu(spm, scene)
+    for k in ("dist", "parent", "gen_cost", "gen_parent"):
+        assert np.array_equal(a[k], b[k]), k
+
+
+def test_edge_cases(oracle_mod, spm):
+    cases = [
+        ("free-point", Scene(37, 23, [], np.asarray([[5, 9]]), None)),
+        ("free-segment", Scene(29, 31, [], None, np.asarray([[3, 3, 27, 20]]))),
+        ("one-pixel", Scene(1, 1, [], np.asarray([[0, 0]]), None)),
+        ("thin-strip", Scene(200, 3, [_rect_poly(50, 1, 60, 2)], np.asarray([[0, 0]]), None)),
+        ("walled-off", Scene(40, 40, [np.asarray([(10, 0), (12, 0), (12, 40), (10, 40)])],
+                              np.asarray([[2, 20]]), None)),
+        ("pixel-on-segment", Scene(20, 20, [_rect_poly(12, 12, 16, 16)], None, np.asarray([[0, 0, 10, 10]]))),
+        ("diagonal-edge", Scene(24, 24, [np.asarray([(4, 4), (14, 4), (14, 14)])], np.asarray([[20, 2]]), None)),
+    ]
+    for name, sc in cases:
+        _full(oracle_mod, spm, sc, name)
+
+
+def test_max_side_sampled(oracle_mod, spm):
+    scene = Scene(8192, 8192, [_rect_poly(4000, 100, 4100, 8100), _rect_poly(1000, 3000, 3900, 3050)],
+                  np.asarray([[10, 10]]), np.asarray([[8000, 8000, 8190, 7000]]))
+    _say("[parity] max-side 8192 sampled")
+    h = _gpu(spm, scene)
+    cost, gpar = oracle_mod.costs(scene)
+    compare_generators(h, cost, gpar, "max-side")
+    rng = np.random.default_rng(1)
+    pix = np.unique(rng.integers(0, 8192 * 8192, 20000))
+    r = oracle_mod.pixels(scene, cost, pix)
+    compare(h["dist"].reshape(-1)[pix], h["parent"].reshape(-1)[pix], r, "max-side")
