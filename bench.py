@@ -1,0 +1,169 @@
+"""Benchmark: shortest-path-map builds on one MI355X.
+
+One step = one complete spm_build (device ingest, generator visibility,
+relaxation, cost sort, inside mask and pixel propagation) of the 1024 x 1024
+scene with 60 convex obstacles, 3 point sources and 2 segment sources, with
+the scene already resident in device memory.
+
+value = W * H * G / t_step / 1e6  (Mpixel*generator/s; G = point sources +
+segment sources + corner generators, the dense pair count the paper's method
+shades).
+
+Prints one JSON line.  See the design doc for the roofline definition.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "SPM build Mpixel·gen/s + % VALU roofline; batched & backward vs plain"
+PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9      # CUs x SIMDs x lanes x clock: one 32-bit VALU op per lane per cycle
+# arithmetic lane-ops per counted unit of the instrumented pixel kernel
+OPS = {
+    "tile_bound": 12,    # per generator per tile: box gap (4 sub/max), squares, sqrt, scale, add, compare
+    "lane_bound": 9,     # per (pixel, generator): 2 sub, mul+mad, sub, cvt, 2 mul, compare
+    "relevance": 30,     # per (tile, edge): facing test, box ranges of 3 affine forms, compares
+    "lane_edge": 12,     # per (pixel, generator, edge): 4 mad (two orientations), 2 med3, mul, 2 mad, 3 compares
+    "accept": 4,         # per accepted candidate: cvt, sqrt, mad, compare
+}
+
+
+def _parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--seed", type=int, default=1)
+    ap.add_argument("--tile", default="8x8")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-pixels", type=int, default=400000, help="oracle pixel sample for the CPU baseline")
+    return ap.parse_args()
+
+
+def _file_hash(path):
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def _traffic(kernel_src_hash):
+    """HBM bytes per k_pixel launch from the committed rocprofv3 counter summary, if the
+    kernel source has not changed since the counters were taken."""
+    p = os.path.join(ROOT, "profiles", "k_pixel_convex1024_traffic.json")
+    if not os.path.exists(p):
+        return None
+    with open(p) as f:
+        t = json.load(f)
+    if t.get("source_hash") != kernel_src_hash:
+        return None
+    return t.get("bytes_per_launch")
+
+
+def _cpu_baseline(scene, G, npix):
+    import numpy as np
+    from oracle import oracle as O
+    O.build()
+    threads = O.max_threads()
+    t0 = time.perf_counter()
+    cost, _ = O.costs(scene, nthreads=threads)
+    t1 = time.perf_counter()
+    rng = np.random.default_rng(123)
+    pix = np.unique(rng.integers(0, scene.width * scene.height, npix))
+    t2 = time.perf_counter()
+    O.pixels(scene, cost, pix, nthreads=threads)
+    t3 = time.perf_counter()
+    WH = scene.width * scene.height
+    t_full = (t1 - t0) + (t3 - t2) * WH / len(pix)
+    return {
+        "value": WH * G / t_full / 1e6, "unit": "Mpixel·gen/s", "cores": int(threads), "kind": "oracle",
+        "sample": (f"generator costs in full ({t1 - t0:.2f} s) + {len(pix)} random pixels ({t3 - t2:.2f} s) "
+                   f"of the same scene, extrapolated to all {WH} pixels"),
+    }
+
+
+def main():
+    args = _parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; multi-GPU runs are not part of it",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import paper_1805_08500_amd as spm
+    from scenegen import config2
+
+    tw, th = (int(x) for x in args.tile.split("x"))
+    scene = config2(args.seed)
+    ds = spm.DeviceScene(scene, "cuda:0")
+    b = spm.Builder(ds, tile=(tw, th))
+    stream = torch.cuda.current_stream()
+    for _ in range(args.warmup):
+        b.build(stream)
+    torch.cuda.synchronize()
+    G = int(b.map.n_gen.item())
+    W, H = scene.width, scene.height
+
+    # timed region: exactly K whole builds
+    timer = spm.Timer()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        b.build(stream, timer=timer)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    stages, nb = timer.elapsed()
+    ms_step = (t1 - t0) * 1e3 / args.steps
+    stage_avg = {k: v / max(nb, 1) for k, v in stages.items()}
+
+    # one instrumented build (outside the timed region) for the work counts
+    stats = torch.zeros(8, dtype=torch.int64, device="cuda:0")
+    b.build(stream, stats=stats)
+    torch.cuda.synchronize()
+    s = stats.cpu().numpy().astype(np.float64)
+    ops = (s[1] * 64 * OPS["tile_bound"] + s[2] * OPS["lane_bound"] + s[4] * 64 * OPS["relevance"]
+           + s[5] * OPS["lane_edge"] + s[7] * OPS["accept"])
+    t_pix = stage_avg["pixel"] * 1e-3
+    achieved = ops / t_pix / 1e12
+    peak = PEAK_LANE_OPS / 1e12
+    src_hash = _file_hash(os.path.join(ROOT, "paper_1805_08500_amd", "csrc", "k_pixel.hip"))
+
+    pairs = W * H * G
+    out = {
+        "metric": METRIC,
+        "value": pairs / (ms_step * 1e-3) / 1e6,
+        "unit": "Mpixel·gen/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "convex-1024: 1024x1024 grid, 60 convex hulls (6-10 seeded points in 20-80 px "
+                               "boxes), 3 point sources, 2 segment sources, seed %d" % args.seed,
+                   "W": W, "H": H, "G": G, "E": scene.n_vertices, "tile": args.tile},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TOP/s",
+                     "frac": achieved / peak, "traffic": _traffic(src_hash), "kernel": "k_pixel",
+                     "ops_per_launch": ops},
+        "stages_ms": stage_avg,
+        "k_pixel_Mpixel_gen_per_s": pairs / t_pix / 1e6,
+        "work_counts": {k: int(v) for k, v in zip(
+            ["tiles", "gen_batches", "lane_bound", "wave_vis", "relevance", "lane_edge", "occluded", "accept"], s)},
+        "k_pixel_source_hash": src_hash,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = _cpu_baseline(scene, G, args.cpu_pixels)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

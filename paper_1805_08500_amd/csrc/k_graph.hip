@@ -189,11 +189,12 @@ __global__ __launch_bounds__(1024) void k_relax(int Gmax, int RW, const GenRec* 
 
 // One wavefront per generator: rank by (float cost, id) among all generators;
 // unreached ones (+inf) rank last and are not copied.
-__global__ __launch_bounds__(256) void k_gsort(const int* __restrict__ misc, const GenRec* __restrict__ gens,
+__global__ __launch_bounds__(256) void k_gsort(int* misc, const GenRec* __restrict__ gens,
                                                const double* __restrict__ cost64, GenRec* __restrict__ sgen,
                                                float* __restrict__ sgcost, int4* __restrict__ sgbb) {
   const int g = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
   const int G = uni(misc[MISC_G]);
+  if (g == 0 && threadIdx.x == 0) misc[MISC_TILE_CTR] = 0;  // tile queue of the pixel stage
   if (g >= G) return;
   const int lane = lane_id();
   const float cf = (float)cost64[g];

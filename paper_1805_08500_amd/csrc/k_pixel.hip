@@ -49,21 +49,17 @@ __device__ __forceinline__ void mask_box(u64 m, int i0, int j0, int& bx0, int& b
   by1 = 2 * (j0 + r1) + 1;
 }
 
+// One tile: the per-lane minimum over generators for 64 pixels.  The
+// generator tables and the edges come through plain pointers that point
+// either into LDS (staged by the kernel) or into global memory.
 template <int TW, bool STATS>
-__global__ __launch_bounds__(256) void k_pixel(int W, int H, int W32, const int* __restrict__ misc,
-                                               const unsigned* __restrict__ inside,
-                                               const GenRec* __restrict__ sgen, const float* __restrict__ sgcost,
-                                               const int4* __restrict__ sgbb, const EdgeRec* __restrict__ edges,
-                                               const EdgeExt* __restrict__ ext, const int4* __restrict__ chunks,
-                                               int E, int NC, float* __restrict__ dist, int* __restrict__ parent,
-                                               u64* __restrict__ stats) {
+__device__ __forceinline__ void tile_work(int tile, int W, int H, int W32, int G, const unsigned* __restrict__ inside,
+                                          const GenRec* sgen, const float* sgcost, const int4* sgbb, const Geo& geo,
+                                          float* __restrict__ dist, int* __restrict__ parent, u64* st) {
   constexpr int TH = 64 / TW;
   const int lane = lane_id();
-  const int wid = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-  const int ntx = (W + TW - 1) / TW, nty = (H + TH - 1) / TH;
-  if (wid >= ntx * nty) return;
-  const Geo geo{edges, ext, chunks, E, NC};
-  const int ty = wid / ntx, tx = wid - ty * ntx;
+  const int ntx = (W + TW - 1) / TW;
+  const int ty = tile / ntx, tx = tile - ty * ntx;
   const int i0 = tx * TW, j0 = ty * TH;
   const int i = i0 + (lane % TW), j = j0 + (lane / TW);
   const bool valid = i < W && j < H;
@@ -71,13 +67,11 @@ __global__ __launch_bounds__(256) void k_pixel(int W, int H, int W32, const int*
   bool ins = false;
   if (valid) ins = (inside[(size_t)j * W32 + (i >> 5)] >> (i & 31)) & 1u;
   const bool active = valid && !ins;
-  u64 st[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   if (STATS) st[ST_TILES] += 1;
   float best = INFINITY;
   int par = -1;
   const u64 act = ballot(active);
   if (act) {
-    const int G = uni(misc[MISC_REACHED]);
     int tbx0, tby0, tbx1, tby1;
     mask_box<TW>(act, i0, j0, tbx0, tby0, tbx1, tby1);
     float UB = INFINITY;
@@ -128,6 +122,7 @@ __global__ __launch_bounds__(256) void k_pixel(int W, int H, int W32, const int*
           const int ax = gx, ay = gy, bx = sgen[k].x2, by = sgen[k].y2;
           int clamp;
           const RPt q = seg_closest(ax, ay, bx, by, px, py, &clamp);
+          (void)q;
           float dd;
           if (clamp == 0) {
             dd = 0.5f * sqrtf((float)(mad24(px - ax, px - ax, mul24(py - ay, py - ay))));
@@ -143,13 +138,29 @@ __global__ __launch_bounds__(256) void k_pixel(int W, int H, int W32, const int*
           const u64 nm = ballot(need);
           if (STATS) st[ST_BOUND] += __popcll(act);
           if (!nm) continue;
-          if (STATS) st[ST_VISWAVE] += 1;
+          // lanes whose closest point is endpoint A, endpoint B, or interior
+          u64 bl = 0;
+          const u64 mA = ballot(need && clamp == 0), mB = ballot(need && clamp == 1);
+          const u64 mI = nm & ~mA & ~mB;
           int bx0, by0, bx1, by1;
-          mask_box<TW>(nm, i0, j0, bx0, by0, bx1, by1);
-          const bool vs = lane_visible_rational(geo, px, py, false, 0, 0, 0, 0, q, need, min(bx0, min(ax, bx)),
-                                                min(by0, min(ay, by)), max(bx1, max(ax, bx)),
-                                                max(by1, max(ay, by)));
-          if (need && vs) { best = c; par = sgen[k].id; upd = true; }
+          if (mA) {
+            if (STATS) st[ST_VISWAVE] += 1;
+            mask_box<TW>(mA, i0, j0, bx0, by0, bx1, by1);
+            bl |= wave_blocked_uniform<STATS>(geo, px, py, mA, ax, ay, false, 0, 0, 0, 0, false, 0, 0, 0, 0, bx0,
+                                              by0, bx1, by1, st);
+          }
+          if (mB) {
+            if (STATS) st[ST_VISWAVE] += 1;
+            mask_box<TW>(mB, i0, j0, bx0, by0, bx1, by1);
+            bl |= wave_blocked_uniform<STATS>(geo, px, py, mB, bx, by, false, 0, 0, 0, 0, false, 0, 0, 0, 0, bx0,
+                                              by0, bx1, by1, st);
+          }
+          if (mI) {
+            if (STATS) st[ST_VISWAVE] += 1;
+            mask_box<TW>(mI, i0, j0, bx0, by0, bx1, by1);
+            bl |= wave_blocked_perp<STATS>(geo, px, py, mI, ax, ay, bx, by, bx0, by0, bx1, by1, st);
+          }
+          if (need && !((bl >> lane) & 1ull)) { best = c; par = sgen[k].id; upd = true; }
         }
         if (ballot(upd)) {
           if (STATS) st[ST_ACCEPT] += __popcll(ballot(upd));
@@ -163,30 +174,116 @@ __global__ __launch_bounds__(256) void k_pixel(int W, int H, int W32, const int*
     dist[o] = best;
     parent[o] = par;
   }
-  if (STATS && lane == 0) {
+}
+
+constexpr int kPixelThreads = 512;
+constexpr size_t kPixelLdsMax = 64 * 1024;
+
+inline size_t pixel_lds_bytes(int Gmax, int E, int NC) {
+  return (size_t)Gmax * (sizeof(GenRec) + 4 + 16) + 16 + (size_t)E * sizeof(EdgeRec) + (size_t)NC * 16;
+}
+
+// Persistent kernel: every wavefront takes tiles from a device queue
+// (misc[MISC_TILE_CTR], reset by the generator sort) until none is left.
+// LDSD: the cost-sorted generator table, the edges and the chunk boxes are
+// first staged in LDS, so the wave-uniform reads of the hot loops are LDS
+// broadcasts instead of L2 round trips.
+template <int TW, bool STATS, bool LDSD>
+__global__ __launch_bounds__(kPixelThreads) void k_pixel(int W, int H, int W32, int Gmax, int* misc,
+                                                         const unsigned* __restrict__ inside,
+                                                         const GenRec* __restrict__ sgen_g,
+                                                         const float* __restrict__ sgcost_g,
+                                                         const int4* __restrict__ sgbb_g,
+                                                         const EdgeRec* __restrict__ edges_g,
+                                                         const EdgeExt* __restrict__ ext,
+                                                         const int4* __restrict__ chunks_g, int E, int NC,
+                                                         float* __restrict__ dist, int* __restrict__ parent,
+                                                         u64* __restrict__ stats) {
+  constexpr int TH = 64 / TW;
+  extern __shared__ int4 smem[];
+  const int G = misc[MISC_REACHED];
+  const GenRec* sgen = sgen_g;
+  const float* sgcost = sgcost_g;
+  const int4* sgbb = sgbb_g;
+  Geo geo{edges_g, ext, chunks_g, E, NC};
+  if (LDSD) {
+    GenRec* s_gen = (GenRec*)smem;
+    int4* s_bb = (int4*)(s_gen + Gmax);
+    EdgeRec* s_edges = (EdgeRec*)(s_bb + Gmax);
+    int4* s_chunks = (int4*)(s_edges + E);
+    float* s_cost = (float*)(s_chunks + NC);
+    const int t = threadIdx.x, nt = blockDim.x;
+    const int4* src = (const int4*)sgen_g;
+    for (int k = t; k < G * 4; k += nt) ((int4*)s_gen)[k] = src[k];
+    for (int k = t; k < G; k += nt) { s_bb[k] = sgbb_g[k]; s_cost[k] = sgcost_g[k]; }
+    const int4* se = (const int4*)edges_g;
+    for (int k = t; k < E * 2; k += nt) ((int4*)s_edges)[k] = se[k];
+    for (int k = t; k < NC; k += nt) s_chunks[k] = chunks_g[k];
+    __syncthreads();
+    sgen = s_gen;
+    sgcost = s_cost;
+    sgbb = s_bb;
+    geo.edges = s_edges;
+    geo.chunks = s_chunks;
+  }
+  const int ntiles = ((W + TW - 1) / TW) * ((H + TH - 1) / TH);
+  u64 st[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  for (;;) {
+    int tile = 0;
+    if (lane_id() == 0) tile = atomicAdd(&misc[MISC_TILE_CTR], 1);
+    tile = __shfl(tile, 0, 64);
+    if (tile >= ntiles) break;
+    tile_work<TW, STATS>(tile, W, H, W32, G, inside, sgen, sgcost, sgbb, geo, dist, parent, st);
+  }
+  if (STATS && lane_id() == 0) {
 #pragma unroll
     for (int s = 0; s < 8; ++s) atomicAdd(&stats[s], st[s]);
   }
 }
 
-template <int TW>
-static void launch_tw(const Dev& d, hipStream_t s) {
+static int device_cus() {
+  static int cached[64] = {0};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+  if (!cached[dev]) {
+    int n = 0;
+    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0) n = 256;
+    cached[dev] = n;
+  }
+  return cached[dev];
+}
+
+template <int TW, bool STATS, bool LDSD>
+static hipError_t launch_variant(const Dev& d, hipStream_t s, size_t shm) {
+  auto kern = k_pixel<TW, STATS, LDSD>;
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kPixelThreads, shm) != hipSuccess || per_cu < 1)
+    per_cu = 1;
   constexpr int TH = 64 / TW;
   const long long tiles = (long long)((d.W + TW - 1) / TW) * ((d.H + TH - 1) / TH);
-  const dim3 grid((unsigned)((tiles + 3) / 4));
-  if (d.stats)
-    hipLaunchKernelGGL((k_pixel<TW, true>), grid, dim3(256), 0, s, d.W, d.H, d.W32, d.misc, d.inside, d.sgen,
-                       d.sgcost, d.sgbb, d.edges, d.ext, d.chunks, d.E, d.NC, d.dist, d.parent, d.stats);
-  else
-    hipLaunchKernelGGL((k_pixel<TW, false>), grid, dim3(256), 0, s, d.W, d.H, d.W32, d.misc, d.inside, d.sgen,
-                       d.sgcost, d.sgbb, d.edges, d.ext, d.chunks, d.E, d.NC, d.dist, d.parent, d.stats);
+  const long long waves_needed = tiles;
+  long long blocks = (long long)device_cus() * per_cu;
+  const long long max_blocks = (waves_needed + (kPixelThreads / 64) - 1) / (kPixelThreads / 64);
+  if (blocks > max_blocks) blocks = max_blocks;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(kPixelThreads), shm, s, d.W, d.H, d.W32, d.Gmax, d.misc,
+                     d.inside, d.sgen, d.sgcost, d.sgbb, d.edges, d.ext, d.chunks, d.E, d.NC, d.dist, d.parent,
+                     d.stats);
+  return hipGetLastError();
+}
+
+template <int TW>
+static hipError_t launch_tw(const Dev& d, hipStream_t s) {
+  const size_t shm = pixel_lds_bytes(d.Gmax, d.E, d.NC);
+  const bool lds = shm <= kPixelLdsMax;
+  if (d.stats) return lds ? launch_variant<TW, true, true>(d, s, shm) : launch_variant<TW, true, false>(d, s, 0);
+  return lds ? launch_variant<TW, false, true>(d, s, shm) : launch_variant<TW, false, false>(d, s, 0);
 }
 
 hipError_t launch_pixel(const Dev& d, hipStream_t s) {
-  if (d.tile_w == 16) launch_tw<16>(d, s);
-  else if (d.tile_w == 4) launch_tw<4>(d, s);
-  else launch_tw<8>(d, s);
-  return hipGetLastError();
+  if (d.tile_w == 16) return launch_tw<16>(d, s);
+  if (d.tile_w == 4) return launch_tw<4>(d, s);
+  return launch_tw<8>(d, s);
 }
 
 }  // namespace spm

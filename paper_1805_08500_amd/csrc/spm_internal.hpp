@@ -49,7 +49,7 @@ struct GenRec {
 static_assert(sizeof(GenRec) == 64, "GenRec must be 64 bytes");
 
 // misc ints in the workspace
-enum { MISC_G = 0, MISC_REACHED = 1, MISC_ROUNDS = 2, MISC_N = 16 };
+enum { MISC_G = 0, MISC_REACHED = 1, MISC_ROUNDS = 2, MISC_TILE_CTR = 3, MISC_N = 16 };
 
 struct Layout {
   int W, H, nv, np, ns, np_polys;
@@ -395,6 +395,108 @@ __device__ __forceinline__ u64 wave_blocked_uniform(const Geo& d, int px, int py
         }
       }
     }
+    blocked = ballot(blk) & need;
+  }
+  return blocked;
+}
+// Wave-level visibility between per-lane pixel points P and their closest
+// points q*(P) on one segment source A-B, for lanes whose closest point lies
+// strictly inside the segment.  Then [P, q*] is perpendicular to e = B - A, so
+// with D(x) = e . x the endpoints w, v of an edge lie strictly on opposite
+// sides of line P-q* iff D(P) is strictly between D(w) and D(v); and the
+// obstacle-side sign of q* is the common sign of E(A) and E(B) unless the edge
+// line cuts the segment (then it is computed per lane, exactly, in 64 bits).
+// Lanes with a vertex exactly on their line fall back to the generic test.
+// (bx0..by1) is a box containing every needed P.
+template <bool STATS>
+__device__ __forceinline__ u64 wave_blocked_perp(const Geo& d, int px, int py, u64 need, int ax, int ay, int bx,
+                                                 int by, int bx0, int by0, int bx1, int by1, u64* st) {
+  const int lane = lane_id();
+  const int ex = bx - ax, ey = by - ay;
+  const int L = ex * ex + ey * ey;
+  const int DA = ex * ax + ey * ay;
+  const int Pp = ex * px + ey * py;  // D(P)
+  const long long num = (long long)Pp - DA;  // (P - A) . e, in (0, L) for needed lanes
+  const int Pmin = ex * (ex > 0 ? bx0 : bx1) + ey * (ey > 0 ? by0 : by1);
+  const int Pmax = ex * (ex > 0 ? bx1 : bx0) + ey * (ey > 0 ? by1 : by0);
+  // culling box: the pixel box and the part of the segment it projects onto
+  const float t0 = fminf(fmaxf((float)(Pmin - DA) / (float)L, 0.0f), 1.0f);
+  const float t1 = fminf(fmaxf((float)(Pmax - DA) / (float)L, 0.0f), 1.0f);
+  const float qx0 = ax + t0 * ex, qx1 = ax + t1 * ex, qy0 = ay + t0 * ey, qy1 = ay + t1 * ey;
+  const int cx0 = min(bx0, (int)floorf(fminf(qx0, qx1)) - 1), cx1 = max(bx1, (int)ceilf(fmaxf(qx0, qx1)) + 1);
+  const int cy0 = min(by0, (int)floorf(fminf(qy0, qy1)) - 1), cy1 = max(by1, (int)ceilf(fmaxf(qy0, qy1)) + 1);
+  bool blk = false, dg = false;
+  u64 blocked = 0;
+  for (int cb = 0; cb < d.NC; cb += kWave) {
+    int ci = cb + lane;
+    bool hit = false;
+    if (ci < d.NC) {
+      int4 bb = d.chunks[ci];
+      hit = bb.x <= cx1 && bb.z >= cx0 && bb.y <= cy1 && bb.w >= cy0;
+    }
+    u64 cm = ballot(hit);
+    while (cm) {
+      const int chunk = cb + first_bit(cm);
+      cm &= cm - 1;
+      const int e = chunk * kChunk + lane;
+      bool rel = false, occ = false;
+      if (e < d.E) {
+        EdgeRec r = d.edges[e];
+        const int EA = r.a * ax + r.b * ay + r.c, EB = r.a * bx + r.b * by + r.c;
+        const int hiE = r.a * (r.a > 0 ? bx1 : bx0) + r.b * (r.b > 0 ? by1 : by0) + r.c;
+        const int loE = r.a * (r.a > 0 ? bx0 : bx1) + r.b * (r.b > 0 ? by0 : by1) + r.c;
+        const int Dw = ex * r.wx + ey * r.wy, Dv = ex * r.vx + ey * r.vy;
+        const int lo = min(Dw, Dv), hi = max(Dw, Dv);
+        const bool strad = Pmax >= lo && Pmin <= hi;
+        bool side, full;
+        if (EA > 0 && EB > 0) { side = loE < 0; full = hiE < 0; }
+        else if (EA < 0 && EB < 0) { side = hiE > 0; full = loE > 0; }
+        else if (EA == 0 && EB == 0) { side = false; full = false; }
+        else { side = loE < 0 || hiE > 0; full = false; }
+        rel = strad && side;
+        occ = full && lo < Pmin && Pmax < hi;
+      }
+      if (STATS) st[4] += 1;
+      if (ballot(occ)) {
+        if (STATS) st[6] += 1;
+        return need;
+      }
+      u64 rm = ballot(rel);
+      while (rm) {
+        const int q = chunk * kChunk + first_bit(rm);
+        rm &= rm - 1;
+        const int wx = d.edges[q].wx, wy = d.edges[q].wy, vx = d.edges[q].vx, vy = d.edges[q].vy;
+        const int ea = d.edges[q].a, eb = d.edges[q].b, ec = d.edges[q].c;
+        if (STATS) st[5] += (u64)__popcll(need & ~blocked);
+        const int Dw = ex * wx + ey * wy, Dv = ex * vx + ey * vy;
+        const int lo = min(Dw, Dv), hi = max(Dw, Dv);
+        const int EA = ea * ax + eb * ay + ec, EB = ea * bx + eb * by + ec;
+        const bool str = Pp > lo && Pp < hi;
+        dg = dg || Pp == lo || Pp == hi;
+        const int ep = mad24(ea, px, mad24(eb, py, ec));
+        bool opp;
+        if (EA > 0 && EB > 0) opp = ep < 0;
+        else if (EA < 0 && EB < 0) opp = ep > 0;
+        else if (EA == 0 && EB == 0) opp = false;
+        else {
+          // E(q*) * L = E(A) * L + num * (E(B) - E(A)), exact in 64 bits
+          const long long eq = (long long)EA * L + num * (long long)(EB - EA);
+          opp = (ep > 0 && eq < 0) || (ep < 0 && eq > 0);
+        }
+        blk = blk || (str && opp);
+      }
+      blocked = ballot(blk) & need;
+      if (blocked == need) return need;
+    }
+  }
+  u64 slow = ballot(dg) & need & ~blocked;
+  if (slow) {
+    int clamp;
+    const RPt q = seg_closest(ax, ay, bx, by, px, py, &clamp);
+    const bool mine = (slow >> lane) & 1ull;
+    const bool vs = lane_visible_rational(d, px, py, false, 0, 0, 0, 0, q, mine, min(cx0, bx0), min(cy0, by0),
+                                          max(cx1, bx1), max(cy1, by1));
+    blk = blk || (mine && !vs);
     blocked = ballot(blk) & need;
   }
   return blocked;
