@@ -36,7 +36,7 @@ __global__ void k_ingest_edges(int nv, int n_polys, const int* __restrict__ poly
   r.a = wy - ny;
   r.b = nx - wx;
   r.c = -(r.a * wx + r.b * wy);
-  r.id = i;
+  r.nc = -r.c;
   edges_raw[i] = r;
   EdgeExt x;
   x.ux = ux; x.uy = uy; x.nx = 2 * vx[inn]; x.ny = 2 * vy[inn];

@@ -49,6 +49,46 @@ __device__ __forceinline__ void mask_box(u64 m, int i0, int j0, int& bx0, int& b
   by1 = 2 * (j0 + r1) + 1;
 }
 
+// Lane mask of quadrant q (0..3) of a TW x (64/TW) tile: the tile is halved in
+// both directions so that the tile bound can use four boxes and four upper
+// bounds instead of one.
+template <int TW>
+__host__ __device__ constexpr u64 quad_mask(int q) {
+  u64 m = 0;
+  for (int l = 0; l < 64; ++l) {
+    const int c = l % TW, r = l / TW;
+    const int lq = (c >= TW / 2 ? 1 : 0) + (r >= (64 / TW) / 2 ? 2 : 0);
+    if (lq == q) m |= 1ull << l;
+  }
+  return m;
+}
+
+// Per-quadrant maximum of v over the lanes of each quadrant (4 exchange steps).
+template <int TW>
+__device__ __forceinline__ float quad_max(float v) {
+  constexpr int TH = 64 / TW;
+#pragma unroll
+  for (int m = 1; m < TW / 2; m <<= 1) v = fmaxf(v, __shfl_xor(v, m, 64));
+#pragma unroll
+  for (int m = TW; m < (TH / 2) * TW; m <<= 1) v = fmaxf(v, __shfl_xor(v, m, 64));
+  return v;
+}
+
+__device__ __forceinline__ float readlane_f(float v, int l) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+__device__ __forceinline__ int readlane_i(int v, int l) { return __builtin_amdgcn_readlane(v, l); }
+
+// conservative test: can a generator with cost c and bounding box (x0..y1) come
+// below ub anywhere in the box (bx0..by1)?
+__device__ __forceinline__ bool box_may_win(float c, int x0, int y0, int x1, int y1, int bx0, int by0, int bx1,
+                                            int by1, float ub) {
+  const int dx = max(max(x0 - bx1, bx0 - x1), 0);
+  const int dy = max(max(y0 - by1, by0 - y1), 0);
+  const float room = ub - c;
+  return room > 0.0f && (float)(dx * dx + dy * dy) < 4.0f * room * room * (1.0f + 2e-6f);
+}
+
 // One tile: the per-lane minimum over generators for 64 pixels.  The
 // generator tables and the edges come through plain pointers that point
 // either into LDS (staged by the kernel) or into global memory.
@@ -57,6 +97,7 @@ __device__ __forceinline__ void tile_work(int tile, int W, int H, int W32, int G
                                           const GenRec* sgen, const float* sgcost, const int4* sgbb, const Geo& geo,
                                           float* __restrict__ dist, int* __restrict__ parent, u64* st) {
   constexpr int TH = 64 / TW;
+  constexpr int QL[4] = {0, TW / 2, (TH / 2) * TW, (TH / 2) * TW + TW / 2};  // first lane of each quadrant
   const int lane = lane_id();
   const int ntx = (W + TW - 1) / TW;
   const int ty = tile / ntx, tx = tile - ty * ntx;
@@ -72,55 +113,53 @@ __device__ __forceinline__ void tile_work(int tile, int W, int H, int W32, int G
   int par = -1;
   const u64 act = ballot(active);
   if (act) {
-    int tbx0, tby0, tbx1, tby1;
-    mask_box<TW>(act, i0, j0, tbx0, tby0, tbx1, tby1);
+    // quadrant upper bounds; quadrant q spans pixel columns i0 + (q & 1) * TW/2 .. + TW/2 - 1 and rows
+    // j0 + (q >> 1) * TH/2 .. + TH/2 - 1 (doubled centres below)
+    float ubq[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) ubq[q] = (act & quad_mask<TW>(q)) ? INFINITY : -INFINITY;
+    const int qx0 = 2 * i0 + 1, qx1 = qx0 + TW, qy0 = 2 * j0 + 1, qy1 = qy0 + TH;  // lower-half / upper-half starts
     float UB = INFINITY;
     bool done = false;
     for (int base = 0; base < G && !done; base += 64) {
       if (sgcost[base] >= UB) break;
       if (STATS) st[ST_BATCHES] += 1;
-      // lane-parallel tile bound: cost + distance from the generator to the tile
+      // lane-parallel tile bound against the four quadrants
       const int g = base + lane;
       bool cand = false;
+      float c = INFINITY;
+      int4 bb = make_int4(0, 0, 0, 0);
       if (g < G) {
-        const float c = sgcost[g];
-        const int4 bb = sgbb[g];
-        const int dx = max(max(bb.x - tbx1, tbx0 - bb.z), 0);
-        const int dy = max(max(bb.y - tby1, tby0 - bb.w), 0);
-        const float lb = (c + 0.5f * sqrtf((float)(dx * dx + dy * dy))) * (1.0f - 1e-6f);
-        cand = lb < UB;
+        c = sgcost[g];
+        bb = sgbb[g];
+        cand = box_may_win(c, bb.x, bb.y, bb.z, bb.w, qx0, qy0, qx1 - 2, qy1 - 2, ubq[0]) ||
+               box_may_win(c, bb.x, bb.y, bb.z, bb.w, qx1, qy0, qx1 + TW - 2, qy1 - 2, ubq[1]) ||
+               box_may_win(c, bb.x, bb.y, bb.z, bb.w, qx0, qy1, qx1 - 2, qy1 + TH - 2, ubq[2]) ||
+               box_may_win(c, bb.x, bb.y, bb.z, bb.w, qx1, qy1, qx1 + TW - 2, qy1 + TH - 2, ubq[3]);
       }
       u64 cm = ballot(cand);
       while (cm) {
-        const int k = base + first_bit(cm);
+        const int jl = first_bit(cm);
         cm &= cm - 1;
-        const float gc = sgcost[k];
+        const int k = base + jl;
+        const float gc = readlane_f(c, jl);
         if (gc >= UB) { done = true; break; }
-        const int kind = sgen[k].kind;
-        const int gx = sgen[k].x, gy = sgen[k].y;
+        const int x0 = readlane_i(bb.x, jl), y0 = readlane_i(bb.y, jl);
+        const int x1 = readlane_i(bb.z, jl), y1 = readlane_i(bb.w, jl);
         bool upd = false;
-        if (kind != SPM_GEN_SEGMENT) {
-          const int dx = px - gx, dy = py - gy;
-          const int d2 = mad24(dx, dx, mul24(dy, dy));
+        const bool is_seg = !(x0 == x1 && y0 == y1);
+        float cc = 0.0f;  // segment: this lane's candidate value
+        int clamp = 0;    // segment: closest point is A (0), B (1) or interior (2)
+        int ax = x0, ay = y0, bx = x1, by = y1;
+        const int ddx = px - x0, ddy = py - y0;
+        const int d2 = mad24(ddx, ddx, mul24(ddy, ddy));   // point or corner: squared doubled distance
+        bool need;
+        if (!is_seg) {
+          // cost + |p - g| < best  <=>  d2 < 4 (best - cost)^2; the factor keeps the filter conservative
           const float room = best - gc;
-          const bool need = active && room > 0.0f && (float)d2 < 4.0f * room * room * (1.0f + 1e-6f);
-          const u64 nm = ballot(need);
-          if (STATS) st[ST_BOUND] += __popcll(act);
-          if (!nm) continue;
-          if (STATS) st[ST_VISWAVE] += 1;
-          int bx0, by0, bx1, by1;
-          mask_box<TW>(nm, i0, j0, bx0, by0, bx1, by1);
-          const bool gv = kind == SPM_GEN_VERTEX;
-          const u64 bl = wave_blocked_uniform<STATS>(geo, px, py, nm, gx, gy, gv, sgen[k].ux, sgen[k].uy,
-                                                     sgen[k].nx, sgen[k].ny, false, 0, 0, 0, 0, bx0, by0, bx1,
-                                                     by1, st);
-          if (need && !((bl >> lane) & 1ull)) {
-            const float c = gc + 0.5f * sqrtf((float)d2);
-            if (c < best) { best = c; par = sgen[k].id; upd = true; }
-          }
+          need = active && room > 0.0f && (float)d2 < 4.0f * room * room * (1.0f + 1e-6f);
         } else {
-          const int ax = gx, ay = gy, bx = sgen[k].x2, by = sgen[k].y2;
-          int clamp;
+          ax = sgen[k].x; ay = sgen[k].y; bx = sgen[k].x2; by = sgen[k].y2;
           const RPt q = seg_closest(ax, ay, bx, by, px, py, &clamp);
           (void)q;
           float dd;
@@ -133,38 +172,47 @@ __device__ __forceinline__ void tile_work(int tile, int W, int H, int W32, int G
             const long long cr = ex * (py - ay) - ey * (px - ax);
             dd = 0.5f * fabsf((float)cr) / sqrtf((float)(ex * ex + ey * ey));
           }
-          const float c = gc + dd;
-          const bool need = active && c < best;
-          const u64 nm = ballot(need);
-          if (STATS) st[ST_BOUND] += __popcll(act);
-          if (!nm) continue;
-          // lanes whose closest point is endpoint A, endpoint B, or interior
-          u64 bl = 0;
-          const u64 mA = ballot(need && clamp == 0), mB = ballot(need && clamp == 1);
-          const u64 mI = nm & ~mA & ~mB;
-          int bx0, by0, bx1, by1;
-          if (mA) {
-            if (STATS) st[ST_VISWAVE] += 1;
-            mask_box<TW>(mA, i0, j0, bx0, by0, bx1, by1);
-            bl |= wave_blocked_uniform<STATS>(geo, px, py, mA, ax, ay, false, 0, 0, 0, 0, false, 0, 0, 0, 0, bx0,
-                                              by0, bx1, by1, st);
-          }
-          if (mB) {
-            if (STATS) st[ST_VISWAVE] += 1;
-            mask_box<TW>(mB, i0, j0, bx0, by0, bx1, by1);
-            bl |= wave_blocked_uniform<STATS>(geo, px, py, mB, bx, by, false, 0, 0, 0, 0, false, 0, 0, 0, 0, bx0,
-                                              by0, bx1, by1, st);
-          }
-          if (mI) {
-            if (STATS) st[ST_VISWAVE] += 1;
-            mask_box<TW>(mI, i0, j0, bx0, by0, bx1, by1);
-            bl |= wave_blocked_perp<STATS>(geo, px, py, mI, ax, ay, bx, by, bx0, by0, bx1, by1, st);
-          }
-          if (need && !((bl >> lane) & 1ull)) { best = c; par = sgen[k].id; upd = true; }
+          cc = gc + dd;
+          need = active && cc < best;
         }
-        if (ballot(upd)) {
-          if (STATS) st[ST_ACCEPT] += __popcll(ballot(upd));
-          UB = wave_max(active ? best : -INFINITY);
+        const u64 nm = ballot(need);
+        if (STATS) st[ST_BOUND] += __popcll(act);
+        if (!nm) continue;
+        // visibility groups: a point or corner is one group at (x0, y0); a segment has up to three
+        // (lanes reaching endpoint A, endpoint B, or an interior point)
+        const u64 mA = is_seg ? ballot(need && clamp == 0) : nm;
+        const u64 mB = is_seg ? ballot(need && clamp == 1) : 0ull;
+        const u64 mI = nm & ~mA & ~mB;
+        const bool gv = !is_seg && sgen[k].kind == SPM_GEN_VERTEX;
+        u64 bl = 0;
+        for (int grp = 0; grp < 2; ++grp) {
+          const u64 m = grp ? mB : mA;
+          if (!m) continue;
+          if (STATS) st[ST_VISWAVE] += 1;
+          int bx0, by0, bx1, by1;
+          mask_box<TW>(m, i0, j0, bx0, by0, bx1, by1);
+          const int gx = grp ? bx : ax, gy = grp ? by : ay;
+          bl |= wave_blocked_uniform<STATS>(geo, px, py, m, gx, gy, gv, gv ? sgen[k].ux : 0, gv ? sgen[k].uy : 0,
+                                            gv ? sgen[k].nx : 0, gv ? sgen[k].ny : 0, false, 0, 0, 0, 0, bx0, by0,
+                                            bx1, by1, st);
+        }
+        if (mI) {
+          if (STATS) st[ST_VISWAVE] += 1;
+          int bx0, by0, bx1, by1;
+          mask_box<TW>(mI, i0, j0, bx0, by0, bx1, by1);
+          bl |= wave_blocked_perp<STATS>(geo, px, py, mI, ax, ay, bx, by, bx0, by0, bx1, by1, st);
+        }
+        if (need && !((bl >> lane) & 1ull)) {
+          if (!is_seg) cc = gc + 0.5f * sqrtf((float)d2);
+          if (cc < best) { best = cc; par = sgen[k].id; upd = true; }
+        }
+        const u64 um = ballot(upd);
+        if (um) {
+          if (STATS) st[ST_ACCEPT] += __popcll(um);
+          const float qm = quad_max<TW>(active ? best : -INFINITY);
+#pragma unroll
+          for (int q = 0; q < 4; ++q) ubq[q] = readlane_f(qm, QL[q]);
+          UB = fmaxf(fmaxf(ubq[0], ubq[1]), fmaxf(ubq[2], ubq[3]));
         }
       }
     }
@@ -189,7 +237,7 @@ inline size_t pixel_lds_bytes(int Gmax, int E, int NC) {
 // first staged in LDS, so the wave-uniform reads of the hot loops are LDS
 // broadcasts instead of L2 round trips.
 template <int TW, bool STATS, bool LDSD>
-__global__ __launch_bounds__(kPixelThreads) void k_pixel(int W, int H, int W32, int Gmax, int* misc,
+__global__ __launch_bounds__(kPixelThreads, 6) void k_pixel(int W, int H, int W32, int Gmax, int* misc,
                                                          const unsigned* __restrict__ inside,
                                                          const GenRec* __restrict__ sgen_g,
                                                          const float* __restrict__ sgcost_g,

@@ -28,7 +28,7 @@ constexpr int kRelaxLdsMaxGen = 7680;   // keeps the relaxation LDS (costs + cha
 // E(x, y) = a x + b y + c, positive on the obstacle side.
 struct EdgeRec {
   int wx, wy, vx, vy;
-  int a, b, c, id;  // id: index of w in the input vertex order
+  int a, b, c, nc;  // nc = -c
 };
 // Neighbours needed by the vertex rule: prev(w) and next(v).
 struct EdgeExt {
@@ -348,14 +348,15 @@ __device__ __forceinline__ u64 wave_blocked_uniform(const Geo& d, int px, int py
         const int q = chunk * kChunk + first_bit(rm);
         rm &= rm - 1;
         const int wx = d.edges[q].wx, wy = d.edges[q].wy, vx = d.edges[q].vx, vy = d.edges[q].vy;
-        const int ea = d.edges[q].a, eb = d.edges[q].b, ec = d.edges[q].c;
+        const int ea = d.edges[q].a, eb = d.edges[q].b, enc = d.edges[q].nc;
         if (STATS) st[5] += (u64)__popcll(need & ~blocked);
-        int ow = mad24(A, wx, mad24(B, wy, C));
-        int ov = mad24(A, vx, mad24(B, vy, C));
-        int prod = mul24(sgn3(ow), sgn3(ov));
-        int ep = mad24(ea, px, mul24(eb, py));
-        blk = blk || (prod < 0 && ep > -ec);
-        dg = dg || (prod == 0);
+        const int ow = mad24(A, wx, mad24(B, wy, C));
+        const int ov = mad24(A, vx, mad24(B, vy, C));
+        // sign of ow * ov: converting to float keeps every sign and every zero exact
+        const float prod = (float)ow * (float)ov;
+        const int ep = mad24(ea, px, mul24(eb, py));
+        blk = blk || (prod < 0.0f && ep > enc);
+        dg = dg || (prod == 0.0f);
       }
       blocked = ballot(blk) & need;
       if (blocked == need) return need;
