@@ -41,25 +41,40 @@ __device__ __forceinline__ double arc_len(const GenRec& u, int vx, int vy) {
 
 // One wavefront per (row corner v, block of 64 generators u): bit u of row v
 // is set iff the arc u -> v exists (u a source or another corner that sees v;
-// for a segment source, v sees the segment's closest point to v).
-__global__ __launch_bounds__(256) void k_genvis(int Gmax, int RW, const int* __restrict__ misc,
-                                                const GenRec* __restrict__ gens,
+// for a segment source, v sees the segment's closest point to v).  Rows and
+// bits are indexed by spatial position (gorder), so the 64 generators of a
+// wavefront are neighbours in space and share few relevant edges.  LDSE: the
+// edges and chunk boxes are staged in LDS first.
+template <bool LDSE>
+__global__ __launch_bounds__(256) void k_genvis(int Gmax, int RW, int nsrc, const int* __restrict__ misc,
+                                                const GenRec* __restrict__ gens, const int* __restrict__ gorder,
                                                 const EdgeRec* __restrict__ edges,
                                                 const EdgeExt* __restrict__ ext,
                                                 const int4* __restrict__ chunks, int E, int NC,
                                                 u64* __restrict__ vis) {
+  extern __shared__ int4 smem[];
+  Geo geo{edges, ext, chunks, E, NC};
+  if (LDSE) {
+    EdgeRec* s_edges = (EdgeRec*)smem;
+    int4* s_chunks = (int4*)(s_edges + E);
+    const int4* se = (const int4*)edges;
+    for (int k = threadIdx.x; k < E * 2; k += blockDim.x) ((int4*)s_edges)[k] = se[k];
+    for (int k = threadIdx.x; k < NC; k += blockDim.x) s_chunks[k] = chunks[k];
+    __syncthreads();
+    geo.edges = s_edges;
+    geo.chunks = s_chunks;
+  }
   const int wid = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-  const int v = wid / RW, blk = wid - v * RW;
+  const int r = wid / RW, blk = wid - r * RW;
   const int G = uni(misc[MISC_G]);
-  if (v >= G) return;
+  if (r >= G || r < nsrc) return;  // only corner rows are read
   const int lane = lane_id();
-  const Geo geo{edges, ext, chunks, E, NC};
-  const int vkind = uni(gens[v].kind);
-  if (vkind != SPM_GEN_VERTEX) return;
+  const int v = uni(gorder[r]);
   const int gx = uni(gens[v].x), gy = uni(gens[v].y);
   const int gux = uni(gens[v].ux), guy = uni(gens[v].uy), gnx = uni(gens[v].nx), gny = uni(gens[v].ny);
-  const int u = blk * 64 + lane;
-  const bool valid = u < G && u != v;
+  const int upos = blk * 64 + lane;
+  const int u = upos < G ? gorder[upos] : -1;
+  const bool valid = u >= 0 && u != v;
   GenRec gu = {};
   if (valid) gu = gens[u];
   const bool fast = valid && gu.kind != SPM_GEN_SEGMENT;
@@ -87,32 +102,56 @@ __global__ __launch_bounds__(256) void k_genvis(int Gmax, int RW, const int* __r
     if (seg) ok = vs;
   }
   const u64 bits = ballot(ok);
-  if (lane == 0) vis[(size_t)v * RW + blk] = bits;
+  if (lane == 0) vis[(size_t)r * RW + blk] = bits;
 }
 
-// Single workgroup Bellman-Ford over the arc matrix.  Sources start at 0;
-// a round relaxes every corner from the generators whose cost changed in the
-// previous round, updating in place; it stops at the first round without a
-// change.  Positive arc weights make the double-precision fixed point unique,
-// so the result does not depend on thread timing.
+// Arc weight from a generator with doubled coordinates (x, y, x2, y2) --
+// a segment iff (x, y) != (x2, y2) -- to the corner at (vx, vy).
+__device__ __forceinline__ double arc_len4(int4 u, int vx, int vy) {
+  GenRec r;
+  r.kind = (u.x != u.z || u.y != u.w) ? SPM_GEN_SEGMENT : SPM_GEN_POINT;
+  r.x = u.x; r.y = u.y; r.x2 = u.z; r.y2 = u.w;
+  return arc_len(r, vx, vy);
+}
+
+constexpr int kRelaxFront = 2048;   // largest frontier kept as a list (push rounds)
+
+// Single workgroup Bellman-Ford over the arc matrix, iterated to its fixed
+// point (the costs Dijkstra reaches).  Sources start at 0.  Each round relaxes
+// the arcs leaving the generators whose cost changed in the previous round:
+//   pull  (large frontier): every corner v scans row v restricted to the
+//         frontier and keeps the best candidate;
+//   push  (small frontier, corners only): for each frontier corner u, every
+//         corner v of row u -- corner-to-corner visibility is symmetric -- takes
+//         cost(u) + |u - v| through an atomic minimum on the IEEE bits of the
+//         non-negative doubles, which order like the values.
+// Positive arc weights make the double-precision fixed point unique, so the
+// result does not depend on thread timing or on the pull/push schedule.
+// LDS: costs, generator coordinates, change masks and the frontier list live
+// in LDS when they fit, else in global memory.
 template <bool LDS>
-__global__ __launch_bounds__(1024) void k_relax(int Gmax, int RW, const GenRec* __restrict__ gens,
-                                                const u64* __restrict__ vis, double* __restrict__ cost_g, int* misc,
-                                                double* __restrict__ gen_cost, int* __restrict__ gen_parent) {
+__global__ __launch_bounds__(1024) void k_relax(int Gmax, int RW, int nsrc, const GenRec* __restrict__ gens,
+                                                const int* __restrict__ gorder, const u64* __restrict__ vis,
+                                                u64* __restrict__ cost_pos_g, u64* __restrict__ cost_out,
+                                                int4* __restrict__ gxy_g, int* misc, double* __restrict__ gen_cost,
+                                                int* __restrict__ gen_parent) {
   extern __shared__ u64 shm[];
+  __shared__ int any, nfront, reached;
+  __shared__ int front[kRelaxFront];
   u64* chg_a = shm;
   u64* chg_b = shm + RW;
-  double* cost = LDS ? (double*)(shm + 2 * RW) : cost_g;
-  __shared__ int any;
-  __shared__ int reached;
-  const int tid = threadIdx.x;
+  u64* cost = LDS ? (shm + 2 * RW) : cost_pos_g;   // indexed by spatial position
+  int4* gxy = LDS ? (int4*)(shm + 2 * RW + Gmax) : gxy_g;
+  const int tid = threadIdx.x, nt = blockDim.x;
   const int G = misc[MISC_G];
-  for (int k = tid; k < RW; k += blockDim.x) { chg_a[k] = 0; chg_b[k] = 0; }
-  if (tid == 0) reached = 0;
+  for (int k = tid; k < RW; k += nt) { chg_a[k] = 0; chg_b[k] = 0; }
+  if (tid == 0) { reached = 0; nfront = -1; }
   __syncthreads();
-  for (int g = tid; g < G; g += blockDim.x) {
-    const bool src = gens[g].kind != SPM_GEN_VERTEX;
-    cost[g] = src ? 0.0 : INFINITY;
+  for (int g = tid; g < G; g += nt) {
+    const GenRec r = gens[gorder[g]];
+    const bool src = g < nsrc;
+    cost[g] = (u64)__double_as_longlong(src ? 0.0 : INFINITY);
+    gxy[g] = make_int4(r.x, r.y, r.x2, r.y2);
     if (src) atomicOr(&chg_a[g >> 6], 1ull << (g & 63));
   }
   __syncthreads();
@@ -121,62 +160,111 @@ __global__ __launch_bounds__(1024) void k_relax(int Gmax, int RW, const GenRec* 
   int rounds = 0;
   for (; rounds <= G; ++rounds) {
     if (tid == 0) any = 0;
+    const int nf = nfront;  // frontier list size, or -1 when only the mask is valid
     __syncthreads();
-    for (int v = tid; v < G; v += blockDim.x) {
-      const GenRec gv = gens[v];
-      if (gv.kind != SPM_GEN_VERTEX) continue;
-      const double old = cost[v];
-      double best = old;
-      const u64* row = vis + (size_t)v * RW;
-      for (int k = 0; k < RW; ++k) {
-        const u64 c = cur[k];
-        if (!c) continue;
-        u64 m = row[k] & c;
-        while (m) {
-          const int u = k * 64 + __builtin_ctzll(m);
-          m &= m - 1;
-          const double cu = cost[u];
-          if (!(cu < INFINITY)) continue;
-          const double cand = cu + arc_len(gens[u], gv.x, gv.y);
-          if (cand < best) best = cand;
+    if (nf < 0) {
+      for (int v = tid; v < G; v += nt) {
+        const int4 pv = gxy[v];
+        if (v < nsrc) continue;  // sources (ids below nsrc) keep cost 0
+        const double old = __longlong_as_double((long long)cost[v]);
+        double best = old;
+        const u64* row = vis + (size_t)v * RW;
+        for (int k = 0; k < RW; ++k) {
+          const u64 c = cur[k];
+          if (!c) continue;
+          u64 m = row[k] & c;
+          while (m) {
+            const int u = k * 64 + __builtin_ctzll(m);
+            m &= m - 1;
+            const double cu = __longlong_as_double((long long)cost[u]);
+            if (!(cu < best)) continue;
+            const double cand = cu + arc_len4(gxy[u], pv.x, pv.y);
+            if (cand < best) best = cand;
+          }
+        }
+        if (best < old) {
+          cost[v] = (u64)__double_as_longlong(best);
+          atomicOr(&nxt[v >> 6], 1ull << (v & 63));
+          any = 1;
         }
       }
-      if (best < old) {
-        cost[v] = best;
-        atomicOr(&nxt[v >> 6], 1ull << (v & 63));
-        any = 1;
+    } else {
+      for (int it = tid; it < nf * RW; it += nt) {
+        const int f = it / RW, k = it - f * RW;
+        const int u = front[f];
+        u64 m = vis[(size_t)u * RW + k];
+        if (!m) continue;
+        const double cu = __longlong_as_double((long long)cost[u]);
+        const int4 pu = gxy[u];
+        while (m) {
+          const int v = k * 64 + __builtin_ctzll(m);
+          m &= m - 1;
+          const double cv = __longlong_as_double((long long)cost[v]);
+          if (!(cu < cv)) continue;
+          const int4 pv = gxy[v];
+          const double cand = cu + arc_len4(pu, pv.x, pv.y);
+          if (cand < cv) {
+            const u64 ob = atomicMin(&cost[v], (u64)__double_as_longlong(cand));
+            if (__longlong_as_double((long long)ob) > cand) {
+              atomicOr(&nxt[v >> 6], 1ull << (v & 63));
+              any = 1;
+            }
+          }
+        }
       }
     }
     __syncthreads();
     if (!any) break;
+    // next frontier: a list when small enough (all corners), else the mask alone
+    if (tid == 0) nfront = 0;
+    __syncthreads();
+    for (int k = tid; k < RW; k += nt) {
+      const u64 m = nxt[k];
+      if (!m) continue;
+      const int n = __popcll(m);
+      const int at = atomicAdd(&nfront, n);
+      u64 mm = m;
+      for (int t = 0; t < n; ++t) {
+        const int b = __builtin_ctzll(mm);
+        mm &= mm - 1;
+        if (at + t < kRelaxFront) front[at + t] = k * 64 + b;
+      }
+    }
+    __syncthreads();
+    if (tid == 0 && nfront > kRelaxFront / 4) nfront = -1;  // large frontier: pull round
     u64* t = cur;
     cur = nxt;
     nxt = t;
-    for (int k = tid; k < RW; k += blockDim.x) nxt[k] = 0;
+    for (int k = tid; k < RW; k += nt) nxt[k] = 0;
     __syncthreads();
   }
-  // parents and outputs
+  // parents (smallest canonical id attaining the cost) and outputs, in canonical order
   int mine = 0;
-  for (int v = tid; v < G; v += blockDim.x) {
-    const GenRec gv = gens[v];
-    const double c = cost[v];
+  for (int p = tid; p < G; p += nt) {
+    const double c = __longlong_as_double((long long)cost[p]);
+    const int v = gorder[p];
     int par = -1;
-    if (gv.kind != SPM_GEN_VERTEX) par = v;
+    if (p < nsrc) par = v;
     else if (c < INFINITY) {
-      const u64* row = vis + (size_t)v * RW;
-      for (int k = 0; k < RW && par < 0; ++k) {
+      const int4 pv = gxy[p];
+      const u64* row = vis + (size_t)p * RW;
+      for (int k = 0; k < RW; ++k) {
         u64 m = row[k];
         while (m) {
-          const int u = k * 64 + __builtin_ctzll(m);
+          const int up = k * 64 + __builtin_ctzll(m);
           m &= m - 1;
-          const double cu = cost[u];
-          if (cu < INFINITY && cu + arc_len(gens[u], gv.x, gv.y) == c) { par = u; break; }
+          const double cu = __longlong_as_double((long long)cost[up]);
+          if (!(cu < c)) continue;
+          if (cu + arc_len4(gxy[up], pv.x, pv.y) == c) {
+            const int u = gorder[up];
+            if (par < 0 || u < par) par = u;
+          }
         }
       }
     }
     gen_cost[v] = c;
     gen_parent[v] = par;
-    if (LDS) cost_g[v] = c;
+    cost_out[v] = (u64)__double_as_longlong(c);
     if (c < INFINITY) ++mine;
   }
   atomicAdd(&reached, mine);
@@ -220,20 +308,46 @@ __global__ __launch_bounds__(256) void k_gsort(int* misc, const GenRec* __restri
 hipError_t launch_genvis(const Dev& d, hipStream_t s) {
   if (d.Gmax == 0) return hipSuccess;
   const long long waves = (long long)d.Gmax * d.RW;
-  hipLaunchKernelGGL(k_genvis, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, s, d.Gmax, d.RW, d.misc, d.gens,
-                     d.edges, d.ext, d.chunks, d.E, d.NC, d.vis);
+  const dim3 grid((unsigned)((waves + 3) / 4));
+  const size_t shm = (size_t)d.E * sizeof(EdgeRec) + (size_t)d.NC * 16;
+  if (shm <= 32768)
+    hipLaunchKernelGGL(k_genvis<true>, grid, dim3(256), shm, s, d.Gmax, d.RW, d.np + d.ns, d.misc, d.gens,
+                       d.gorder, d.edges, d.ext, d.chunks, d.E, d.NC, d.vis);
+  else
+    hipLaunchKernelGGL(k_genvis<false>, grid, dim3(256), 0, s, d.Gmax, d.RW, d.np + d.ns, d.misc, d.gens,
+                       d.gorder, d.edges, d.ext, d.chunks, d.E, d.NC, d.vis);
   return hipGetLastError();
+}
+
+static int max_lds_per_block() {
+  static int cached[64] = {0};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 65536;
+  if (!cached[dev]) {
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess || v <= 0) v = 65536;
+    cached[dev] = v;
+  }
+  return cached[dev];
 }
 
 hipError_t launch_relax(const Dev& d, hipStream_t s) {
   const size_t chg = 2 * (size_t)(d.RW > 0 ? d.RW : 1) * sizeof(u64);
-  if (d.Gmax <= kRelaxLdsMaxGen) {
-    const size_t shm = chg + (size_t)(d.Gmax > 0 ? d.Gmax : 1) * sizeof(double);
-    hipLaunchKernelGGL(k_relax<true>, dim3(1), dim3(kRelaxThreads), shm, s, d.Gmax, d.RW, d.gens, d.vis,
-                       d.cost64, d.misc, d.gen_cost, d.gen_parent);
+  const size_t G1 = (size_t)(d.Gmax > 0 ? d.Gmax : 1);
+  const size_t shm = chg + G1 * (sizeof(u64) + sizeof(int4));
+  const size_t static_lds = 4 * 3 + kRelaxFront * 4 + 64;
+  u64* cost_bits = (u64*)d.cost64;   // the same 8-byte slots, as IEEE bit patterns
+  if (shm + static_lds <= (size_t)max_lds_per_block()) {
+    if (shm > 65536) {
+      hipError_t e = hipFuncSetAttribute((const void*)k_relax<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                         (int)shm);
+      if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(k_relax<true>, dim3(1), dim3(kRelaxThreads), shm, s, d.Gmax, d.RW, d.np + d.ns, d.gens,
+                       d.gorder, d.vis, d.costpos, cost_bits, d.gxy, d.misc, d.gen_cost, d.gen_parent);
   } else {
-    hipLaunchKernelGGL(k_relax<false>, dim3(1), dim3(kRelaxThreads), chg, s, d.Gmax, d.RW, d.gens, d.vis,
-                       d.cost64, d.misc, d.gen_cost, d.gen_parent);
+    hipLaunchKernelGGL(k_relax<false>, dim3(1), dim3(kRelaxThreads), chg, s, d.Gmax, d.RW, d.np + d.ns, d.gens,
+                       d.gorder, d.vis, d.costpos, cost_bits, d.gxy, d.misc, d.gen_cost, d.gen_parent);
   }
   return hipGetLastError();
 }

@@ -57,7 +57,8 @@ __global__ __launch_bounds__(1024) void k_gen_table(int np, int ns, int nv, int 
                                                     const EdgeExt* __restrict__ ext_raw,
                                                     const int* __restrict__ convex, GenRec* __restrict__ gens,
                                                     int* __restrict__ misc, int* __restrict__ n_gen,
-                                                    int* __restrict__ gen_kind, int* __restrict__ gen_xy) {
+                                                    int* __restrict__ gen_kind, int* __restrict__ gen_xy,
+                                                    int* __restrict__ vtx2gid) {
   __shared__ int wave_tot[16];
   __shared__ int running;
   const int tid = threadIdx.x;
@@ -111,6 +112,7 @@ __global__ __launch_bounds__(1024) void k_gen_table(int np, int ns, int nv, int 
       r.nx = e.vx; r.ny = e.vy;
       r.vtx = i;
       gens[g] = r;
+      vtx2gid[i] = g;
       gen_kind[g] = SPM_GEN_VERTEX;
       gen_xy[4 * g] = gen_xy[4 * g + 2] = e.wx / 2;
       gen_xy[4 * g + 1] = gen_xy[4 * g + 3] = e.wy / 2;
@@ -135,7 +137,7 @@ __global__ __launch_bounds__(1024) void k_gen_table(int np, int ns, int nv, int 
 __global__ __launch_bounds__(256) void k_edge_rank(int E, const u64* __restrict__ keys,
                                                    const EdgeRec* __restrict__ edges_raw,
                                                    const EdgeExt* __restrict__ ext_raw, EdgeRec* __restrict__ edges,
-                                                   EdgeExt* __restrict__ ext) {
+                                                   EdgeExt* __restrict__ ext, int* __restrict__ vsorted) {
   const int w = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
   if (w >= E) return;
   const int lane = lane_id();
@@ -148,6 +150,41 @@ __global__ __launch_bounds__(256) void k_edge_rank(int E, const u64* __restrict_
   if (lane == 0) {
     edges[cnt] = edges_raw[w];
     ext[cnt] = ext_raw[w];
+    vsorted[cnt] = w;
+  }
+}
+
+// Single workgroup: the spatial generator order used by the generator graph
+// kernels.  Sources keep their ids as positions; then come the convex corners
+// in the Morton order of their outgoing edges.
+__global__ __launch_bounds__(1024) void k_gorder(int nsrc, int E, const int* __restrict__ vsorted,
+                                                 const int* __restrict__ convex, const int* __restrict__ vtx2gid,
+                                                 int* __restrict__ gorder) {
+  __shared__ int wave_tot[16];
+  __shared__ int running;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  for (int g = tid; g < nsrc; g += blockDim.x) gorder[g] = g;
+  if (tid == 0) running = nsrc;
+  __syncthreads();
+  for (int base = 0; base < E; base += blockDim.x) {
+    const int s = base + tid;
+    int vi = -1;
+    if (s < E) vi = vsorted[s];
+    const bool f = vi >= 0 && convex[vi];
+    const u64 m = ballot(f);
+    const int before = __popcll(m & ((1ull << lane) - 1ull));
+    if (lane == 0) wave_tot[wv] = __popcll(m);
+    __syncthreads();
+    int off = running;
+    for (int k = 0; k < wv; ++k) off += wave_tot[k];
+    if (f) gorder[off + before] = vtx2gid[vi];
+    __syncthreads();
+    if (tid == 0) {
+      int t = 0;
+      for (int k = 0; k < (int)(blockDim.x >> 6); ++k) t += wave_tot[k];
+      running += t;
+    }
+    __syncthreads();
   }
 }
 
@@ -239,14 +276,20 @@ hipError_t launch_ingest(const Dev& d, hipStream_t s) {
                        d.vx, d.vy, d.edges_raw, d.ext_raw, d.convex, d.keys);
   }
   hipLaunchKernelGGL(k_gen_table, dim3(1), dim3(1024), 0, s, d.np, d.ns, d.nv, d.n_polys, d.pts, d.segs,
-                     d.edges_raw, d.ext_raw, d.convex, d.gens, d.misc, d.n_gen, d.gen_kind, d.gen_xy);
+                     d.edges_raw, d.ext_raw, d.convex, d.gens, d.misc, d.n_gen, d.gen_kind, d.gen_xy, d.vtx2gid);
   return hipGetLastError();
 }
 
 hipError_t launch_edge_sort(const Dev& d, hipStream_t s) {
-  if (d.E == 0) return hipSuccess;
+  if (d.E == 0) {
+    hipLaunchKernelGGL(k_gorder, dim3(1), dim3(1024), 0, s, d.np + d.ns, 0, d.vsorted, d.convex, d.vtx2gid,
+                       d.gorder);
+    return hipGetLastError();
+  }
   hipLaunchKernelGGL(k_edge_rank, dim3((d.E + 3) / 4), dim3(256), 0, s, d.E, d.keys, d.edges_raw, d.ext_raw,
-                     d.edges, d.ext);
+                     d.edges, d.ext, d.vsorted);
+  hipLaunchKernelGGL(k_gorder, dim3(1), dim3(1024), 0, s, d.np + d.ns, d.E, d.vsorted, d.convex, d.vtx2gid,
+                     d.gorder);
   hipLaunchKernelGGL(k_chunk_boxes, dim3((d.NC + 127) / 128), dim3(128), 0, s, d.E, d.NC, d.edges, d.chunks);
   return hipGetLastError();
 }

@@ -327,7 +327,12 @@ int spm_build_ex(const spm_scene* s, const spm_out* out, void* d_ws, size_t ws_b
   d.sgbb = (int4*)(ws + L.off_sgbb);
   d.inside = (unsigned*)(ws + L.off_inside);
   d.cost64 = (double*)(ws + L.off_cost64);
+  d.gxy = (int4*)(ws + L.off_gxy);
   d.misc = (int*)(ws + L.off_misc);
+  d.vsorted = (int*)(ws + L.off_vsorted);
+  d.vtx2gid = (int*)(ws + L.off_vtx2gid);
+  d.gorder = (int*)(ws + L.off_gorder);
+  d.costpos = (u64*)(ws + L.off_costpos);
   d.dist = out->dist; d.parent = out->parent; d.gen_kind = out->gen_kind; d.gen_xy = out->gen_xy;
   d.gen_cost = out->gen_cost; d.gen_parent = out->gen_parent; d.n_gen = out->n_gen;
   d.tile_w = tw; d.tile_h = 64 / tw;

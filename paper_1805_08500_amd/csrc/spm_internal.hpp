@@ -22,7 +22,6 @@ typedef unsigned long long u64;
 constexpr int kWave = 64;
 constexpr int kChunk = 64;        // edges per spatial chunk
 constexpr int kRelaxThreads = 1024;
-constexpr int kRelaxLdsMaxGen = 7680;   // keeps the relaxation LDS (costs + change masks) under 64 KB
 
 // One obstacle edge w -> v (obstacle on the left), with its line function
 // E(x, y) = a x + b y + c, positive on the obstacle side.
@@ -55,7 +54,8 @@ struct Layout {
   int W, H, nv, np, ns, np_polys;
   int E, NC, Gmax, RW, W32;
   size_t off_edges_raw, off_ext_raw, off_keys, off_edges, off_ext, off_chunks, off_convex;
-  size_t off_gens, off_vis, off_sgen, off_sgcost, off_sgbb, off_inside, off_cost64, off_misc;
+  size_t off_gens, off_vis, off_sgen, off_sgcost, off_sgbb, off_inside, off_cost64, off_gxy, off_misc;
+  size_t off_vsorted, off_vtx2gid, off_gorder, off_costpos;
   size_t total;
 };
 
@@ -87,7 +87,12 @@ inline Layout make_layout(int W, int H, int n_polys, int nv, int np, int ns) {
   L.off_sgbb = take(G1 * 16);
   L.off_inside = take((size_t)H * L.W32 * sizeof(unsigned));
   L.off_cost64 = take(G1 * sizeof(double));
+  L.off_gxy = take(G1 * 16);
   L.off_misc = take(MISC_N * sizeof(int));
+  L.off_vsorted = take(E1 * sizeof(int));
+  L.off_vtx2gid = take(E1 * sizeof(int));
+  L.off_gorder = take(G1 * sizeof(int));
+  L.off_costpos = take(G1 * sizeof(u64));
   L.total = o;
   return L;
 }
@@ -117,7 +122,12 @@ struct Dev {
   int4* sgbb;
   unsigned* inside;
   double* cost64;
+  int4* gxy;
   int* misc;
+  int* vsorted;   // vertex index at each Morton-sorted edge position
+  int* vtx2gid;   // generator id of each convex vertex
+  int* gorder;    // generator id at each spatial position (sources first)
+  u64* costpos;   // relaxation costs by spatial position (IEEE bits) when they do not fit in LDS
   // outputs
   float* dist;
   int* parent;
@@ -270,6 +280,25 @@ __device__ __forceinline__ bool lane_visible_rational(const Geo& d, int px, int 
   return !blocked;
 }
 
+// Culled chunks of one 64-chunk batch, split into three classes by the gap
+// between the chunk box and the lanes' box (doubled units): touching or within
+// 64, within 256, farther.  Walking the near classes first finds the nearby
+// occluders -- which usually decide visibility -- before the far ones.
+__device__ __forceinline__ void chunk_classes(const int4* chunks, int NC, int cb, int cx0, int cy0, int cx1, int cy1,
+                                              int bx0, int by0, int bx1, int by1, u64 cls[3]) {
+  const int ci = cb + lane_id();
+  bool hit = false;
+  int gap = 0;
+  if (ci < NC) {
+    const int4 bb = chunks[ci];
+    hit = bb.x <= cx1 && bb.z >= cx0 && bb.y <= cy1 && bb.w >= cy0;
+    gap = max(max(max(bb.x - bx1, bx0 - bb.z), max(bb.y - by1, by0 - bb.w)), 0);
+  }
+  cls[0] = ballot(hit && gap <= 64);
+  cls[1] = ballot(hit && gap <= 256) & ~cls[0];
+  cls[2] = ballot(hit) & ~cls[0] & ~cls[1];
+}
+
 // Wave-level visibility between per-lane integer points P (lanes in `need`)
 // and one wave-uniform integer point g.  (bx0..by1) is a box containing every
 // needed P.  Returns the mask of needed lanes whose closed segment [P, g]
@@ -308,13 +337,10 @@ __device__ __forceinline__ u64 wave_blocked_uniform(const Geo& d, int px, int py
   const int cx0 = min(bx0, gx), cy0 = min(by0, gy), cx1 = max(bx1, gx), cy1 = max(by1, gy);
   const int rx0 = bx0 - gx, rx1 = bx1 - gx, ry0 = by0 - gy, ry1 = by1 - gy;
   for (int cb = 0; cb < d.NC; cb += kWave) {
-    int ci = cb + lane;
-    bool hit = false;
-    if (ci < d.NC) {
-      int4 bb = d.chunks[ci];
-      hit = bb.x <= cx1 && bb.z >= cx0 && bb.y <= cy1 && bb.w >= cy0;
-    }
-    u64 cm = ballot(hit);
+    u64 cls[3];
+    chunk_classes(d.chunks, d.NC, cb, cx0, cy0, cx1, cy1, bx0, by0, bx1, by1, cls);
+    for (int cl = 0; cl < 3; ++cl) {
+    u64 cm = cls[cl];
     while (cm) {
       const int chunk = cb + first_bit(cm);
       cm &= cm - 1;
@@ -360,6 +386,7 @@ __device__ __forceinline__ u64 wave_blocked_uniform(const Geo& d, int px, int py
       }
       blocked = ballot(blk) & need;
       if (blocked == need) return need;
+    }
     }
   }
   // exact vertex rule for lanes with an endpoint exactly on their line P-g
@@ -429,13 +456,10 @@ __device__ __forceinline__ u64 wave_blocked_perp(const Geo& d, int px, int py, u
   bool blk = false, dg = false;
   u64 blocked = 0;
   for (int cb = 0; cb < d.NC; cb += kWave) {
-    int ci = cb + lane;
-    bool hit = false;
-    if (ci < d.NC) {
-      int4 bb = d.chunks[ci];
-      hit = bb.x <= cx1 && bb.z >= cx0 && bb.y <= cy1 && bb.w >= cy0;
-    }
-    u64 cm = ballot(hit);
+    u64 cls[3];
+    chunk_classes(d.chunks, d.NC, cb, cx0, cy0, cx1, cy1, bx0, by0, bx1, by1, cls);
+    for (int cl = 0; cl < 3; ++cl) {
+    u64 cm = cls[cl];
     while (cm) {
       const int chunk = cb + first_bit(cm);
       cm &= cm - 1;
@@ -488,6 +512,7 @@ __device__ __forceinline__ u64 wave_blocked_perp(const Geo& d, int px, int py, u
       }
       blocked = ballot(blk) & need;
       if (blocked == need) return need;
+    }
     }
   }
   u64 slow = ballot(dg) & need & ~blocked;
