@@ -134,6 +134,43 @@ typedef struct {
 int spm_build_ex(const spm_scene* dev_scene, const spm_out* out, void* d_ws, size_t ws_bytes, void* stream,
                  const spm_build_opts* opts);
 
+/* ---------------------------------------------------------------------
+ * Batched builds.  Many independent scenes are built by one launch per
+ * stage; the pixel stage is a single persistent launch whose workgroups take
+ * (scene, slice of tiles) items from a device queue.  The paper motivates
+ * cheap rebuilds of many maps for dynamic scenes (Section 1); this batches
+ * them.  Each scene follows the conventions above and gets its own outputs.
+ * ------------------------------------------------------------------- */
+typedef struct {
+  int32_t n;                /* number of scenes, >= 1 */
+  const spm_scene* scenes;  /* [n] device-memory scenes (counts are host values) */
+  const spm_out* outs;      /* [n] outputs, sized by spm_query_sizes per scene */
+  const int32_t* tile_w;    /* [n] tile width per scene: 8 (8x8), 16 (16x4) or 4 (4x16); NULL = all 8 */
+} spm_batch;
+
+/* Device workspace bytes for a batch (host arithmetic only). */
+int spm_batch_query_sizes(const spm_batch* b, size_t* workspace_bytes);
+
+/* Writes the batch's per-scene descriptors into d_ws with a synchronous
+ * host-to-device copy.  Must be called (outside any stream capture) before
+ * spm_build_batch, and again whenever any pointer, count or tile width of
+ * the batch changes; the scene contents may change freely in between. */
+int spm_batch_prepare(const spm_batch* b, void* d_ws, size_t ws_bytes);
+
+/* Queues the batched build on `stream` (kernels only: no allocation, no host
+ * synchronisation, no copies), so it can be captured in a HIP graph.  b must
+ * describe the same batch as the last spm_batch_prepare on d_ws.  timer may
+ * be NULL (see spm_timer_elapsed for the stage order). */
+int spm_build_batch(const spm_batch* b, void* d_ws, size_t ws_bytes, void* stream, spm_timer* timer);
+
+/* A batched build captured in a HIP graph on a non-null `stream`; replay with
+ * spm_graph_launch on any stream.  The graph keeps the batch's pointers: the
+ * buffers must outlive it. */
+typedef struct spm_graph spm_graph;
+int spm_graph_capture_batch(const spm_batch* b, void* d_ws, size_t ws_bytes, void* stream, spm_graph** g);
+int spm_graph_launch(spm_graph* g, void* stream);
+int spm_graph_destroy(spm_graph* g);
+
 /* Host copy of a built map for path queries. */
 typedef struct {
   int32_t width, height;

@@ -3,7 +3,9 @@ Path Maps with GPU Shaders"): a HIP library behind a C ABI (include/spm.h)
 and a thin PyTorch-facing binding."""
 from . import _lib  # noqa: F401
 from .spm import (  # noqa: F401
+    BatchBuilder,
     Builder,
+    Graph,
     DeviceScene,
     Map,
     Timer,

@@ -43,6 +43,11 @@ class SpmBuildOpts(ctypes.Structure):
     _fields_ = [("tile_w", c_i32), ("tile_h", c_i32), ("timer", c_vp), ("d_stats", c_vp)]
 
 
+class SpmBatch(ctypes.Structure):
+    _fields_ = [("n", c_i32), ("scenes", ctypes.POINTER(SpmScene)), ("outs", ctypes.POINTER(SpmOut)),
+                ("tile_w", ctypes.POINTER(c_i32))]
+
+
 class SpmMapHost(ctypes.Structure):
     _fields_ = [("width", c_i32), ("height", c_i32), ("parent", c_vp), ("n_gen", c_i32), ("gen_kind", c_vp),
                 ("gen_xy", c_vp), ("gen_parent", c_vp), ("gen_cost", c_vp)]
@@ -74,8 +79,17 @@ def lib():
     L.spm_timer_elapsed.argtypes = [c_vp, P(ctypes.c_float), P(c_i32)]
     L.spm_query_path.argtypes = [P(SpmMapHost), ctypes.c_float, ctypes.c_float, P(ctypes.c_float), c_i32,
                                  P(c_i32), P(ctypes.c_float)]
+    bp = P(SpmBatch)
+    L.spm_batch_query_sizes.argtypes = [bp, P(ctypes.c_size_t)]
+    L.spm_batch_prepare.argtypes = [bp, c_vp, ctypes.c_size_t]
+    L.spm_build_batch.argtypes = [bp, c_vp, ctypes.c_size_t, c_vp, c_vp]
+    L.spm_graph_capture_batch.argtypes = [bp, c_vp, ctypes.c_size_t, c_vp, P(c_vp)]
+    L.spm_graph_launch.argtypes = [c_vp, c_vp]
+    L.spm_graph_destroy.argtypes = [c_vp]
     for name in ("spm_validate", "spm_query_sizes", "spm_build", "spm_build_ex", "spm_timer_create",
-                 "spm_timer_destroy", "spm_timer_reset", "spm_timer_elapsed", "spm_query_path"):
+                 "spm_timer_destroy", "spm_timer_reset", "spm_timer_elapsed", "spm_query_path",
+                 "spm_batch_query_sizes", "spm_batch_prepare", "spm_build_batch", "spm_graph_capture_batch",
+                 "spm_graph_launch", "spm_graph_destroy"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L

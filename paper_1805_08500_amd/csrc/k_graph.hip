@@ -3,7 +3,8 @@
 // The paper expands generators one at a time in cost order (Procedure 1),
 // shades their cones and relaxes every visible DataArray entry (Procedure 4),
 // which is Dijkstra's algorithm on the visibility graph of the generators.
-// Here the same costs come from three kernels:
+// Here the same costs come from three kernels (templates over the scene
+// source, like the ingest kernels):
 //   k_genvis   every (corner, generator) arc of the visibility graph, as a
 //              bit matrix (one wavefront per 64 arcs, exact predicates);
 //   k_relax    a single-workgroup Bellman-Ford over that matrix in double
@@ -44,39 +45,40 @@ __device__ __forceinline__ double arc_len(const GenRec& u, int vx, int vy) {
 // for a segment source, v sees the segment's closest point to v).  Rows and
 // bits are indexed by spatial position (gorder), so the 64 generators of a
 // wavefront are neighbours in space and share few relevant edges.  LDSE: the
-// edges and chunk boxes are staged in LDS first.
-template <bool LDSE>
-__global__ __launch_bounds__(256) void k_genvis(int Gmax, int RW, int nsrc, const int* __restrict__ misc,
-                                                const GenRec* __restrict__ gens, const int* __restrict__ gorder,
-                                                const EdgeRec* __restrict__ edges,
-                                                const EdgeExt* __restrict__ ext,
-                                                const int4* __restrict__ chunks, int E, int NC,
-                                                u64* __restrict__ vis) {
+// edges and chunk boxes are staged in LDS first.  Workgroups never straddle
+// scenes (each scene's wavefronts are padded to whole workgroups).
+template <class S, bool LDSE>
+__global__ __launch_bounds__(256) void k_genvis(S src) {
+  int sc, blk4;
+  if (!src.locate(STG_GVBLK, blockIdx.x, sc, blk4)) return;
+  const Dev& d = src.scene(sc);
   extern __shared__ int4 smem[];
-  Geo geo{edges, ext, chunks, E, NC};
+  const int E = d.E, NC = d.NC, RW = d.RW;
+  Geo geo{d.edges, d.ext, d.chunks, E, NC};
   if (LDSE) {
     EdgeRec* s_edges = (EdgeRec*)smem;
     int4* s_chunks = (int4*)(s_edges + E);
-    const int4* se = (const int4*)edges;
+    const int4* se = (const int4*)d.edges;
     for (int k = threadIdx.x; k < E * 2; k += blockDim.x) ((int4*)s_edges)[k] = se[k];
-    for (int k = threadIdx.x; k < NC; k += blockDim.x) s_chunks[k] = chunks[k];
+    for (int k = threadIdx.x; k < NC; k += blockDim.x) s_chunks[k] = d.chunks[k];
     __syncthreads();
     geo.edges = s_edges;
     geo.chunks = s_chunks;
   }
-  const int wid = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  const int wid = blk4 * 4 + (threadIdx.x >> 6);
   const int r = wid / RW, blk = wid - r * RW;
-  const int G = uni(misc[MISC_G]);
+  const int G = uni(d.misc[MISC_G]);
+  const int nsrc = d.np + d.ns;
   if (r >= G || r < nsrc) return;  // only corner rows are read
   const int lane = lane_id();
-  const int v = uni(gorder[r]);
-  const int gx = uni(gens[v].x), gy = uni(gens[v].y);
-  const int gux = uni(gens[v].ux), guy = uni(gens[v].uy), gnx = uni(gens[v].nx), gny = uni(gens[v].ny);
+  const int v = uni(d.gorder[r]);
+  const int gx = uni(d.gens[v].x), gy = uni(d.gens[v].y);
+  const int gux = uni(d.gens[v].ux), guy = uni(d.gens[v].uy), gnx = uni(d.gens[v].nx), gny = uni(d.gens[v].ny);
   const int upos = blk * 64 + lane;
-  const int u = upos < G ? gorder[upos] : -1;
+  const int u = upos < G ? d.gorder[upos] : -1;
   const bool valid = u >= 0 && u != v;
   GenRec gu = {};
-  if (valid) gu = gens[u];
+  if (valid) gu = d.gens[u];
   const bool fast = valid && gu.kind != SPM_GEN_SEGMENT;
   const bool seg = valid && gu.kind == SPM_GEN_SEGMENT;
   bool ok = false;
@@ -102,7 +104,7 @@ __global__ __launch_bounds__(256) void k_genvis(int Gmax, int RW, int nsrc, cons
     if (seg) ok = vs;
   }
   const u64 bits = ballot(ok);
-  if (lane == 0) vis[(size_t)r * RW + blk] = bits;
+  if (lane == 0) d.vis[(size_t)r * RW + blk] = bits;
 }
 
 // Arc weight from a generator with doubled coordinates (x, y, x2, y2) --
@@ -116,9 +118,10 @@ __device__ __forceinline__ double arc_len4(int4 u, int vx, int vy) {
 
 constexpr int kRelaxFront = 2048;   // largest frontier kept as a list (push rounds)
 
-// Single workgroup Bellman-Ford over the arc matrix, iterated to its fixed
-// point (the costs Dijkstra reaches).  Sources start at 0.  Each round relaxes
-// the arcs leaving the generators whose cost changed in the previous round:
+// One workgroup per scene: Bellman-Ford over the arc matrix, iterated to its
+// fixed point (the costs Dijkstra reaches).  Sources start at 0.  Each round
+// relaxes the arcs leaving the generators whose cost changed in the previous
+// round:
 //   pull  (large frontier): every corner v scans row v restricted to the
 //         frontier and keeps the best candidate;
 //   push  (small frontier, corners only): for each frontier corner u, every
@@ -127,32 +130,36 @@ constexpr int kRelaxFront = 2048;   // largest frontier kept as a list (push rou
 //         non-negative doubles, which order like the values.
 // Positive arc weights make the double-precision fixed point unique, so the
 // result does not depend on thread timing or on the pull/push schedule.
-// LDS: costs, generator coordinates, change masks and the frontier list live
-// in LDS when they fit, else in global memory.
-template <bool LDS>
-__global__ __launch_bounds__(1024) void k_relax(int Gmax, int RW, int nsrc, const GenRec* __restrict__ gens,
-                                                const int* __restrict__ gorder, const u64* __restrict__ vis,
-                                                u64* __restrict__ cost_pos_g, u64* __restrict__ cost_out,
-                                                int4* __restrict__ gxy_g, int* misc, double* __restrict__ gen_cost,
-                                                int* __restrict__ gen_parent) {
+// LDS: costs, generator coordinates and change masks live in LDS when they
+// fit, else in global memory.  Everything is indexed by spatial position;
+// outputs go back to canonical ids.
+template <class S, bool LDS>
+__global__ __launch_bounds__(1024) void k_relax(S src, int Gcap, int RWcap) {
+  int sc, one;
+  if (!src.locate(STG_SCENE, blockIdx.x, sc, one)) return;
+  const Dev& d = src.scene(sc);
   extern __shared__ u64 shm[];
   __shared__ int any, nfront, reached;
   __shared__ int front[kRelaxFront];
+  const int RW = d.RW;
+  const u64* __restrict__ vis = d.vis;
+  const int* __restrict__ gorder = d.gorder;
   u64* chg_a = shm;
-  u64* chg_b = shm + RW;
-  u64* cost = LDS ? (shm + 2 * RW) : cost_pos_g;   // indexed by spatial position
-  int4* gxy = LDS ? (int4*)(shm + 2 * RW + Gmax) : gxy_g;
+  u64* chg_b = shm + RWcap;
+  u64* cost = LDS ? (shm + 2 * RWcap) : d.costpos;   // indexed by spatial position
+  int4* gxy = LDS ? (int4*)(shm + 2 * RWcap + Gcap) : d.gxy;
   const int tid = threadIdx.x, nt = blockDim.x;
-  const int G = misc[MISC_G];
+  const int G = d.misc[MISC_G];
+  const int nsrc = d.np + d.ns;
   for (int k = tid; k < RW; k += nt) { chg_a[k] = 0; chg_b[k] = 0; }
   if (tid == 0) { reached = 0; nfront = -1; }
   __syncthreads();
   for (int g = tid; g < G; g += nt) {
-    const GenRec r = gens[gorder[g]];
-    const bool src = g < nsrc;
-    cost[g] = (u64)__double_as_longlong(src ? 0.0 : INFINITY);
+    const GenRec r = d.gens[gorder[g]];
+    const bool srcg = g < nsrc;
+    cost[g] = (u64)__double_as_longlong(srcg ? 0.0 : INFINITY);
     gxy[g] = make_int4(r.x, r.y, r.x2, r.y2);
-    if (src) atomicOr(&chg_a[g >> 6], 1ull << (g & 63));
+    if (srcg) atomicOr(&chg_a[g >> 6], 1ull << (g & 63));
   }
   __syncthreads();
   u64* cur = chg_a;
@@ -164,8 +171,8 @@ __global__ __launch_bounds__(1024) void k_relax(int Gmax, int RW, int nsrc, cons
     __syncthreads();
     if (nf < 0) {
       for (int v = tid; v < G; v += nt) {
+        if (v < nsrc) continue;  // sources keep cost 0
         const int4 pv = gxy[v];
-        if (v < nsrc) continue;  // sources (ids below nsrc) keep cost 0
         const double old = __longlong_as_double((long long)cost[v]);
         double best = old;
         const u64* row = vis + (size_t)v * RW;
@@ -262,61 +269,47 @@ __global__ __launch_bounds__(1024) void k_relax(int Gmax, int RW, int nsrc, cons
         }
       }
     }
-    gen_cost[v] = c;
-    gen_parent[v] = par;
-    cost_out[v] = (u64)__double_as_longlong(c);
+    d.gen_cost[v] = c;
+    d.gen_parent[v] = par;
+    d.cost64[v] = c;
     if (c < INFINITY) ++mine;
   }
   atomicAdd(&reached, mine);
   __syncthreads();
   if (tid == 0) {
-    misc[MISC_REACHED] = reached;
-    misc[MISC_ROUNDS] = rounds;
+    d.misc[MISC_REACHED] = reached;
+    d.misc[MISC_ROUNDS] = rounds;
   }
 }
 
 // One wavefront per generator: rank by (float cost, id) among all generators;
 // unreached ones (+inf) rank last and are not copied.
-__global__ __launch_bounds__(256) void k_gsort(int* misc, const GenRec* __restrict__ gens,
-                                               const double* __restrict__ cost64, GenRec* __restrict__ sgen,
-                                               float* __restrict__ sgcost, int4* __restrict__ sgbb) {
-  const int g = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-  const int G = uni(misc[MISC_G]);
-  if (g == 0 && threadIdx.x == 0) misc[MISC_TILE_CTR] = 0;  // tile queue of the pixel stage
+template <class S>
+__global__ __launch_bounds__(256) void k_gsort(S src) {
+  int sc, g;
+  if (!src.locate(STG_GEN, blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6), sc, g)) return;
+  const Dev& d = src.scene(sc);
+  const int G = uni(d.misc[MISC_G]);
   if (g >= G) return;
   const int lane = lane_id();
-  const float cf = (float)cost64[g];
+  const float cf = (float)d.cost64[g];
   const u64 key = ((u64)__float_as_uint(cf) << 32) | (u64)(unsigned)g;
   int rank = 0;
   for (int h = lane; h - lane < G; h += 64) {
     bool lt = false;
     if (h < G) {
-      const float ch = (float)cost64[h];
+      const float ch = (float)d.cost64[h];
       lt = (((u64)__float_as_uint(ch) << 32) | (u64)(unsigned)h) < key;
     }
     rank += __popcll(ballot(lt));
   }
   if (lane == 0 && cf < INFINITY) {
-    GenRec r = gens[g];
+    GenRec r = d.gens[g];
     r.costf = cf;
-    sgen[rank] = r;
-    sgcost[rank] = cf;
-    sgbb[rank] = make_int4(min(r.x, r.x2), min(r.y, r.y2), max(r.x, r.x2), max(r.y, r.y2));
+    d.sgen[rank] = r;
+    d.sgcost[rank] = cf;
+    d.sgbb[rank] = make_int4(min(r.x, r.x2), min(r.y, r.y2), max(r.x, r.x2), max(r.y, r.y2));
   }
-}
-
-hipError_t launch_genvis(const Dev& d, hipStream_t s) {
-  if (d.Gmax == 0) return hipSuccess;
-  const long long waves = (long long)d.Gmax * d.RW;
-  const dim3 grid((unsigned)((waves + 3) / 4));
-  const size_t shm = (size_t)d.E * sizeof(EdgeRec) + (size_t)d.NC * 16;
-  if (shm <= 32768)
-    hipLaunchKernelGGL(k_genvis<true>, grid, dim3(256), shm, s, d.Gmax, d.RW, d.np + d.ns, d.misc, d.gens,
-                       d.gorder, d.edges, d.ext, d.chunks, d.E, d.NC, d.vis);
-  else
-    hipLaunchKernelGGL(k_genvis<false>, grid, dim3(256), 0, s, d.Gmax, d.RW, d.np + d.ns, d.misc, d.gens,
-                       d.gorder, d.edges, d.ext, d.chunks, d.E, d.NC, d.vis);
-  return hipGetLastError();
 }
 
 static int max_lds_per_block() {
@@ -331,32 +324,50 @@ static int max_lds_per_block() {
   return cached[dev];
 }
 
-hipError_t launch_relax(const Dev& d, hipStream_t s) {
-  const size_t chg = 2 * (size_t)(d.RW > 0 ? d.RW : 1) * sizeof(u64);
-  const size_t G1 = (size_t)(d.Gmax > 0 ? d.Gmax : 1);
-  const size_t shm = chg + G1 * (sizeof(u64) + sizeof(int4));
+template <class S>
+hipError_t launch_genvis(const S& src, const Plan& p, hipStream_t s) {
+  if (p.total[STG_GVBLK] <= 0) return hipSuccess;
+  const dim3 grid((unsigned)p.total[STG_GVBLK]);
+  if (p.genvis_lds > 0 && p.genvis_lds <= 32768)
+    hipLaunchKernelGGL((k_genvis<S, true>), grid, dim3(256), p.genvis_lds, s, src);
+  else
+    hipLaunchKernelGGL((k_genvis<S, false>), grid, dim3(256), 0, s, src);
+  return hipGetLastError();
+}
+
+template <class S>
+hipError_t launch_relax(const S& src, const Plan& p, hipStream_t s) {
+  const int RWcap = p.maxRW > 0 ? p.maxRW : 1;
+  const int Gcap = p.maxGmax > 0 ? p.maxGmax : 1;
+  const size_t chg = 2 * (size_t)RWcap * sizeof(u64);
+  const size_t shm = chg + (size_t)Gcap * (sizeof(u64) + sizeof(int4));
   const size_t static_lds = 4 * 3 + kRelaxFront * 4 + 64;
-  u64* cost_bits = (u64*)d.cost64;   // the same 8-byte slots, as IEEE bit patterns
+  const dim3 grid((unsigned)p.total[STG_SCENE]);
   if (shm + static_lds <= (size_t)max_lds_per_block()) {
     if (shm > 65536) {
-      hipError_t e = hipFuncSetAttribute((const void*)k_relax<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+      hipError_t e = hipFuncSetAttribute((const void*)k_relax<S, true>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                          (int)shm);
       if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(k_relax<true>, dim3(1), dim3(kRelaxThreads), shm, s, d.Gmax, d.RW, d.np + d.ns, d.gens,
-                       d.gorder, d.vis, d.costpos, cost_bits, d.gxy, d.misc, d.gen_cost, d.gen_parent);
+    hipLaunchKernelGGL((k_relax<S, true>), grid, dim3(kRelaxThreads), shm, s, src, Gcap, RWcap);
   } else {
-    hipLaunchKernelGGL(k_relax<false>, dim3(1), dim3(kRelaxThreads), chg, s, d.Gmax, d.RW, d.np + d.ns, d.gens,
-                       d.gorder, d.vis, d.costpos, cost_bits, d.gxy, d.misc, d.gen_cost, d.gen_parent);
+    hipLaunchKernelGGL((k_relax<S, false>), grid, dim3(kRelaxThreads), chg, s, src, Gcap, RWcap);
   }
   return hipGetLastError();
 }
 
-hipError_t launch_gsort(const Dev& d, hipStream_t s) {
-  if (d.Gmax == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_gsort, dim3((d.Gmax + 3) / 4), dim3(256), 0, s, d.misc, d.gens, d.cost64, d.sgen, d.sgcost,
-                     d.sgbb);
+template <class S>
+hipError_t launch_gsort(const S& src, const Plan& p, hipStream_t s) {
+  if (p.total[STG_GEN] <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_gsort<S>, dim3((unsigned)((p.total[STG_GEN] + 3) / 4)), dim3(256), 0, s, src);
   return hipGetLastError();
 }
+
+template hipError_t launch_genvis<SingleSrc>(const SingleSrc&, const Plan&, hipStream_t);
+template hipError_t launch_genvis<BatchSrc>(const BatchSrc&, const Plan&, hipStream_t);
+template hipError_t launch_relax<SingleSrc>(const SingleSrc&, const Plan&, hipStream_t);
+template hipError_t launch_relax<BatchSrc>(const BatchSrc&, const Plan&, hipStream_t);
+template hipError_t launch_gsort<SingleSrc>(const SingleSrc&, const Plan&, hipStream_t);
+template hipError_t launch_gsort<BatchSrc>(const BatchSrc&, const Plan&, hipStream_t);
 
 }  // namespace spm

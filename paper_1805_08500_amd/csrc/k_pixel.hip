@@ -227,7 +227,7 @@ __device__ __forceinline__ void tile_work(int tile, int W, int H, int W32, int G
 constexpr int kPixelThreads = 512;
 constexpr size_t kPixelLdsMax = 64 * 1024;
 
-inline size_t pixel_lds_bytes(int Gmax, int E, int NC) {
+size_t pixel_lds_bytes(int Gmax, int E, int NC) {
   return (size_t)Gmax * (sizeof(GenRec) + 4 + 16) + 16 + (size_t)E * sizeof(EdgeRec) + (size_t)NC * 16;
 }
 
@@ -332,6 +332,99 @@ hipError_t launch_pixel(const Dev& d, hipStream_t s) {
   if (d.tile_w == 16) return launch_tw<16>(d, s);
   if (d.tile_w == 4) return launch_tw<4>(d, s);
   return launch_tw<8>(d, s);
+}
+
+// Batched pixel stage: one persistent launch for every scene of a batch.  A
+// workgroup takes a work item -- kSlice tiles of one scene -- from the batch
+// queue, stages that scene's generator table and edges in LDS when it differs
+// from the scene already staged, and its wavefronts share the slice's tiles
+// through an LDS counter.  Tile shapes may differ between scenes.
+template <bool LDSD>
+__global__ __launch_bounds__(kPixelThreads, 4) void k_pixel_batch(BatchSrc src, int* ctr) {
+  extern __shared__ int4 smem[];
+  __shared__ int item_scene, item_t0, item_t1, staged, next_tile;
+  const int tid = threadIdx.x;
+  if (tid == 0) staged = -1;
+  u64 st[8];
+  for (;;) {
+    if (tid == 0) {
+      const int it = atomicAdd(ctr, 1);
+      int sc, local;
+      if (src.locate(STG_SLICE, it, sc, local)) {
+        const Dev& d0 = src.scene(sc);
+        const int nt = tiles_of(d0.W, d0.H, d0.tile_w);
+        item_scene = sc;
+        item_t0 = local * kSlice;
+        item_t1 = min(nt, item_t0 + kSlice);
+      } else {
+        item_scene = -1;
+      }
+      next_tile = 0;
+    }
+    __syncthreads();
+    const int sc = item_scene;
+    if (sc < 0) break;
+    const Dev& d = src.scene(sc);
+    const int G = d.misc[MISC_REACHED];
+    const GenRec* sgen = d.sgen;
+    const float* sgcost = d.sgcost;
+    const int4* sgbb = d.sgbb;
+    Geo geo{d.edges, d.ext, d.chunks, d.E, d.NC};
+    if (LDSD) {
+      GenRec* s_gen = (GenRec*)smem;
+      int4* s_bb = (int4*)(s_gen + d.Gmax);
+      EdgeRec* s_edges = (EdgeRec*)(s_bb + d.Gmax);
+      int4* s_chunks = (int4*)(s_edges + d.E);
+      float* s_cost = (float*)(s_chunks + d.NC);
+      if (sc != staged) {
+        const int4* gsrc = (const int4*)d.sgen;
+        for (int k = tid; k < G * 4; k += blockDim.x) ((int4*)s_gen)[k] = gsrc[k];
+        for (int k = tid; k < G; k += blockDim.x) { s_bb[k] = d.sgbb[k]; s_cost[k] = d.sgcost[k]; }
+        const int4* se = (const int4*)d.edges;
+        for (int k = tid; k < d.E * 2; k += blockDim.x) ((int4*)s_edges)[k] = se[k];
+        for (int k = tid; k < d.NC; k += blockDim.x) s_chunks[k] = d.chunks[k];
+        __syncthreads();
+        if (tid == 0) staged = sc;
+      }
+      sgen = s_gen;
+      sgcost = s_cost;
+      sgbb = s_bb;
+      geo.edges = s_edges;
+      geo.chunks = s_chunks;
+    }
+    for (;;) {
+      int t = 0;
+      if (lane_id() == 0) t = atomicAdd(&next_tile, 1);
+      t = __shfl(t, 0, 64);
+      const int tile = item_t0 + t;
+      if (tile >= item_t1) break;
+      if (d.tile_w == 16)
+        tile_work<16, false>(tile, d.W, d.H, d.W32, G, d.inside, sgen, sgcost, sgbb, geo, d.dist, d.parent, st);
+      else if (d.tile_w == 4)
+        tile_work<4, false>(tile, d.W, d.H, d.W32, G, d.inside, sgen, sgcost, sgbb, geo, d.dist, d.parent, st);
+      else
+        tile_work<8, false>(tile, d.W, d.H, d.W32, G, d.inside, sgen, sgcost, sgbb, geo, d.dist, d.parent, st);
+    }
+    __syncthreads();
+  }
+}
+
+__global__ void k_reset_counter(int* ctr) { *ctr = 0; }
+
+hipError_t launch_pixel_batch(const BatchSrc& b, const Plan& p, int* ctr, hipStream_t s) {
+  hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(1), 0, s, ctr);
+  const size_t shm = p.pixel_lds;
+  const bool lds = shm > 0 && shm <= kPixelLdsMax;
+  auto kern = lds ? k_pixel_batch<true> : k_pixel_batch<false>;
+  const size_t use = lds ? shm : 0;
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kPixelThreads, use) != hipSuccess || per_cu < 1)
+    per_cu = 1;
+  long long blocks = (long long)device_cus() * per_cu;
+  if (blocks > p.total[STG_SLICE]) blocks = p.total[STG_SLICE];
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(kPixelThreads), use, s, b, ctr);
+  return hipGetLastError();
 }
 
 }  // namespace spm

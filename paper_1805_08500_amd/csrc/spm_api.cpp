@@ -291,25 +291,13 @@ int spm_timer_elapsed(spm_timer* t, float* ms, int32_t* n_builds) {
 }
 
 // ---------------------------------------------------------------- build
-int spm_build_ex(const spm_scene* s, const spm_out* out, void* d_ws, size_t ws_bytes, void* stream,
-                 const spm_build_opts* opts) {
-  int rc = check_counts(s);
-  if (rc) return rc;
-  if ((rc = check_ptrs(s))) return rc;
-  if (!out || !out->dist || !out->parent || !out->gen_kind || !out->gen_xy || !out->gen_cost || !out->gen_parent ||
-      !out->n_gen)
-    return fail(SPM_ERR_INVALID_ARG, "an output pointer is NULL");
-  Layout L = make_layout(s->width, s->height, s->n_polys, s->n_vertices, s->n_points, s->n_segs);
-  if (!d_ws) return fail(SPM_ERR_INVALID_ARG, "workspace is NULL");
-  if (ws_bytes < L.total) return fail(SPM_ERR_CAPACITY, "workspace has %zu bytes, needs %zu", ws_bytes, L.total);
-  int tw = 8;
-  if (opts && opts->tile_w) {
-    tw = opts->tile_w;
-    if (!((tw == 8 && opts->tile_h == 8) || (tw == 16 && opts->tile_h == 4) || (tw == 4 && opts->tile_h == 16)))
-      return fail(SPM_ERR_INVALID_ARG, "unsupported tile %d x %d", opts->tile_w, opts->tile_h);
-  }
-  char* ws = (char*)d_ws;
-  Dev d{};
+}  // extern "C"
+
+namespace {
+
+// Device view of one scene's build: inputs, its sub-workspace and outputs.
+void fill_dev(Dev& d, const spm_scene* s, const spm_out* out, char* ws, const Layout& L, int tw, u64* stats) {
+  d = Dev{};
   d.W = L.W; d.H = L.H; d.nv = L.nv; d.np = L.np; d.ns = L.ns; d.n_polys = s->n_polys;
   d.E = L.E; d.NC = L.NC; d.Gmax = L.Gmax; d.RW = L.RW; d.W32 = L.W32;
   d.poly_start = s->poly_start; d.vx = s->vx; d.vy = s->vy; d.pts = s->pts; d.segs = s->segs;
@@ -336,32 +324,241 @@ int spm_build_ex(const spm_scene* s, const spm_out* out, void* d_ws, size_t ws_b
   d.dist = out->dist; d.parent = out->parent; d.gen_kind = out->gen_kind; d.gen_xy = out->gen_xy;
   d.gen_cost = out->gen_cost; d.gen_parent = out->gen_parent; d.n_gen = out->n_gen;
   d.tile_w = tw; d.tile_h = 64 / tw;
-  d.stats = opts ? (u64*)opts->d_stats : nullptr;
-  hipStream_t st = (hipStream_t)stream;
-  spm_timer* tm = opts ? opts->timer : nullptr;
+  d.stats = stats;
+}
+
+void plan_add(Plan& p, const Dev& d) {
+  for (int k = 0; k < STG_COUNT; ++k) p.total[k] += stage_count(d, k);
+  p.maxGmax = std::max(p.maxGmax, d.Gmax);
+  p.maxRW = std::max(p.maxRW, d.RW);
+  p.maxW = std::max(p.maxW, d.W);
+  p.maxE = std::max(p.maxE, d.E);
+  p.maxNC = std::max(p.maxNC, d.NC);
+  p.pixel_lds = std::max(p.pixel_lds, pixel_lds_bytes(d.Gmax, d.E, d.NC));
+  p.genvis_lds = std::max(p.genvis_lds, (size_t)d.E * sizeof(EdgeRec) + (size_t)d.NC * 16);
+}
+
+int check_out(const spm_out* out) {
+  if (!out || !out->dist || !out->parent || !out->gen_kind || !out->gen_xy || !out->gen_cost || !out->gen_parent ||
+      !out->n_gen)
+    return fail(SPM_ERR_INVALID_ARG, "an output pointer is NULL");
+  return SPM_OK;
+}
+
+int check_tile(int tw, int th) {
+  if (!((tw == 8 && th == 8) || (tw == 16 && th == 4) || (tw == 4 && th == 16)))
+    return fail(SPM_ERR_INVALID_ARG, "unsupported tile %d x %d", tw, th);
+  return SPM_OK;
+}
+
+const char* kStageNames[7] = {"ingest", "edge sort", "inside mask", "generator visibility", "relaxation",
+                              "generator sort", "pixel propagation"};
+
+// queue the seven stages of a build for a scene source; marks timer events
+template <class S, class PixelFn>
+int run_stages(const S& src, const Plan& p, hipStream_t st, spm_timer* tm, PixelFn pixel) {
   hipEvent_t* ev = nullptr;
   if (tm && tm->n < tm->cap) ev = &tm->ev[(size_t)tm->n * SPM_N_STAGES];
   auto mark = [&](int k) -> int {
     if (ev && hipEventRecord(ev[k], st) != hipSuccess) return fail(SPM_ERR_HIP, "hipEventRecord failed");
     return SPM_OK;
   };
-  typedef hipError_t (*Stage)(const Dev&, hipStream_t);
-  static const Stage stages[7] = {launch_ingest, launch_edge_sort, launch_inside, launch_genvis,
-                                  launch_relax,  launch_gsort,     launch_pixel};
-  static const char* names[7] = {"ingest", "edge sort", "inside mask", "generator visibility", "relaxation",
-                                 "generator sort", "pixel propagation"};
+  int rc;
   if ((rc = mark(0))) return rc;
   for (int k = 0; k < 7; ++k) {
-    hipError_t e = stages[k](d, st);
-    if (e != hipSuccess) return fail(SPM_ERR_HIP, "%s launch failed: %s", names[k], hipGetErrorString(e));
+    hipError_t e = hipSuccess;
+    switch (k) {
+      case 0: e = launch_ingest(src, p, st); break;
+      case 1: e = launch_edge_sort(src, p, st); break;
+      case 2: e = launch_inside(src, p, st); break;
+      case 3: e = launch_genvis(src, p, st); break;
+      case 4: e = launch_relax(src, p, st); break;
+      case 5: e = launch_gsort(src, p, st); break;
+      default: e = pixel(); break;
+    }
+    if (e != hipSuccess) return fail(SPM_ERR_HIP, "%s launch failed: %s", kStageNames[k], hipGetErrorString(e));
     if ((rc = mark(k + 1))) return rc;
   }
   if (ev) tm->n++;
+  return SPM_OK;
+}
+
+// batch workspace: [counter][descriptor table][stage offsets][scene workspaces]
+struct BatchLayout {
+  size_t off_ctr, off_tab, off_offs, total;
+  std::vector<size_t> off_scene;
+  std::vector<Layout> L;
+};
+
+int batch_layout(const spm_batch* b, BatchLayout& B) {
+  if (!b || b->n < 1 || !b->scenes || !b->outs) return fail(SPM_ERR_INVALID_ARG, "empty or NULL batch");
+  const int n = b->n;
+  size_t o = 0;
+  auto take = [&](size_t bytes) { size_t r = o; o = align_up(o + (bytes ? bytes : 1), 256); return r; };
+  B.off_ctr = take(256);
+  B.off_tab = take((size_t)n * sizeof(Dev));
+  B.off_offs = take((size_t)STG_COUNT * (n + 1) * sizeof(int));
+  B.off_scene.resize(n);
+  B.L.resize(n);
+  for (int i = 0; i < n; ++i) {
+    int rc = check_counts(&b->scenes[i]);
+    if (rc) return fail(rc, "scene %d: %s", i, g_err.c_str());
+    if ((rc = check_ptrs(&b->scenes[i]))) return fail(rc, "scene %d: %s", i, g_err.c_str());
+    if ((rc = check_out(&b->outs[i]))) return fail(rc, "scene %d: %s", i, g_err.c_str());
+    const int tw = b->tile_w ? b->tile_w[i] : 8;
+    if ((rc = check_tile(tw, tw ? 64 / tw : 0))) return fail(rc, "scene %d: %s", i, g_err.c_str());
+    const spm_scene* s = &b->scenes[i];
+    B.L[i] = make_layout(s->width, s->height, s->n_polys, s->n_vertices, s->n_points, s->n_segs);
+    B.off_scene[i] = take(B.L[i].total);
+  }
+  B.total = o;
+  return SPM_OK;
+}
+
+void batch_devs(const spm_batch* b, const BatchLayout& B, char* ws, std::vector<Dev>& devs, Plan& p) {
+  const int n = b->n;
+  devs.resize(n);
+  p = Plan{};
+  for (int i = 0; i < n; ++i) {
+    const int tw = b->tile_w ? b->tile_w[i] : 8;
+    fill_dev(devs[i], &b->scenes[i], &b->outs[i], ws + B.off_scene[i], B.L[i], tw, nullptr);
+    plan_add(p, devs[i]);
+  }
+}
+
+}  // namespace
+
+struct spm_graph {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+extern "C" {
+
+int spm_build_ex(const spm_scene* s, const spm_out* out, void* d_ws, size_t ws_bytes, void* stream,
+                 const spm_build_opts* opts) {
+  int rc = check_counts(s);
+  if (rc) return rc;
+  if ((rc = check_ptrs(s))) return rc;
+  if ((rc = check_out(out))) return rc;
+  Layout L = make_layout(s->width, s->height, s->n_polys, s->n_vertices, s->n_points, s->n_segs);
+  if (!d_ws) return fail(SPM_ERR_INVALID_ARG, "workspace is NULL");
+  if (ws_bytes < L.total) return fail(SPM_ERR_CAPACITY, "workspace has %zu bytes, needs %zu", ws_bytes, L.total);
+  int tw = 8;
+  if (opts && opts->tile_w) {
+    tw = opts->tile_w;
+    if ((rc = check_tile(opts->tile_w, opts->tile_h))) return rc;
+  }
+  SingleSrc src;
+  fill_dev(src.d, s, out, (char*)d_ws, L, tw, opts ? (u64*)opts->d_stats : nullptr);
+  Plan p{};
+  plan_add(p, src.d);
+  hipStream_t st = (hipStream_t)stream;
+  const Dev& d = src.d;
+  rc = run_stages(src, p, st, opts ? opts->timer : nullptr, [&]() { return launch_pixel(d, st); });
+  if (rc) return rc;
   return ok();
 }
 
 int spm_build(const spm_scene* s, const spm_out* out, void* d_ws, size_t ws_bytes, void* stream) {
   return spm_build_ex(s, out, d_ws, ws_bytes, stream, nullptr);
+}
+
+int spm_batch_query_sizes(const spm_batch* b, size_t* workspace_bytes) {
+  BatchLayout B;
+  int rc = batch_layout(b, B);
+  if (rc) return rc;
+  if (workspace_bytes) *workspace_bytes = B.total;
+  return ok();
+}
+
+int spm_batch_prepare(const spm_batch* b, void* d_ws, size_t ws_bytes) {
+  BatchLayout B;
+  int rc = batch_layout(b, B);
+  if (rc) return rc;
+  if (!d_ws) return fail(SPM_ERR_INVALID_ARG, "workspace is NULL");
+  if (ws_bytes < B.total) return fail(SPM_ERR_CAPACITY, "workspace has %zu bytes, needs %zu", ws_bytes, B.total);
+  char* ws = (char*)d_ws;
+  std::vector<Dev> devs;
+  Plan p;
+  batch_devs(b, B, ws, devs, p);
+  const int n = b->n;
+  std::vector<int> offs((size_t)STG_COUNT * (n + 1), 0);
+  for (int k = 0; k < STG_COUNT; ++k) {
+    long long acc = 0;
+    for (int i = 0; i < n; ++i) {
+      offs[(size_t)k * (n + 1) + i] = (int)acc;
+      acc += stage_count(devs[i], k);
+    }
+    if (acc > 0x7fffffffLL) return fail(SPM_ERR_CAPACITY, "batch too large for 32-bit work offsets");
+    offs[(size_t)k * (n + 1) + n] = (int)acc;
+  }
+  if (hipMemcpy(ws + B.off_tab, devs.data(), (size_t)n * sizeof(Dev), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(ws + B.off_offs, offs.data(), offs.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess)
+    return fail(SPM_ERR_HIP, "descriptor upload failed");
+  return ok();
+}
+
+int spm_build_batch(const spm_batch* b, void* d_ws, size_t ws_bytes, void* stream, spm_timer* timer) {
+  BatchLayout B;
+  int rc = batch_layout(b, B);
+  if (rc) return rc;
+  if (!d_ws) return fail(SPM_ERR_INVALID_ARG, "workspace is NULL");
+  if (ws_bytes < B.total) return fail(SPM_ERR_CAPACITY, "workspace has %zu bytes, needs %zu", ws_bytes, B.total);
+  char* ws = (char*)d_ws;
+  std::vector<Dev> devs;
+  Plan p;
+  batch_devs(b, B, ws, devs, p);
+  BatchSrc src{(const Dev*)(ws + B.off_tab), (const int*)(ws + B.off_offs), b->n};
+  hipStream_t st = (hipStream_t)stream;
+  int* ctr = (int*)(ws + B.off_ctr);
+  rc = run_stages(src, p, st, timer, [&]() { return launch_pixel_batch(src, p, ctr, st); });
+  if (rc) return rc;
+  return ok();
+}
+
+int spm_graph_capture_batch(const spm_batch* b, void* d_ws, size_t ws_bytes, void* stream, spm_graph** out) {
+  if (!out) return fail(SPM_ERR_INVALID_ARG, "graph out pointer is NULL");
+  if (!stream) return fail(SPM_ERR_INVALID_ARG, "capture needs a non-null stream");
+  hipStream_t st = (hipStream_t)stream;
+  if (hipStreamBeginCapture(st, hipStreamCaptureModeRelaxed) != hipSuccess)
+    return fail(SPM_ERR_HIP, "hipStreamBeginCapture failed");
+  const int rc = spm_build_batch(b, d_ws, ws_bytes, stream, nullptr);
+  const std::string msg = g_err;
+  hipGraph_t graph = nullptr;
+  const hipError_t e = hipStreamEndCapture(st, &graph);
+  if (rc) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return fail(rc, "%s", msg.c_str());
+  }
+  if (e != hipSuccess || !graph) return fail(SPM_ERR_HIP, "hipStreamEndCapture failed");
+  spm_graph* g = new (std::nothrow) spm_graph();
+  if (!g) {
+    (void)hipGraphDestroy(graph);
+    return fail(SPM_ERR_INVALID_ARG, "out of host memory");
+  }
+  g->graph = graph;
+  if (hipGraphInstantiate(&g->exec, graph, nullptr, nullptr, 0) != hipSuccess) {
+    (void)hipGraphDestroy(graph);
+    delete g;
+    return fail(SPM_ERR_HIP, "hipGraphInstantiate failed");
+  }
+  *out = g;
+  return ok();
+}
+
+int spm_graph_launch(spm_graph* g, void* stream) {
+  if (!g || !g->exec) return fail(SPM_ERR_INVALID_ARG, "graph is NULL");
+  if (hipGraphLaunch(g->exec, (hipStream_t)stream) != hipSuccess) return fail(SPM_ERR_HIP, "hipGraphLaunch failed");
+  return ok();
+}
+
+int spm_graph_destroy(spm_graph* g) {
+  if (!g) return ok();
+  if (g->exec) (void)hipGraphExecDestroy(g->exec);
+  if (g->graph) (void)hipGraphDestroy(g->graph);
+  delete g;
+  return ok();
 }
 
 // ---------------------------------------------------------------- path query

@@ -151,14 +151,94 @@ struct Geo {
   int E, NC;
 };
 
+// ------------------------------------------------------------------------
+// Work decomposition.  Every stage kernel runs over "items" of one kind; a
+// build of one scene and a batch of scenes use the same kernels, with the
+// scene of an item found from per-stage prefix offsets in the batch case.
+// ------------------------------------------------------------------------
+enum StageKind {
+  STG_VTX = 0,   // one thread per obstacle vertex
+  STG_SCENE,     // one workgroup per scene
+  STG_EDGE,      // one wavefront per edge
+  STG_CHUNK,     // one thread per edge chunk
+  STG_ROW,       // one workgroup per pixel row
+  STG_GVBLK,     // one 4-wavefront workgroup per 4 generator-visibility words
+  STG_GEN,       // one wavefront per generator slot
+  STG_SLICE,     // one pixel-tile slice (batched pixel stage)
+  STG_COUNT
+};
+constexpr int kSlice = 64;   // tiles per work item of the batched pixel stage
+
+__host__ __device__ inline int tiles_of(int W, int H, int tw) {
+  const int th = 64 / tw;
+  return ((W + tw - 1) / tw) * ((H + th - 1) / th);
+}
+
+__host__ __device__ inline int stage_count(const Dev& d, int stage) {
+  switch (stage) {
+    case STG_VTX: return d.nv;
+    case STG_SCENE: return 1;
+    case STG_EDGE: return d.E;
+    case STG_CHUNK: return d.NC;
+    case STG_ROW: return d.H;
+    case STG_GVBLK: return (int)(((long long)d.Gmax * d.RW + 3) / 4);
+    case STG_GEN: return d.Gmax;
+    case STG_SLICE: return (tiles_of(d.W, d.H, d.tile_w) + kSlice - 1) / kSlice;
+    default: return 0;
+  }
+}
+
+// One scene, carried by value in the kernel arguments.
+struct SingleSrc {
+  Dev d;
+  __device__ __forceinline__ bool locate(int stage, int idx, int& s, int& local) const {
+    s = 0;
+    local = idx;
+    return idx < stage_count(d, stage);
+  }
+  __device__ __forceinline__ const Dev& scene(int) const { return d; }
+};
+
+// A batch: per-scene descriptors and per-stage prefix offsets in device memory
+// (offs[stage * (n + 1) + s] = first item of scene s).
+struct BatchSrc {
+  const Dev* tab;
+  const int* offs;
+  int n;
+  __device__ __forceinline__ bool locate(int stage, int idx, int& s, int& local) const {
+    const int* o = offs + stage * (n + 1);
+    if (idx < 0 || idx >= o[n]) return false;
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (o[mid] <= idx) lo = mid;
+      else hi = mid - 1;
+    }
+    s = lo;
+    local = idx - o[lo];
+    return true;
+  }
+  __device__ __forceinline__ const Dev& scene(int s) const { return tab[s]; }
+};
+
+// Host-side totals of a build (single scene or batch): items per stage and
+// the largest per-scene sizes that set LDS allocations.
+struct Plan {
+  long long total[STG_COUNT];
+  int maxGmax, maxRW, maxW, maxE, maxNC;
+  size_t pixel_lds, genvis_lds;
+};
+
 // host launchers (each queues kernels on the stream and returns hipError_t)
-hipError_t launch_ingest(const Dev& d, hipStream_t s);
-hipError_t launch_edge_sort(const Dev& d, hipStream_t s);
-hipError_t launch_inside(const Dev& d, hipStream_t s);
-hipError_t launch_genvis(const Dev& d, hipStream_t s);
-hipError_t launch_relax(const Dev& d, hipStream_t s);
-hipError_t launch_gsort(const Dev& d, hipStream_t s);
+template <class S> hipError_t launch_ingest(const S& src, const Plan& p, hipStream_t s);
+template <class S> hipError_t launch_edge_sort(const S& src, const Plan& p, hipStream_t s);
+template <class S> hipError_t launch_inside(const S& src, const Plan& p, hipStream_t s);
+template <class S> hipError_t launch_genvis(const S& src, const Plan& p, hipStream_t s);
+template <class S> hipError_t launch_relax(const S& src, const Plan& p, hipStream_t s);
+template <class S> hipError_t launch_gsort(const S& src, const Plan& p, hipStream_t s);
 hipError_t launch_pixel(const Dev& d, hipStream_t s);
+hipError_t launch_pixel_batch(const BatchSrc& b, const Plan& p, int* batch_ctr, hipStream_t s);
+size_t pixel_lds_bytes(int Gmax, int E, int NC);
 
 #ifdef __HIPCC__
 // ------------------------------------------------------------------------

@@ -148,6 +148,97 @@ class Builder:
         return self.map
 
 
+def _alloc_map(H, W, max_gen, dev) -> Map:
+    G = max(max_gen, 1)
+    return Map(
+        dist=torch.empty((H, W), dtype=torch.float32, device=dev),
+        parent=torch.empty((H, W), dtype=torch.int32, device=dev),
+        gen_kind=torch.empty((G,), dtype=torch.int32, device=dev),
+        gen_xy=torch.empty((G, 4), dtype=torch.int32, device=dev),
+        gen_cost=torch.empty((G,), dtype=torch.float64, device=dev),
+        gen_parent=torch.empty((G,), dtype=torch.int32, device=dev),
+        n_gen=torch.empty((1,), dtype=torch.int32, device=dev),
+    )
+
+
+def _out_struct(m: Map) -> C.SpmOut:
+    return C.SpmOut(m.dist.data_ptr(), m.parent.data_ptr(), m.gen_kind.data_ptr(), m.gen_xy.data_ptr(),
+                    m.gen_cost.data_ptr(), m.gen_parent.data_ptr(), m.n_gen.data_ptr())
+
+
+class Graph:
+    """A batched build captured in a HIP graph (replay with launch())."""
+
+    def __init__(self, handle, owner):
+        self.h = handle
+        self._owner = owner   # keeps the buffers the graph points at alive
+
+    def launch(self, stream=None):
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        C.check(C.lib().spm_graph_launch(self.h, ctypes.c_void_p(stream.cuda_stream)))
+
+    def __del__(self):
+        try:
+            C.lib().spm_graph_destroy(self.h)
+        except Exception:
+            pass
+
+
+class BatchBuilder:
+    """Outputs and workspace for batched builds of many independent scenes.
+
+    tile_w: None (8x8 everywhere), a list of per-scene tile widths (8, 16, 4),
+    or a dict {side: tile_w} such as the one autotune.tune() returns.
+    """
+
+    def __init__(self, scenes, device="cuda", tile_w=None, check: bool = True):
+        self.ds = [DeviceScene(s, device, check=check) for s in scenes]
+        n = len(self.ds)
+        if n < 1:
+            raise ValueError("empty batch")
+        self.maps = []
+        for d in self.ds:
+            mg, _ = d.sizes
+            self.maps.append(_alloc_map(d.height, d.width, mg, d.t["vx"].device))
+        if isinstance(tile_w, dict):
+            tiles = [int(tile_w.get(max(d.width, d.height), tile_w.get(str(max(d.width, d.height)), 8)))
+                     for d in self.ds]
+        elif tile_w is None:
+            tiles = [8] * n
+        else:
+            tiles = [int(t) for t in tile_w]
+        self.tile_w = tiles
+        self._scenes = (C.SpmScene * n)(*[d.c for d in self.ds])
+        self._outs = (C.SpmOut * n)(*[_out_struct(m) for m in self.maps])
+        self._tiles = (C.c_i32 * n)(*tiles)
+        self.c = C.SpmBatch(n, self._scenes, self._outs, self._tiles)
+        ws = ctypes.c_size_t(0)
+        C.check(C.lib().spm_batch_query_sizes(ctypes.byref(self.c), ctypes.byref(ws)))
+        self.ws_bytes = int(ws.value)
+        self.ws = torch.empty((self.ws_bytes,), dtype=torch.uint8, device=self.ds[0].t["vx"].device)
+        C.check(C.lib().spm_batch_prepare(ctypes.byref(self.c), self.ws.data_ptr(), self.ws_bytes))
+
+    def build(self, stream=None, timer: Timer = None):
+        if stream is None:
+            stream = torch.cuda.current_stream(self.ws.device)
+        C.check(C.lib().spm_build_batch(ctypes.byref(self.c), self.ws.data_ptr(), self.ws_bytes,
+                                        ctypes.c_void_p(stream.cuda_stream), timer.h if timer is not None else None))
+        return self.maps
+
+    def capture(self, stream) -> Graph:
+        """Capture one batched build on the (non-default) torch stream `stream`."""
+        h = ctypes.c_void_p()
+        C.check(C.lib().spm_graph_capture_batch(ctypes.byref(self.c), self.ws.data_ptr(), self.ws_bytes,
+                                                ctypes.c_void_p(stream.cuda_stream), ctypes.byref(h)))
+        return Graph(h, self)
+
+    @property
+    def pairs(self) -> int:
+        """Sum over scenes of W * H * G (needs the generator counts, so it synchronises)."""
+        return int(sum(d.width * d.height * int(m.n_gen.item()) for d, m in zip(self.ds, self.maps)))
+
+
 def build(scene, device="cuda", tile=(8, 8)) -> Map:
     """Upload, build and return the map (device tensors; the build is queued on the current stream)."""
     b = Builder(DeviceScene(scene, device), tile=tile)

@@ -166,3 +166,28 @@ def test_query_path_errors(oracle_mod, C):
     with pytest.raises(SpmError) as e:
         query_path(hm, i + 0.5, j + 0.5, cap=1)
     assert e.value.code == C.SPM_ERR_CAPACITY
+
+
+def test_batch_argument_errors(C):
+    L = C.lib()
+    rc = L.spm_batch_query_sizes(None, None)
+    assert rc == C.SPM_ERR_INVALID_ARG
+    sc = (C.SpmScene * 1)(C.SpmScene(10, 10, 0, 0, 1, 0, None, None, None, None, None))
+    outs = (C.SpmOut * 1)()
+    b = C.SpmBatch(1, sc, outs, None)
+    assert L.spm_batch_query_sizes(ctypes.byref(b), None) == C.SPM_ERR_INVALID_ARG   # pts NULL
+    pts = (ctypes.c_int32 * 2)(1, 1)
+    sc[0].pts = ctypes.cast(pts, ctypes.c_void_p)
+    assert L.spm_batch_query_sizes(ctypes.byref(b), None) == C.SPM_ERR_INVALID_ARG   # outputs NULL
+    fake = ctypes.c_void_p(16)
+    outs[0] = C.SpmOut(fake, fake, fake, fake, fake, fake, fake)
+    ws = ctypes.c_size_t(0)
+    assert L.spm_batch_query_sizes(ctypes.byref(b), ctypes.byref(ws)) == C.SPM_OK and ws.value > 0
+    tiles = (ctypes.c_int32 * 1)(5)
+    b.tile_w = tiles
+    assert L.spm_batch_query_sizes(ctypes.byref(b), ctypes.byref(ws)) == C.SPM_ERR_INVALID_ARG
+    b.tile_w = None
+    assert L.spm_batch_prepare(ctypes.byref(b), None, 0) == C.SPM_ERR_INVALID_ARG
+    assert L.spm_build_batch(ctypes.byref(b), fake, 1, None, None) == C.SPM_ERR_CAPACITY
+    g = ctypes.c_void_p()
+    assert L.spm_graph_capture_batch(ctypes.byref(b), fake, 1, None, ctypes.byref(g)) == C.SPM_ERR_INVALID_ARG

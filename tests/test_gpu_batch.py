@@ -1,0 +1,88 @@
+"""Batched builds (one launch per stage, persistent pixel launch) and their HIP graphs."""
+import numpy as np
+import pytest
+
+from scenegen import config4_list, random_small
+from tests.spm_compare import compare, compare_generators
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def spm():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1805_08500_amd as m
+    return m
+
+
+def _single(spm, scene, tw):
+    import torch
+    b = spm.Builder(spm.DeviceScene(scene), tile=(tw, 64 // tw))
+    b.build()
+    torch.cuda.synchronize()
+    return b.map.host()
+
+
+def test_batch_matches_oracle_and_single_builds(oracle_mod, spm):
+    import torch
+    scenes = [random_small(s) for s in range(200, 224)]
+    tiles = [(8, 16, 4)[k % 3] for k in range(len(scenes))]
+    bb = spm.BatchBuilder(scenes, tile_w=tiles)
+    maps = bb.build()
+    torch.cuda.synchronize()
+    for k, (sc, m) in enumerate(zip(scenes, maps)):
+        h = m.host()
+        ref = oracle_mod.full_map(sc)
+        compare(h["dist"], h["parent"], ref, f"batch[{k}]")
+        compare_generators(h, ref["cost"], ref["gparent"], f"batch[{k}]")
+        one = _single(spm, sc, tiles[k])
+        assert np.array_equal(one["dist"], h["dist"]) and np.array_equal(one["parent"], h["parent"]), k
+
+
+def test_batch_graph_replays(spm):
+    import torch
+    scenes = [random_small(s) for s in range(300, 316)]
+    bb = spm.BatchBuilder(scenes)
+    eager = [m.host() for m in bb.build()]
+    torch.cuda.synchronize()
+    stream = torch.cuda.Stream()
+    g = bb.capture(stream)
+    for rep in range(3):
+        for m in bb.maps:            # clobber the outputs so each replay must rewrite them
+            m.dist.fill_(-1.0)
+            m.parent.fill_(-7)
+        x = torch.randn(256, 256, device="cuda")
+        (x @ x).sum().item()         # unrelated eager work between replays
+        g.launch(stream)
+        stream.synchronize()
+        for k, m in enumerate(bb.maps):
+            h = m.host()
+            assert np.array_equal(h["dist"], eager[k]["dist"]), (rep, k)
+            assert np.array_equal(h["parent"], eager[k]["parent"]), (rep, k)
+            assert np.array_equal(h["gen_cost"], eager[k]["gen_cost"]), (rep, k)
+
+
+def test_config4_batch_sampled(oracle_mod, spm):
+    import torch
+    scenes = config4_list()
+    bb = spm.BatchBuilder(scenes, check=False)
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        bb.build(stream)
+    stream.synchronize()
+    g = bb.capture(stream)
+    g.launch(stream)
+    stream.synchronize()
+    rng = np.random.default_rng(4)
+    for k in rng.choice(len(scenes), 6, replace=False):
+        sc = scenes[k]
+        h = bb.maps[k].host()
+        cost, gpar = oracle_mod.costs(sc)
+        compare_generators(h, cost, gpar, f"c4[{k}]")
+        pix = np.unique(rng.integers(0, sc.width * sc.height, 4000))
+        r = oracle_mod.pixels(sc, cost, pix)
+        compare(h["dist"].reshape(-1)[pix], h["parent"].reshape(-1)[pix], r, f"c4[{k}]")
+        one = _single(spm, sc, 8)
+        assert np.array_equal(one["dist"], h["dist"]) and np.array_equal(one["parent"], h["parent"]), k
