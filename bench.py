@@ -43,7 +43,10 @@ def _parse():
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--tile", default="8x8")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-pixels", type=int, default=400000, help="oracle pixel sample for the CPU baseline")
+    ap.add_argument("--no-extras", action="store_true", help="skip the batched and backward figures")
+    ap.add_argument("--cpu-pixels", type=int, default=1 << 20, help="oracle pixel sample for the CPU baseline")
+    ap.add_argument("--calibrate-copy", type=int, default=0,
+                    help="only run one plain device copy of this many bytes (HBM counter calibration) and exit")
     return ap.parse_args()
 
 
@@ -74,7 +77,8 @@ def _cpu_baseline(scene, G, npix):
     cost, _ = O.costs(scene, nthreads=threads)
     t1 = time.perf_counter()
     rng = np.random.default_rng(123)
-    pix = np.unique(rng.integers(0, scene.width * scene.height, npix))
+    WH0 = scene.width * scene.height
+    pix = np.arange(WH0, dtype=np.int64) if npix >= WH0 else np.unique(rng.integers(0, WH0, npix))
     t2 = time.perf_counter()
     O.pixels(scene, cost, pix, nthreads=threads)
     t3 = time.perf_counter()
@@ -82,13 +86,77 @@ def _cpu_baseline(scene, G, npix):
     t_full = (t1 - t0) + (t3 - t2) * WH / len(pix)
     return {
         "value": WH * G / t_full / 1e6, "unit": "Mpixel·gen/s", "cores": int(threads), "kind": "oracle",
-        "sample": (f"generator costs in full ({t1 - t0:.2f} s) + {len(pix)} random pixels ({t3 - t2:.2f} s) "
-                   f"of the same scene, extrapolated to all {WH} pixels"),
+        "sample": (f"generator costs ({t1 - t0:.2f} s) + {len(pix)} of {WH} pixels ({t3 - t2:.2f} s) of the same "
+                   f"scene" + ("" if len(pix) == WH else ", extrapolated to all pixels")),
     }
+
+
+def _batched(spm, torch, reps=10):
+    """256 mixed scenes (sides 128-1024, 4-80 hulls, 1-5 points, 0-3 segments), one hipGraph replay
+    per batched build.  Throughput = sum over scenes of W * H * G / t."""
+    from scenegen import config4_list
+    scenes = config4_list()
+    bb = spm.BatchBuilder(scenes, check=False)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        bb.build(s)
+    s.synchronize()
+    pairs = bb.pairs
+    g = bb.capture(s)
+    g.launch(s)
+    s.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    for _ in range(reps):
+        g.launch(s)
+    e1.record(s)
+    s.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    return {"workload": "256 scenes, sides in {128,256,512,1024}, 4-80 convex hulls, 1-5 points, 0-3 segments, "
+                        "seed 7; one hipGraph replay per build",
+            "scenes": len(scenes), "pixels": int(sum(x.width * x.height for x in scenes)), "pairs": pairs,
+            "ms_per_batch": ms, "value": pairs / (ms * 1e-3) / 1e6, "unit": "Mpixel·gen/s"}
+
+
+def _backward(spm, torch, b, scene, reps=20):
+    """4096 agents on the plain workload: map rebuild + agent distances (forward) and the adjoint."""
+    from scenegen import config5_agents
+    A = torch.from_numpy(config5_agents(scene, 4096, seed=11)).cuda()
+    w = torch.full((A.shape[0],), 1.0 / A.shape[0], device="cuda")
+    for _ in range(3):
+        b.build()
+        spm.agent_distance(b, A)
+        spm.source_gradients(b, A, w)
+    torch.cuda.synchronize()
+    e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    e[0].record()
+    for _ in range(reps):
+        b.build()
+        spm.agent_distance(b, A)
+    e[1].record()
+    for _ in range(reps):
+        spm.source_gradients(b, A, w)
+    e[2].record()
+    torch.cuda.synchronize()
+    fwd = e[0].elapsed_time(e[1]) / reps
+    bwd = e[1].elapsed_time(e[2]) / reps
+    return {"agents": int(A.shape[0]), "forward_ms": fwd, "backward_ms": bwd, "forward_plus_backward_ms": fwd + bwd,
+            "backward_agents_per_s": A.shape[0] / (bwd * 1e-3)}
 
 
 def main():
     args = _parse()
+    if args.calibrate_copy:
+        import torch
+        n = args.calibrate_copy // 4
+        a = torch.ones(n, dtype=torch.float32, device="cuda:0")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibrate_copy_bytes": n * 4}))
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; multi-GPU runs are not part of it",
                           "n_gpus": args.gpus}))
@@ -160,6 +228,9 @@ def main():
             ["tiles", "gen_batches", "lane_bound", "wave_vis", "relevance", "lane_edge", "occluded", "accept"], s)},
         "k_pixel_source_hash": src_hash,
     }
+    if not args.no_extras:
+        out["batched"] = _batched(spm, torch)
+        out["backward"] = _backward(spm, torch, b, scene)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = _cpu_baseline(scene, G, args.cpu_pixels)
     print(json.dumps(out), flush=True)

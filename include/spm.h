@@ -171,6 +171,33 @@ int spm_graph_capture_batch(const spm_batch* b, void* d_ws, size_t ws_bytes, voi
 int spm_graph_launch(spm_graph* g, void* stream);
 int spm_graph_destroy(spm_graph* g);
 
+/* ---------------------------------------------------------------------
+ * Agents and the adjoint.  An agent at a (domain units) reads its pixel's
+ * parent g from a built map (Section 1: grid lookup) and its distance
+ * D(a) = |a - x_g(a)| + cost(g), x_g(a) being g, or the closest point of a
+ * segment source (Section 4).  With the parent chains held fixed, D depends
+ * on the sources only through the last leg of each path, which gives the
+ * gradient of any loss L(D) with respect to the point sources and the
+ * segment endpoints (obstacle corners are fixed).  Device memory, queued on
+ * `stream`; the scene argument is only read for its counts and sizes.
+ * ------------------------------------------------------------------- */
+
+/* Workspace bytes of spm_backward for n_agents agents. */
+int spm_agent_query_ws(const spm_scene* scene, int32_t n_agents, size_t* workspace_bytes);
+
+/* d_dist[i] = D(agent i) (float), +inf for agents outside the grid or in a
+ * pixel without parent.  d_agents_xy is [n_agents][2]. */
+int spm_agent_distance(const spm_scene* scene, const spm_out* map, int32_t n_agents, const float* d_agents_xy,
+                       float* d_dist, void* stream);
+
+/* Gradient of L with respect to the sources, given dL/dD per agent:
+ * d_grad_pts[n_points][2] and d_grad_segs[n_segs][4] (dA then dB) are
+ * overwritten.  Contributions are accumulated in double in a fixed order, so
+ * the result is bitwise reproducible.  Agents without a parent contribute 0. */
+int spm_backward(const spm_scene* scene, const spm_out* map, int32_t n_agents, const float* d_agents_xy,
+                 const float* d_dL_dD, float* d_grad_pts, float* d_grad_segs, void* d_ws, size_t ws_bytes,
+                 void* stream);
+
 /* Host copy of a built map for path queries. */
 typedef struct {
   int32_t width, height;

@@ -6,11 +6,14 @@ from .spm import (  # noqa: F401
     BatchBuilder,
     Builder,
     Graph,
+    SPMDistance,
     DeviceScene,
     Map,
     Timer,
+    agent_distance,
     build,
     query_path,
     query_sizes,
+    source_gradients,
     validate,
 )

@@ -79,6 +79,10 @@ def lib():
     L.spm_timer_elapsed.argtypes = [c_vp, P(ctypes.c_float), P(c_i32)]
     L.spm_query_path.argtypes = [P(SpmMapHost), ctypes.c_float, ctypes.c_float, P(ctypes.c_float), c_i32,
                                  P(c_i32), P(ctypes.c_float)]
+    fpp = P(ctypes.c_float)
+    L.spm_agent_query_ws.argtypes = [sp, c_i32, P(ctypes.c_size_t)]
+    L.spm_agent_distance.argtypes = [sp, op, c_i32, c_vp, c_vp, c_vp]
+    L.spm_backward.argtypes = [sp, op, c_i32, c_vp, c_vp, c_vp, c_vp, c_vp, ctypes.c_size_t, c_vp]
     bp = P(SpmBatch)
     L.spm_batch_query_sizes.argtypes = [bp, P(ctypes.c_size_t)]
     L.spm_batch_prepare.argtypes = [bp, c_vp, ctypes.c_size_t]
@@ -89,7 +93,8 @@ def lib():
     for name in ("spm_validate", "spm_query_sizes", "spm_build", "spm_build_ex", "spm_timer_create",
                  "spm_timer_destroy", "spm_timer_reset", "spm_timer_elapsed", "spm_query_path",
                  "spm_batch_query_sizes", "spm_batch_prepare", "spm_build_batch", "spm_graph_capture_batch",
-                 "spm_graph_launch", "spm_graph_destroy"):
+                 "spm_graph_launch", "spm_graph_destroy", "spm_agent_query_ws", "spm_agent_distance",
+                 "spm_backward"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L

@@ -517,6 +517,46 @@ int spm_build_batch(const spm_batch* b, void* d_ws, size_t ws_bytes, void* strea
   return ok();
 }
 
+int spm_agent_query_ws(const spm_scene* s, int32_t n_agents, size_t* workspace_bytes) {
+  int rc = check_counts(s);
+  if (rc) return rc;
+  if (n_agents < 0) return fail(SPM_ERR_INVALID_ARG, "negative agent count");
+  if (workspace_bytes) *workspace_bytes = agent_ws_bytes(s->n_points + s->n_segs + s->n_vertices, n_agents);
+  return ok();
+}
+
+int spm_agent_distance(const spm_scene* s, const spm_out* out, int32_t n_agents, const float* d_agents_xy,
+                       float* d_dist, void* stream) {
+  int rc = check_counts(s);
+  if (rc) return rc;
+  if ((rc = check_out(out))) return rc;
+  if (n_agents < 0) return fail(SPM_ERR_INVALID_ARG, "negative agent count");
+  if (n_agents > 0 && (!d_agents_xy || !d_dist)) return fail(SPM_ERR_INVALID_ARG, "agent arrays are NULL");
+  hipError_t e = launch_agent_dist(s->width, s->height, n_agents, d_agents_xy, out, d_dist, (hipStream_t)stream);
+  if (e != hipSuccess) return fail(SPM_ERR_HIP, "agent distance launch failed: %s", hipGetErrorString(e));
+  return ok();
+}
+
+int spm_backward(const spm_scene* s, const spm_out* out, int32_t n_agents, const float* d_agents_xy,
+                 const float* d_dL_dD, float* d_grad_pts, float* d_grad_segs, void* d_ws, size_t ws_bytes,
+                 void* stream) {
+  int rc = check_counts(s);
+  if (rc) return rc;
+  if ((rc = check_out(out))) return rc;
+  if (n_agents < 0) return fail(SPM_ERR_INVALID_ARG, "negative agent count");
+  if (n_agents > 0 && (!d_agents_xy || !d_dL_dD)) return fail(SPM_ERR_INVALID_ARG, "agent arrays are NULL");
+  if ((s->n_points > 0 && !d_grad_pts) || (s->n_segs > 0 && !d_grad_segs))
+    return fail(SPM_ERR_INVALID_ARG, "gradient arrays are NULL");
+  const int Gmax = s->n_points + s->n_segs + s->n_vertices;
+  const size_t need = agent_ws_bytes(Gmax, n_agents);
+  if (!d_ws) return fail(SPM_ERR_INVALID_ARG, "workspace is NULL");
+  if (ws_bytes < need) return fail(SPM_ERR_CAPACITY, "workspace has %zu bytes, needs %zu", ws_bytes, need);
+  hipError_t e = launch_backward(s->width, s->height, Gmax, s->n_points, s->n_segs, n_agents, d_agents_xy, d_dL_dD,
+                                 out, d_grad_pts, d_grad_segs, (char*)d_ws, (hipStream_t)stream);
+  if (e != hipSuccess) return fail(SPM_ERR_HIP, "backward launch failed: %s", hipGetErrorString(e));
+  return ok();
+}
+
 int spm_graph_capture_batch(const spm_batch* b, void* d_ws, size_t ws_bytes, void* stream, spm_graph** out) {
   if (!out) return fail(SPM_ERR_INVALID_ARG, "graph out pointer is NULL");
   if (!stream) return fail(SPM_ERR_INVALID_ARG, "capture needs a non-null stream");

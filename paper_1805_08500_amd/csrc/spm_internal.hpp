@@ -239,6 +239,11 @@ template <class S> hipError_t launch_gsort(const S& src, const Plan& p, hipStrea
 hipError_t launch_pixel(const Dev& d, hipStream_t s);
 hipError_t launch_pixel_batch(const BatchSrc& b, const Plan& p, int* batch_ctr, hipStream_t s);
 size_t pixel_lds_bytes(int Gmax, int E, int NC);
+size_t agent_ws_bytes(int Gmax, int n_agents);
+hipError_t launch_agent_dist(int W, int H, int n, const float* agents, const spm_out* out, float* d_out,
+                             hipStream_t s);
+hipError_t launch_backward(int W, int H, int Gmax, int np, int ns, int n, const float* agents, const float* dLdD,
+                           const spm_out* out, float* grad_pts, float* grad_segs, char* ws, hipStream_t s);
 
 #ifdef __HIPCC__
 // ------------------------------------------------------------------------

@@ -148,6 +148,71 @@ class Builder:
         return self.map
 
 
+def agent_distance(builder: Builder, agents: torch.Tensor, stream=None) -> torch.Tensor:
+    """D(a) for agents (n, 2) float32 on the device, read from the builder's last map."""
+    agents = agents.contiguous().to(torch.float32)
+    n = agents.shape[0]
+    out = torch.empty((n,), dtype=torch.float32, device=agents.device)
+    if stream is None:
+        stream = torch.cuda.current_stream(agents.device)
+    C.check(C.lib().spm_agent_distance(ctypes.byref(builder.ds.c), ctypes.byref(builder.out), n,
+                                       agents.data_ptr() if n else None, out.data_ptr() if n else None,
+                                       ctypes.c_void_p(stream.cuda_stream)))
+    return out
+
+
+def source_gradients(builder: Builder, agents: torch.Tensor, dL_dD: torch.Tensor, stream=None):
+    """Gradients of a loss w.r.t. the point sources (n_points, 2) and the segment endpoints
+    (n_segs, 4), given dL/dD per agent, through the builder's last map."""
+    agents = agents.contiguous().to(torch.float32)
+    dL_dD = dL_dD.contiguous().to(torch.float32)
+    n = agents.shape[0]
+    ds = builder.ds
+    dev = agents.device
+    gp = torch.zeros((max(ds.n_points, 1), 2), dtype=torch.float32, device=dev)
+    gs = torch.zeros((max(ds.n_segs, 1), 4), dtype=torch.float32, device=dev)
+    wsb = ctypes.c_size_t(0)
+    C.check(C.lib().spm_agent_query_ws(ctypes.byref(ds.c), n, ctypes.byref(wsb)))
+    ws = torch.empty((int(wsb.value),), dtype=torch.uint8, device=dev)
+    if stream is None:
+        stream = torch.cuda.current_stream(dev)
+    C.check(C.lib().spm_backward(ctypes.byref(ds.c), ctypes.byref(builder.out), n,
+                                 agents.data_ptr() if n else None, dL_dD.data_ptr() if n else None,
+                                 gp.data_ptr(), gs.data_ptr(), ws.data_ptr(), int(wsb.value),
+                                 ctypes.c_void_p(stream.cuda_stream)))
+    return gp[:ds.n_points], gs[:ds.n_segs]
+
+
+class SPMDistance(torch.autograd.Function):
+    """D(agents) as a differentiable function of the source positions.
+
+    forward(pts (n_points, 2), segs (n_segs, 4), agents (n, 2), builder): rounds the
+    source coordinates to the integer lattice the exact predicates need, writes them
+    into the builder's device scene, rebuilds the map and returns D per agent.
+    backward: gradients for pts and segs through the fixed parent chains
+    (spm_backward); agents and builder get none.
+    """
+
+    @staticmethod
+    def forward(ctx, pts, segs, agents, builder):
+        ds = builder.ds
+        if ds.n_points:
+            ds.t["pts"].copy_(torch.round(pts.detach()).to(torch.int32).reshape(-1))
+        if ds.n_segs:
+            ds.t["segs"].copy_(torch.round(segs.detach()).to(torch.int32).reshape(-1))
+        builder.build()
+        D = agent_distance(builder, agents)
+        ctx.save_for_backward(agents)
+        ctx.builder = builder
+        return D
+
+    @staticmethod
+    def backward(ctx, gD):
+        (agents,) = ctx.saved_tensors
+        gp, gs = source_gradients(ctx.builder, agents, gD)
+        return gp, gs, None, None
+
+
 def _alloc_map(H, W, max_gen, dev) -> Map:
     G = max(max_gen, 1)
     return Map(
