@@ -9,7 +9,9 @@ value = W * H * G / t_step / 1e6  (Mpixel*generator/s; G = point sources +
 segment sources + corner generators, the dense pair count the paper's method
 shades).
 
-Prints one JSON line.  See the design doc for the roofline definition.
+Prints one JSON line.  roofline.achieved = arithmetic lane-ops of the pixel
+kernel (work counts from one instrumented build x fixed ops per unit) / its
+average launch time, against 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz.
 """
 from __future__ import annotations
 
@@ -45,6 +47,9 @@ def _parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the batched and backward figures")
     ap.add_argument("--cpu-pixels", type=int, default=1 << 20, help="oracle pixel sample for the CPU baseline")
+    ap.add_argument("--sweep", type=int, default=0, metavar="SOURCES",
+                    help="only run the Profiling-style sweep (k x k squares on 1000^2, k in 2..20) with this many "
+                         "random single sources per map, print its JSON line and exit")
     ap.add_argument("--calibrate-copy", type=int, default=0,
                     help="only run one plain device copy of this many bytes (HBM counter calibration) and exit")
     return ap.parse_args()
@@ -145,8 +150,49 @@ def _backward(spm, torch, b, scene, reps=20):
             "backward_agents_per_s": A.shape[0] / (bwd * 1e-3)}
 
 
+# The paper's own timings of its Profiling maps (Table 1: polygons, computation seconds; GTX 970),
+# quoted as context next to the sweep, never as a target.
+PAPER_PROFILING = {2: (4, 0.0014), 4: (16, 0.0054), 6: (36, 0.0456), 8: (64, 0.1251), 10: (100, 0.2701),
+                   14: (196, 0.8564), 20: (400, 2.7371)}
+
+
+def _sweep(n_sources):
+    """Profiling-style maps: 1000 x 1000, k x k rows of squares (each half its cell's width), one random
+    free source per build, n_sources builds per map.  Reports the mean whole-build time per map."""
+    import torch
+
+    import paper_1805_08500_amd as spm
+    from scenegen import profiling_grid
+    rows = []
+    stream = torch.cuda.current_stream()
+    for k, (polys, paper_s) in PAPER_PROFILING.items():
+        builders = [spm.Builder(spm.DeviceScene(profiling_grid(k, seed=s), "cuda:0")) for s in range(n_sources)]
+        for b in builders[:3]:
+            b.build(stream)
+        torch.cuda.synchronize()
+        timer = spm.Timer()
+        t0 = time.perf_counter()
+        for b in builders:
+            b.build(stream, timer=timer)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        stages, nb = timer.elapsed()
+        G = [int(b.map.n_gen.item()) for b in builders]
+        ms = (t1 - t0) * 1e3 / n_sources
+        rows.append({"k": k, "polygons": polys, "vertices": 4 * polys, "mean_G": sum(G) / len(G),
+                     "ms_per_build": ms, "pixel_ms": stages["pixel"] / max(nb, 1),
+                     "Mpixel_gen_per_s": 1e6 * (sum(G) / len(G)) / (ms * 1e-3) / 1e6,
+                     "paper_comp_s_gtx970": paper_s})
+        del builders
+    return {"sweep": "profiling-style maps, 1000x1000, k x k squares, %d random single sources each" % n_sources,
+            "rows": rows}
+
+
 def main():
     args = _parse()
+    if args.sweep:
+        print(json.dumps(_sweep(args.sweep)), flush=True)
+        return
     if args.calibrate_copy:
         import torch
         n = args.calibrate_copy // 4

@@ -4,7 +4,7 @@ import sys
 import numpy as np
 import pytest
 
-from scenegen import Scene, config1, config2, config3, random_small
+from scenegen import Scene, config1, config2, config3, profiling_grid, random_small
 from scenegen.scenes import _rect_poly
 from tests.spm_compare import compare, compare_generators
 
@@ -85,6 +85,22 @@ def test_config3_maze_sampled(oracle_mod, spm):
     r = oracle_mod.pixels(scene, cost, pix)
     st = compare(h["dist"].reshape(-1)[pix], h["parent"].reshape(-1)[pix], r, "maze")
     _say(f"[parity] maze ok gparent_same={same:.4f} ambiguous={st['ambiguous_frac']:.2e}")
+
+
+@pytest.mark.parametrize("k,seed", [(2, 0), (8, 1), (20, 2)])
+def test_profiling_grid_sampled(oracle_mod, spm, k, seed):
+    """The Profiling-style sweep maps (1000 x 1000, k x k squares, one random source)."""
+    scene = profiling_grid(k, seed=seed)
+    label = f"profiling-{k}x{k}-s{seed}"
+    _say(f"[parity] {label} sampled")
+    h = _gpu(spm, scene)
+    cost, gpar = oracle_mod.costs(scene)
+    compare_generators(h, cost, gpar, label)
+    rng = np.random.default_rng(k)
+    pix = np.unique(rng.integers(0, scene.width * scene.height, 40000))
+    r = oracle_mod.pixels(scene, cost, pix)
+    st = compare(h["dist"].reshape(-1)[pix], h["parent"].reshape(-1)[pix], r, label)
+    _say(f"[parity] {label} ok ambiguous={st['ambiguous_frac']:.2e}")
 
 
 @pytest.mark.parametrize("tile", [(16, 4), (4, 16)])

@@ -391,3 +391,28 @@ def test_sixteen_neighbour_lattice(oracle_mod):
     assert ok.sum() > 0.7 * m.size
     assert np.all(m[ok] <= Dg[ok] + 1.0)
     assert np.all(Dg[ok] <= 1.0275 * m[ok] + 1.0)
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_inside_matches_half_planes(oracle_mod, seed):
+    """The inside mask (pixel centre in or on a closed obstacle) against the
+    half-plane definition of a closed convex polygon: the centre lies on or to
+    the left of every counter-clockwise edge.  The oracle decides it by
+    crossing parity plus an on-boundary test, so the two share nothing."""
+    from scenegen import random_small
+    scene = random_small(seed, "hulls")
+    W, H = scene.width, scene.height
+    jj, ii = np.mgrid[0:H, 0:W]
+    px = (2 * ii + 1).ravel().astype(np.int64)
+    py = (2 * jj + 1).ravel().astype(np.int64)
+    exp = np.zeros(W * H, bool)
+    for P in scene.polys:
+        P2 = 2 * np.asarray(P, np.int64)
+        ok = np.ones(W * H, bool)
+        for k in range(len(P2)):
+            w, v = P2[k], P2[(k + 1) % len(P2)]
+            ok &= (v[0] - w[0]) * (py - w[1]) - (v[1] - w[1]) * (px - w[0]) >= 0
+        exp |= ok
+    assert exp.any()
+    got = oracle_mod.inside(scene, np.arange(W * H, dtype=np.int64))
+    assert np.array_equal(got, exp)
