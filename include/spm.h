@@ -121,15 +121,25 @@ int spm_timer_reset(spm_timer* t);
 int spm_timer_elapsed(spm_timer* t, float* ms /* [SPM_N_STAGES] */, int32_t* n_builds);
 
 /* Build options.  tile_w x tile_h is the pixel tile one wavefront owns
- * (8x8, 16x4 or 4x16; 0 = 8x8).  d_stats, when not NULL, selects the
- * instrumented pixel kernel, which adds its work counters (unsigned 64-bit:
- * [0] tiles, [1] generator batches, [2] lane bound tests, [3] wave
- * visibility tests, [4] edge relevance tests, [5] lane edge tests,
- * [6] occluded tiles, [7] accepted candidates) to the 8 device counters. */
+ * (8x8, 16x4 or 4x16; 0 = 8x8).  strip is the number of consecutive tiles of
+ * one tile row a wavefront takes at a time (1..64; 0 = the default): each
+ * tile after the first first tries the winners of the tile to its left.
+ * samples is the number of seed searches a tile runs, each from one of its
+ * pixels that still has no value: candidates in order of cost + distance,
+ * checked with a cheap visibility test, until one is seen (0 = the default,
+ * -1 = none).  strip and samples change speed only, never an output bit.
+ * d_stats, when not NULL, selects the instrumented pixel kernel, which adds
+ * its work counters (unsigned 64-bit: [0] tiles, [1] batches of 64
+ * lane-parallel generator bound or seed-search tests, [2] lane bound tests,
+ * [3] wave visibility tests, [4] edge relevance or seed-search edge tests (x64
+ * lanes), [5] lane edge tests, [6] occluded tiles, [7] accepted candidates) to
+ * the 8 device counters. */
 typedef struct {
   int32_t tile_w, tile_h;
   spm_timer* timer;
   uint64_t* d_stats;
+  int32_t strip;
+  int32_t samples;
 } spm_build_opts;
 int spm_build_ex(const spm_scene* dev_scene, const spm_out* out, void* d_ws, size_t ws_bytes, void* stream,
                  const spm_build_opts* opts);

@@ -74,28 +74,192 @@ __device__ __forceinline__ float quad_max(float v) {
   return v;
 }
 
+// Hardware square root, reciprocal square root and reciprocal (each within 1
+// ulp, without the correction steps of the correctly rounded library calls).
+// Every value the pixel stage compares or stores comes from these same
+// instructions, so orders and ties are the same whichever path computes them.
+__device__ __forceinline__ float fsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ __forceinline__ float frsq(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ __forceinline__ float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
+
 __device__ __forceinline__ float readlane_f(float v, int l) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
 }
 __device__ __forceinline__ int readlane_i(int v, int l) { return __builtin_amdgcn_readlane(v, l); }
 
+// (value, walk position) order.  The walk keeps, per lane, the least pair over
+// the visible candidates: the generator the cost-ordered walk would settle on
+// (ties keep the earlier generator, as the paper's strict depth test does).
+// Because the pair order is total, the result does not depend on the order in
+// which candidates are tried, so a tile may try a few likely winners (seeds)
+// before the walk without changing any output bit.
+__device__ __forceinline__ bool lex_less(float v, int k, float best, int bpos) {
+  return v < best || (v == best && k < bpos);
+}
+
+// Room below an upper bound ub for a generator of cost c, widened by 1e-6 ub so
+// that every candidate whose float value can round to ub or below passes the
+// square-root-free filters (they are conservative; the exact float compare
+// decides).  ub = -inf (no active lane) gives -inf.
+__device__ __forceinline__ float room_below(float ub, float c) { return (ub - c) + 1e-6f * ub; }
+
 // conservative test: can a generator with cost c and bounding box (x0..y1) come
-// below ub anywhere in the box (bx0..by1)?
+// to ub or below anywhere in the box (bx0..by1)?
 __device__ __forceinline__ bool box_may_win(float c, int x0, int y0, int x1, int y1, int bx0, int by0, int bx1,
                                             int by1, float ub) {
   const int dx = max(max(x0 - bx1, bx0 - x1), 0);
   const int dy = max(max(y0 - by1, by0 - y1), 0);
-  const float room = ub - c;
+  const float room = room_below(ub, c);
   return room > 0.0f && (float)(dx * dx + dy * dy) < 4.0f * room * room * (1.0f + 2e-6f);
 }
+
+constexpr int kMaxTried = 8;    // seeds remembered per tile (skipped by the walk)
+constexpr int kSeedTries = 128; // candidates one seed search may reject
+constexpr int kEstCache = 8;    // seed-search estimates kept in registers per lane
+constexpr int kPrioTries = 6;   // candidates after which a seed search raises its wave's priority
+
+// Seed search for one free pixel P (doubled coordinates, wave-uniform): try
+// generators in order of cost + |P - x_g(P)| -- the exact value whenever g is
+// visible -- until one that P appears to see; that one is P's own winner.
+// "Appears": a cheap test, lane-parallel over edges, in which only a proper
+// crossing of [P, x_g] with an edge, or a start into a corner's own interior
+// angle, blocks.  It may accept a grazing path the exact rule rejects; such a
+// seed costs time, never correctness, because the tile re-evaluates every
+// seed exactly.  Returns the sorted position, or -1 after kSeedTries
+// rejections.
+template <bool STATS>
+__device__ int seed_search(const Geo& geo, const GenRec* sgen, const float* sgcost, const int4* sgbb, int G, int px,
+                           int py, u64* st) {
+  const int lane = lane_id();
+  // cost + |P - x_g(P)| of sorted generator h
+  auto est_of = [&](int h) -> float {
+    const int4 hb = sgbb[h];
+    if (hb.x == hb.z && hb.y == hb.w) {
+      const float dx = (float)(px - hb.x), dy = (float)(py - hb.y);
+      return sgcost[h] + 0.5f * fsqrt(dx * dx + dy * dy);
+    }
+    const float ax = (float)sgen[h].x, ay = (float)sgen[h].y;
+    const float ex = (float)sgen[h].x2 - ax, ey = (float)sgen[h].y2 - ay;
+    const float t = fminf(fmaxf(((px - ax) * ex + (py - ay) * ey) * frcp(ex * ex + ey * ey), 0.0f), 1.0f);
+    const float dx = px - (ax + t * ex), dy = py - (ay + t * ey);
+    return sgcost[h] + 0.5f * fsqrt(dx * dx + dy * dy);
+  };
+  // Up to kEstCache * 64 generators the estimates stay in registers (lane l
+  // holds generators l, l + 64, ...) and a tried candidate is crossed out;
+  // beyond that each try recomputes them and takes the least pair above the
+  // previous candidate.
+  const bool cached = G <= kEstCache * 64;
+  float ec[kEstCache];
+#pragma unroll
+  for (int s = 0; s < kEstCache; ++s) {
+    const int h = lane + 64 * s;
+    ec[s] = (cached && h < G) ? est_of(h) : INFINITY;
+  }
+  if (STATS && cached) st[ST_BATCHES] += (G + 63) / 64;
+  float lastv = -INFINITY;
+  int lastk = -1;
+  for (int it = 0; it < kSeedTries; ++it) {
+    if (it == kPrioTries) __builtin_amdgcn_s_setprio(2);
+    float bv = INFINITY;
+    int bk = 0x7fffffff;
+    if (cached) {
+#pragma unroll
+      for (int s = 0; s < kEstCache; ++s)
+        if (ec[s] < bv) { bv = ec[s]; bk = lane + 64 * s; }
+    } else {
+      if (STATS) st[ST_BATCHES] += (G + 63) / 64;
+      for (int h = lane; h < G; h += 64) {
+        const float v = est_of(h);
+        // the least (v, h) above the previous candidate
+        if ((v > lastv || (v == lastv && h > lastk)) && (v < bv || (v == bv && h < bk))) { bv = v; bk = h; }
+      }
+    }
+    // the least candidate over the wavefront (estimates are >= 0, so their bits order as unsigned)
+    const unsigned key = __float_as_uint(bv);
+    const unsigned mk = wave_min_u32(key);
+    if (mk >= 0x7f800000u) return -1;   // none left
+    if (cached) {
+      const u64 wm = ballot(key == mk);
+      if (!wm) return -1;
+      bk = readlane(bk, first_bit(wm));
+    } else {
+      // lanes holding the least estimate: the least generator among them
+      bk = (int)wave_min_u32(key == mk ? (unsigned)bk : 0xffffffffu);
+    }
+    if (bk < 0 || bk >= G) return -1;
+    lastv = __uint_as_float(mk);
+    lastk = bk;
+    if (cached) {
+#pragma unroll
+      for (int s = 0; s < kEstCache; ++s)
+        if (lane + 64 * s == bk) ec[s] = INFINITY;
+    }
+    // the candidate's point seen from P: the generator, or the segment's closest point
+    const int kind = uni(sgen[bk].kind);
+    const int gx = uni(sgen[bk].x), gy = uni(sgen[bk].y);
+    float qx = (float)gx, qy = (float)gy;
+    if (kind == SPM_GEN_SEGMENT) {
+      const float ex = (float)(uni(sgen[bk].x2) - gx), ey = (float)(uni(sgen[bk].y2) - gy);
+      const float t = fminf(fmaxf(((px - gx) * ex + (py - gy) * ey) * frcp(ex * ex + ey * ey), 0.0f), 1.0f);
+      qx = gx + t * ex;
+      qy = gy + t * ey;
+    } else if (kind == SPM_GEN_VERTEX &&
+               into_interior(uni(sgen[bk].ux), uni(sgen[bk].uy), gx, gy, uni(sgen[bk].nx), uni(sgen[bk].ny),
+                             px - gx, py - gy)) {
+      continue;
+    }
+    const float dqx = qx - px, dqy = qy - py;
+    const int bx0 = min(px, (int)floorf(qx)), bx1 = max(px, (int)ceilf(qx));
+    const int by0 = min(py, (int)floorf(qy)), by1 = max(py, (int)ceilf(qy));
+    bool blocked = false;
+    for (int cb = 0; cb < geo.NC && !blocked; cb += kWave) {
+      const int ci = cb + lane;
+      bool hit = false;
+      if (ci < geo.NC) {
+        const int4 cbx = geo.chunks[ci];
+        hit = cbx.x <= bx1 && cbx.z >= bx0 && cbx.y <= by1 && cbx.w >= by0;
+      }
+      u64 cm = ballot(hit);
+      while (cm) {
+        const int e = (cb + first_bit(cm)) * kChunk + lane;
+        cm &= cm - 1;
+        if (STATS) st[ST_RELEV] += 1;
+        bool x = false;
+        if (e < geo.E) {
+          const EdgeRec r = geo.edges[e];
+          const float o1 = dqx * (float)(r.wy - py) - dqy * (float)(r.wx - px);
+          const float o2 = dqx * (float)(r.vy - py) - dqy * (float)(r.vx - px);
+          const float e1 = (float)(r.a * px + r.b * py + r.c);
+          const float e2 = r.a * qx + r.b * qy + (float)r.c;
+          x = o1 * o2 < 0.0f && e1 * e2 < 0.0f;
+        }
+        if (ballot(x)) {
+          blocked = true;
+          break;
+        }
+      }
+    }
+    if (!blocked) return bk;
+  }
+  return -1;
+}
+
 
 // One tile: the per-lane minimum over generators for 64 pixels.  The
 // generator tables and the edges come through plain pointers that point
 // either into LDS (staged by the kernel) or into global memory.
+//
+//   prevpos: per lane, the walk position of the winner of the previous tile of
+//            the same work item (-1: none).  Its distinct values are tried
+//            first (neighbouring pixels mostly share their parent).
+//   samples: how many seed searches (seed_search) to run, each from a pixel
+//            still without a value after the seeds tried so far.
+// Returns this tile's per-lane winner position (for the next tile).
 template <int TW, bool STATS>
-__device__ __forceinline__ void tile_work(int tile, int W, int H, int W32, int G, const unsigned* __restrict__ inside,
-                                          const GenRec* sgen, const float* sgcost, const int4* sgbb, const Geo& geo,
-                                          float* __restrict__ dist, int* __restrict__ parent, u64* st) {
+__device__ __forceinline__ int tile_work(int tile, int W, int H, int W32, int G, const unsigned* __restrict__ inside,
+                                         const GenRec* sgen, const float* sgcost, const int4* sgbb, const Geo& geo,
+                                         float* __restrict__ dist, int* __restrict__ parent, int prevpos,
+                                         int samples, u64* st) {
   constexpr int TH = 64 / TW;
   constexpr int QL[4] = {0, TW / 2, (TH / 2) * TW, (TH / 2) * TW + TW / 2};  // first lane of each quadrant
   const int lane = lane_id();
@@ -110,7 +274,7 @@ __device__ __forceinline__ void tile_work(int tile, int W, int H, int W32, int G
   const bool active = valid && !ins;
   if (STATS) st[ST_TILES] += 1;
   float best = INFINITY;
-  int par = -1;
+  int bpos = 0x7fffffff;
   const u64 act = ballot(active);
   if (act) {
     // quadrant upper bounds; quadrant q spans pixel columns i0 + (q & 1) * TW/2 .. + TW/2 - 1 and rows
@@ -120,124 +284,206 @@ __device__ __forceinline__ void tile_work(int tile, int W, int H, int W32, int G
     for (int q = 0; q < 4; ++q) ubq[q] = (act & quad_mask<TW>(q)) ? INFINITY : -INFINITY;
     const int qx0 = 2 * i0 + 1, qx1 = qx0 + TW, qy0 = 2 * j0 + 1, qy1 = qy0 + TH;  // lower-half / upper-half starts
     float UB = INFINITY;
-    bool done = false;
-    for (int base = 0; base < G && !done; base += 64) {
-      if (sgcost[base] >= UB) break;
-      if (STATS) st[ST_BATCHES] += 1;
-      // lane-parallel tile bound against the four quadrants
-      const int g = base + lane;
-      bool cand = false;
-      float c = INFINITY;
-      int4 bb = make_int4(0, 0, 0, 0);
-      if (g < G) {
-        c = sgcost[g];
-        bb = sgbb[g];
-        cand = box_may_win(c, bb.x, bb.y, bb.z, bb.w, qx0, qy0, qx1 - 2, qy1 - 2, ubq[0]) ||
-               box_may_win(c, bb.x, bb.y, bb.z, bb.w, qx1, qy0, qx1 + TW - 2, qy1 - 2, ubq[1]) ||
-               box_may_win(c, bb.x, bb.y, bb.z, bb.w, qx0, qy1, qx1 - 2, qy1 + TH - 2, ubq[2]) ||
-               box_may_win(c, bb.x, bb.y, bb.z, bb.w, qx1, qy1, qx1 + TW - 2, qy1 + TH - 2, ubq[3]);
+    int tried[kMaxTried] = {};
+    int ntried = 0;
+    int nvis = 0;
+
+    // Evaluate sorted generator k (cost gc, bounding box x0..y1) for every
+    // lane that it could still improve: per-lane filter, wave-level exact
+    // visibility, (value, position) acceptance, then the quadrant bounds.
+    auto try_gen = [&](int k, float gc, int x0, int y0, int x1, int y1) {
+      const bool is_seg = !(x0 == x1 && y0 == y1);
+      float cc = 0.0f;  // segment: this lane's candidate value
+      int clamp = 0;    // segment: closest point is A (0), B (1) or interior (2)
+      int ax = x0, ay = y0, bx = x1, by = y1;
+      const int ddx = px - x0, ddy = py - y0;
+      const int d2 = mad24(ddx, ddx, mul24(ddy, ddy));   // point or corner: squared doubled distance
+      bool need;
+      if (!is_seg) {
+        // cost + |p - g| <= best  =>  d2 < 4 room^2 (conservative)
+        const float room = room_below(best, gc);
+        need = active && room > 0.0f && (float)d2 < 4.0f * room * room * (1.0f + 1e-6f);
+      } else {
+        ax = sgen[k].x; ay = sgen[k].y; bx = sgen[k].x2; by = sgen[k].y2;
+        const RPt q = seg_closest(ax, ay, bx, by, px, py, &clamp);
+        (void)q;
+        float dd;
+        if (clamp == 0) {
+          dd = 0.5f * fsqrt((float)(mad24(px - ax, px - ax, mul24(py - ay, py - ay))));
+        } else if (clamp == 1) {
+          dd = 0.5f * fsqrt((float)(mad24(px - bx, px - bx, mul24(py - by, py - by))));
+        } else {
+          const long long ex = bx - ax, ey = by - ay;
+          const long long cr = ex * (py - ay) - ey * (px - ax);
+          dd = 0.5f * fabsf((float)cr) * frsq((float)(ex * ex + ey * ey));
+        }
+        cc = gc + dd;
+        need = active && lex_less(cc, k, best, bpos);
       }
-      u64 cm = ballot(cand);
-      while (cm) {
+      const u64 nm = ballot(need);
+      if (STATS) st[ST_BOUND] += __popcll(act);
+      if (!nm) return;
+      // a tile that keeps testing visibility is on the critical path of the launch: let its wave
+      // issue ahead of the others on its SIMD
+      if (++nvis == kPrioTries) __builtin_amdgcn_s_setprio(2);
+      // visibility groups: a point or corner is one group at (x0, y0); a segment has up to three
+      // (lanes reaching endpoint A, endpoint B, or an interior point)
+      const u64 mA = is_seg ? ballot(need && clamp == 0) : nm;
+      const u64 mB = is_seg ? ballot(need && clamp == 1) : 0ull;
+      const u64 mI = nm & ~mA & ~mB;
+      const bool gv = !is_seg && sgen[k].kind == SPM_GEN_VERTEX;
+      u64 bl = 0;
+      for (int grp = 0; grp < 2; ++grp) {
+        const u64 m = grp ? mB : mA;
+        if (!m) continue;
+        if (STATS) st[ST_VISWAVE] += 1;
+        int bx0, by0, bx1, by1;
+        mask_box<TW>(m, i0, j0, bx0, by0, bx1, by1);
+        const int gx = grp ? bx : ax, gy = grp ? by : ay;
+        bl |= wave_blocked_uniform<STATS>(geo, px, py, m, gx, gy, gv, gv ? sgen[k].ux : 0, gv ? sgen[k].uy : 0,
+                                          gv ? sgen[k].nx : 0, gv ? sgen[k].ny : 0, false, 0, 0, 0, 0, bx0, by0,
+                                          bx1, by1, st);
+      }
+      if (mI) {
+        if (STATS) st[ST_VISWAVE] += 1;
+        int bx0, by0, bx1, by1;
+        mask_box<TW>(mI, i0, j0, bx0, by0, bx1, by1);
+        bl |= wave_blocked_perp<STATS>(geo, px, py, mI, ax, ay, bx, by, bx0, by0, bx1, by1, st);
+      }
+      bool upd = false;
+      if (need && !((bl >> lane) & 1ull)) {
+        if (!is_seg) cc = gc + 0.5f * fsqrt((float)d2);
+        if (lex_less(cc, k, best, bpos)) { best = cc; bpos = k; upd = true; }
+      }
+      const u64 um = ballot(upd);
+      if (um) {
+        if (STATS) st[ST_ACCEPT] += __popcll(um);
+        const float qm = quad_max<TW>(active ? best : -INFINITY);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) ubq[q] = readlane_f(qm, QL[q]);
+        UB = fmaxf(fmaxf(ubq[0], ubq[1]), fmaxf(ubq[2], ubq[3]));
+      }
+    };
+    // Candidates come from three sources, in this order: the previous tile's
+    // winners (distinct values), seed searches from pixels that still have no
+    // value, then the walk in (cost, id) order.  One loop serves all
+    // three so that try_gen is instantiated once.
+    u64 pm = ballot(prevpos >= 0 && prevpos < G);
+    int phase = 0;
+    int samples_left = samples;
+    int base = -64;
+    u64 cm = 0;
+    const int g = lane;   // this lane's generator within a walk batch is base + g
+    float c = INFINITY;
+    int4 bb = make_int4(0, 0, 0, 0);
+    auto bound = [&]() {
+      return base + g < G && (box_may_win(c, bb.x, bb.y, bb.z, bb.w, qx0, qy0, qx1 - 2, qy1 - 2, ubq[0]) ||
+                              box_may_win(c, bb.x, bb.y, bb.z, bb.w, qx1, qy0, qx1 + TW - 2, qy1 - 2, ubq[1]) ||
+                              box_may_win(c, bb.x, bb.y, bb.z, bb.w, qx0, qy1, qx1 - 2, qy1 + TH - 2, ubq[2]) ||
+                              box_may_win(c, bb.x, bb.y, bb.z, bb.w, qx1, qy1, qx1 + TW - 2, qy1 + TH - 2, ubq[3]));
+    };
+    for (;;) {
+      int k = -1;
+      if (phase == 0) {
+        if (pm && ntried < kMaxTried) {
+          k = readlane_i(prevpos, first_bit(pm));
+          pm &= ~ballot(prevpos == k);
+        } else {
+          phase = 1;
+        }
+      }
+      if (phase == 1) {
+        const u64 un = ballot(active && best == INFINITY);
+        if (samples_left > 0 && ntried < kMaxTried && un) {
+          --samples_left;
+          // sample the first pixel without a value, starting from the tile centre
+          const u64 hi = un & ~((1ull << ((TH / 2) * TW + TW / 2)) - 1ull);
+          const int l = first_bit(hi ? hi : un);
+          const int k2 = seed_search<STATS>(geo, sgen, sgcost, sgbb, G, readlane_i(px, l), readlane_i(py, l), st);
+          bool seen = k2 < 0;
+#pragma unroll
+          for (int t = 0; t < kMaxTried; ++t) seen |= t < ntried && tried[t] == k2;
+          if (seen) phase = 2;   // nothing new to try: the walk decides
+          else k = k2;
+        } else {
+          phase = 2;
+        }
+      }
+      float gc;
+      int x0, y0, x1, y1;
+      if (phase < 2) {
+        // a seed: remember it so that the walk skips it
+#pragma unroll
+        for (int t = 0; t < kMaxTried; ++t)
+          if (t == ntried) tried[t] = k;
+        ntried = min(ntried + 1, kMaxTried);
+        const int4 kb = sgbb[k];
+        gc = unif(sgcost[k]);
+        x0 = uni(kb.x); y0 = uni(kb.y); x1 = uni(kb.z); y1 = uni(kb.w);
+      } else {
+        if (!cm) {
+          // next batch of the walk: lane-parallel tile bound against the four quadrants
+          base += 64;
+          if (base >= G || sgcost[base] > UB) break;
+          if (STATS) st[ST_BATCHES] += 1;
+          c = INFINITY;
+          bb = make_int4(0, 0, 0, 0);
+          if (base + g < G) {
+            c = sgcost[base + g];
+            bb = sgbb[base + g];
+          }
+          cm = ballot(bound());
+#pragma unroll
+          for (int t = 0; t < kMaxTried; ++t) {
+            const int o = tried[t] - base;
+            if (t < ntried && o >= 0 && o < 64) cm &= ~(1ull << o);
+          }
+          continue;
+        }
         const int jl = first_bit(cm);
         cm &= cm - 1;
-        const int k = base + jl;
-        const float gc = readlane_f(c, jl);
-        if (gc >= UB) { done = true; break; }
-        const int x0 = readlane_i(bb.x, jl), y0 = readlane_i(bb.y, jl);
-        const int x1 = readlane_i(bb.z, jl), y1 = readlane_i(bb.w, jl);
-        bool upd = false;
-        const bool is_seg = !(x0 == x1 && y0 == y1);
-        float cc = 0.0f;  // segment: this lane's candidate value
-        int clamp = 0;    // segment: closest point is A (0), B (1) or interior (2)
-        int ax = x0, ay = y0, bx = x1, by = y1;
-        const int ddx = px - x0, ddy = py - y0;
-        const int d2 = mad24(ddx, ddx, mul24(ddy, ddy));   // point or corner: squared doubled distance
-        bool need;
-        if (!is_seg) {
-          // cost + |p - g| < best  <=>  d2 < 4 (best - cost)^2; the factor keeps the filter conservative
-          const float room = best - gc;
-          need = active && room > 0.0f && (float)d2 < 4.0f * room * room * (1.0f + 1e-6f);
-        } else {
-          ax = sgen[k].x; ay = sgen[k].y; bx = sgen[k].x2; by = sgen[k].y2;
-          const RPt q = seg_closest(ax, ay, bx, by, px, py, &clamp);
-          (void)q;
-          float dd;
-          if (clamp == 0) {
-            dd = 0.5f * sqrtf((float)(mad24(px - ax, px - ax, mul24(py - ay, py - ay))));
-          } else if (clamp == 1) {
-            dd = 0.5f * sqrtf((float)(mad24(px - bx, px - bx, mul24(py - by, py - by))));
-          } else {
-            const long long ex = bx - ax, ey = by - ay;
-            const long long cr = ex * (py - ay) - ey * (px - ax);
-            dd = 0.5f * fabsf((float)cr) / sqrtf((float)(ex * ex + ey * ey));
-          }
-          cc = gc + dd;
-          need = active && cc < best;
-        }
-        const u64 nm = ballot(need);
-        if (STATS) st[ST_BOUND] += __popcll(act);
-        if (!nm) continue;
-        // visibility groups: a point or corner is one group at (x0, y0); a segment has up to three
-        // (lanes reaching endpoint A, endpoint B, or an interior point)
-        const u64 mA = is_seg ? ballot(need && clamp == 0) : nm;
-        const u64 mB = is_seg ? ballot(need && clamp == 1) : 0ull;
-        const u64 mI = nm & ~mA & ~mB;
-        const bool gv = !is_seg && sgen[k].kind == SPM_GEN_VERTEX;
-        u64 bl = 0;
-        for (int grp = 0; grp < 2; ++grp) {
-          const u64 m = grp ? mB : mA;
-          if (!m) continue;
-          if (STATS) st[ST_VISWAVE] += 1;
-          int bx0, by0, bx1, by1;
-          mask_box<TW>(m, i0, j0, bx0, by0, bx1, by1);
-          const int gx = grp ? bx : ax, gy = grp ? by : ay;
-          bl |= wave_blocked_uniform<STATS>(geo, px, py, m, gx, gy, gv, gv ? sgen[k].ux : 0, gv ? sgen[k].uy : 0,
-                                            gv ? sgen[k].nx : 0, gv ? sgen[k].ny : 0, false, 0, 0, 0, 0, bx0, by0,
-                                            bx1, by1, st);
-        }
-        if (mI) {
-          if (STATS) st[ST_VISWAVE] += 1;
-          int bx0, by0, bx1, by1;
-          mask_box<TW>(mI, i0, j0, bx0, by0, bx1, by1);
-          bl |= wave_blocked_perp<STATS>(geo, px, py, mI, ax, ay, bx, by, bx0, by0, bx1, by1, st);
-        }
-        if (need && !((bl >> lane) & 1ull)) {
-          if (!is_seg) cc = gc + 0.5f * sqrtf((float)d2);
-          if (cc < best) { best = cc; par = sgen[k].id; upd = true; }
-        }
-        const u64 um = ballot(upd);
-        if (um) {
-          if (STATS) st[ST_ACCEPT] += __popcll(um);
-          const float qm = quad_max<TW>(active ? best : -INFINITY);
-#pragma unroll
-          for (int q = 0; q < 4; ++q) ubq[q] = readlane_f(qm, QL[q]);
-          UB = fmaxf(fmaxf(ubq[0], ubq[1]), fmaxf(ubq[2], ubq[3]));
-        }
+        gc = readlane_f(c, jl);
+        if (gc > UB) break;
+        k = base + jl;
+        x0 = readlane_i(bb.x, jl); y0 = readlane_i(bb.y, jl); x1 = readlane_i(bb.z, jl); y1 = readlane_i(bb.w, jl);
       }
+      const float ub0 = UB;
+      try_gen(k, gc, x0, y0, x1, y1);
+      if (phase == 2 && UB != ub0) cm &= ballot(bound());   // the bounds tightened: drop what they now exclude
     }
   }
   if (valid) {
     const size_t o = (size_t)j * W + i;
     dist[o] = best;
-    parent[o] = par;
+    parent[o] = best < INFINITY ? sgen[bpos].id : -1;
   }
+  __builtin_amdgcn_s_setprio(0);
+  return best < INFINITY ? bpos : -1;
 }
 
 constexpr int kPixelThreads = 512;
 constexpr size_t kPixelLdsMax = 64 * 1024;
+#ifndef SPM_PIXEL_MIN_WAVES
+#define SPM_PIXEL_MIN_WAVES 4   // waves per SIMD the register budget of k_pixel is sized for
+#endif
 
 size_t pixel_lds_bytes(int Gmax, int E, int NC) {
   return (size_t)Gmax * (sizeof(GenRec) + 4 + 16) + 16 + (size_t)E * sizeof(EdgeRec) + (size_t)NC * 16;
 }
 
-// Persistent kernel: every wavefront takes tiles from a device queue
-// (misc[MISC_TILE_CTR], reset by the generator sort) until none is left.
-// LDSD: the cost-sorted generator table, the edges and the chunk boxes are
-// first staged in LDS, so the wave-uniform reads of the hot loops are LDS
-// broadcasts instead of L2 round trips.
+// Persistent kernel.  A work item is a strip of `strip` consecutive tiles of
+// one tile row, done left to right, so that each tile after the first is
+// seeded with the winners of the tile to its left.  Every wavefront takes its
+// global index as its first item; further items come from kQueues device
+// queues (qctr), one per group of workgroups that the dispatcher places on
+// the same XCD, each handing out every kQueues-th item.  That keeps the
+// number of contended atomics small: a single queue for every wavefront of
+// the chip serialises at one address.  LDSD: the cost-sorted generator
+// table, the edges and the chunk boxes are first staged in LDS, so the
+// wave-uniform reads of the hot loops are LDS broadcasts instead of L2 round
+// trips.
 template <int TW, bool STATS, bool LDSD>
-__global__ __launch_bounds__(kPixelThreads, 6) void k_pixel(int W, int H, int W32, int Gmax, int* misc,
+__global__ __launch_bounds__(kPixelThreads, SPM_PIXEL_MIN_WAVES) void k_pixel(int W, int H, int W32, int Gmax, int* misc,
                                                          const unsigned* __restrict__ inside,
                                                          const GenRec* __restrict__ sgen_g,
                                                          const float* __restrict__ sgcost_g,
@@ -246,6 +492,7 @@ __global__ __launch_bounds__(kPixelThreads, 6) void k_pixel(int W, int H, int W3
                                                          const EdgeExt* __restrict__ ext,
                                                          const int4* __restrict__ chunks_g, int E, int NC,
                                                          float* __restrict__ dist, int* __restrict__ parent,
+                                                         int strip, int samples, int* __restrict__ qctr,
                                                          u64* __restrict__ stats) {
   constexpr int TH = 64 / TW;
   extern __shared__ int4 smem[];
@@ -274,14 +521,26 @@ __global__ __launch_bounds__(kPixelThreads, 6) void k_pixel(int W, int H, int W3
     geo.edges = s_edges;
     geo.chunks = s_chunks;
   }
-  const int ntiles = ((W + TW - 1) / TW) * ((H + TH - 1) / TH);
+  const int ntx = (W + TW - 1) / TW, nty = (H + TH - 1) / TH;
+  const int spr = (ntx + strip - 1) / strip;   // strips per tile row
+  const int nitems = spr * nty;
   u64 st[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-  for (;;) {
-    int tile = 0;
-    if (lane_id() == 0) tile = atomicAdd(&misc[MISC_TILE_CTR], 1);
-    tile = __shfl(tile, 0, 64);
-    if (tile >= ntiles) break;
-    tile_work<TW, STATS>(tile, W, H, W32, G, inside, sgen, sgcost, sgbb, geo, dist, parent, st);
+  const int wpb = blockDim.x / kWave;
+  const int nw = gridDim.x * wpb;                       // wavefronts in the grid
+  const int nq = min(kQueues, (int)gridDim.x);          // queues in use (each has a workgroup)
+  const int q = blockIdx.x % nq;
+  int item = blockIdx.x * wpb + (threadIdx.x / kWave);  // first item: the wavefront's index
+  while (item < nitems) {
+    const int ty = item / spr, sx = item - ty * spr;
+    const int t0 = sx * strip, t1 = min(t0 + strip, ntx);
+    int prev = -1;
+    for (int t = t0; t < t1; ++t)
+      prev = tile_work<TW, STATS>(ty * ntx + t, W, H, W32, G, inside, sgen, sgcost, sgbb, geo, dist, parent, prev,
+                                  samples, st);
+    int n = 0;
+    if (lane_id() == 0) n = atomicAdd(&qctr[q * kQueueStride], 1);
+    n = __shfl(n, 0, 64);
+    item = nw + q + nq * n;
   }
   if (STATS && lane_id() == 0) {
 #pragma unroll
@@ -308,15 +567,15 @@ static hipError_t launch_variant(const Dev& d, hipStream_t s, size_t shm) {
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kPixelThreads, shm) != hipSuccess || per_cu < 1)
     per_cu = 1;
   constexpr int TH = 64 / TW;
-  const long long tiles = (long long)((d.W + TW - 1) / TW) * ((d.H + TH - 1) / TH);
-  const long long waves_needed = tiles;
+  const long long ntx = (d.W + TW - 1) / TW;
+  const long long waves_needed = (ntx + d.strip - 1) / d.strip * ((d.H + TH - 1) / TH);
   long long blocks = (long long)device_cus() * per_cu;
   const long long max_blocks = (waves_needed + (kPixelThreads / 64) - 1) / (kPixelThreads / 64);
   if (blocks > max_blocks) blocks = max_blocks;
   if (blocks < 1) blocks = 1;
   hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(kPixelThreads), shm, s, d.W, d.H, d.W32, d.Gmax, d.misc,
                      d.inside, d.sgen, d.sgcost, d.sgbb, d.edges, d.ext, d.chunks, d.E, d.NC, d.dist, d.parent,
-                     d.stats);
+                     d.strip, d.samples, d.qctr, d.stats);
   return hipGetLastError();
 }
 
@@ -392,18 +651,26 @@ __global__ __launch_bounds__(kPixelThreads, 4) void k_pixel_batch(BatchSrc src, 
       geo.edges = s_edges;
       geo.chunks = s_chunks;
     }
+    // the slice's tiles in strips of d.strip consecutive tiles (seeded left to right)
     for (;;) {
       int t = 0;
-      if (lane_id() == 0) t = atomicAdd(&next_tile, 1);
+      if (lane_id() == 0) t = atomicAdd(&next_tile, d.strip);
       t = __shfl(t, 0, 64);
-      const int tile = item_t0 + t;
-      if (tile >= item_t1) break;
-      if (d.tile_w == 16)
-        tile_work<16, false>(tile, d.W, d.H, d.W32, G, d.inside, sgen, sgcost, sgbb, geo, d.dist, d.parent, st);
-      else if (d.tile_w == 4)
-        tile_work<4, false>(tile, d.W, d.H, d.W32, G, d.inside, sgen, sgcost, sgbb, geo, d.dist, d.parent, st);
-      else
-        tile_work<8, false>(tile, d.W, d.H, d.W32, G, d.inside, sgen, sgcost, sgbb, geo, d.dist, d.parent, st);
+      const int ta = item_t0 + t;
+      if (ta >= item_t1) break;
+      const int tb = min(ta + d.strip, item_t1);
+      int prev = -1;
+      for (int tile = ta; tile < tb; ++tile) {
+        if (d.tile_w == 16)
+          prev = tile_work<16, false>(tile, d.W, d.H, d.W32, G, d.inside, sgen, sgcost, sgbb, geo, d.dist, d.parent,
+                                      prev, d.samples, st);
+        else if (d.tile_w == 4)
+          prev = tile_work<4, false>(tile, d.W, d.H, d.W32, G, d.inside, sgen, sgcost, sgbb, geo, d.dist, d.parent,
+                                     prev, d.samples, st);
+        else
+          prev = tile_work<8, false>(tile, d.W, d.H, d.W32, G, d.inside, sgen, sgcost, sgbb, geo, d.dist, d.parent,
+                                     prev, d.samples, st);
+      }
     }
     __syncthreads();
   }

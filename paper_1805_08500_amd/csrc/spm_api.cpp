@@ -321,9 +321,12 @@ void fill_dev(Dev& d, const spm_scene* s, const spm_out* out, char* ws, const La
   d.vtx2gid = (int*)(ws + L.off_vtx2gid);
   d.gorder = (int*)(ws + L.off_gorder);
   d.costpos = (u64*)(ws + L.off_costpos);
+  d.qctr = (int*)(ws + L.off_qctr);
   d.dist = out->dist; d.parent = out->parent; d.gen_kind = out->gen_kind; d.gen_xy = out->gen_xy;
   d.gen_cost = out->gen_cost; d.gen_parent = out->gen_parent; d.n_gen = out->n_gen;
   d.tile_w = tw; d.tile_h = 64 / tw;
+  d.strip = kDefaultStrip;
+  d.samples = kDefaultSamples;
   d.stats = stats;
 }
 
@@ -449,8 +452,14 @@ int spm_build_ex(const spm_scene* s, const spm_out* out, void* d_ws, size_t ws_b
     tw = opts->tile_w;
     if ((rc = check_tile(opts->tile_w, opts->tile_h))) return rc;
   }
+  if (opts && (opts->strip < 0 || opts->strip > kMaxStrip))
+    return fail(SPM_ERR_INVALID_ARG, "strip %d outside 0..%d", opts->strip, kMaxStrip);
+  if (opts && opts->samples < -1)
+    return fail(SPM_ERR_INVALID_ARG, "samples %d below -1", opts->samples);
   SingleSrc src;
   fill_dev(src.d, s, out, (char*)d_ws, L, tw, opts ? (u64*)opts->d_stats : nullptr);
+  if (opts && opts->strip) src.d.strip = opts->strip;
+  if (opts && opts->samples) src.d.samples = opts->samples < 0 ? 0 : opts->samples;
   Plan p{};
   plan_add(p, src.d);
   hipStream_t st = (hipStream_t)stream;

@@ -22,6 +22,11 @@ typedef unsigned long long u64;
 constexpr int kWave = 64;
 constexpr int kChunk = 64;        // edges per spatial chunk
 constexpr int kRelaxThreads = 1024;
+constexpr int kDefaultStrip = 1;      // tiles per pixel-stage work item
+constexpr int kDefaultSamples = 3;    // seed searches per pixel tile
+constexpr int kMaxStrip = 64;
+constexpr int kQueues = 8;         // pixel-stage work queues (one per XCD)
+constexpr int kQueueStride = 32;   // ints between queue counters (one 128-byte line each)
 
 // One obstacle edge w -> v (obstacle on the left), with its line function
 // E(x, y) = a x + b y + c, positive on the obstacle side.
@@ -55,7 +60,7 @@ struct Layout {
   int E, NC, Gmax, RW, W32;
   size_t off_edges_raw, off_ext_raw, off_keys, off_edges, off_ext, off_chunks, off_convex;
   size_t off_gens, off_vis, off_sgen, off_sgcost, off_sgbb, off_inside, off_cost64, off_gxy, off_misc;
-  size_t off_vsorted, off_vtx2gid, off_gorder, off_costpos;
+  size_t off_vsorted, off_vtx2gid, off_gorder, off_costpos, off_qctr;
   size_t total;
 };
 
@@ -93,6 +98,7 @@ inline Layout make_layout(int W, int H, int n_polys, int nv, int np, int ns) {
   L.off_vtx2gid = take(E1 * sizeof(int));
   L.off_gorder = take(G1 * sizeof(int));
   L.off_costpos = take(G1 * sizeof(u64));
+  L.off_qctr = take(kQueues * kQueueStride * sizeof(int));
   L.total = o;
   return L;
 }
@@ -128,6 +134,7 @@ struct Dev {
   int* vtx2gid;   // generator id of each convex vertex
   int* gorder;    // generator id at each spatial position (sources first)
   u64* costpos;   // relaxation costs by spatial position (IEEE bits) when they do not fit in LDS
+  int* qctr;      // pixel-stage queue counters, kQueues of them kQueueStride ints apart
   // outputs
   float* dist;
   int* parent;
@@ -138,6 +145,8 @@ struct Dev {
   int* n_gen;
   // options
   int tile_w, tile_h;
+  int strip;       // pixel stage: tiles per wavefront work item (>= 1)
+  int samples;     // pixel stage: seed searches per tile (>= 0)
   u64* stats;
 };
 
@@ -253,6 +262,20 @@ __device__ __forceinline__ int lane_id() { return (int)__lane_id(); }
 __device__ __forceinline__ u64 ballot(bool p) { return (u64)__ballot(p); }
 __device__ __forceinline__ int first_bit(u64 m) { return __builtin_ctzll(m); }
 __device__ __forceinline__ int uni(int x) { return __builtin_amdgcn_readfirstlane(x); }
+__device__ __forceinline__ int readlane(int v, int l) { return __builtin_amdgcn_readlane(v, l); }
+
+// Minimum of an unsigned value over the wavefront, in every lane: DPP steps
+// within each row of 16 lanes (quad exchanges, then rotations by 4 and 8),
+// then the four row minima on the scalar unit.
+__device__ __forceinline__ unsigned wave_min_u32(unsigned v) {
+  v = min(v, (unsigned)__builtin_amdgcn_update_dpp(-1, (int)v, 0xB1, 0xF, 0xF, false));   // quad_perm 1,0,3,2
+  v = min(v, (unsigned)__builtin_amdgcn_update_dpp(-1, (int)v, 0x4E, 0xF, 0xF, false));   // quad_perm 2,3,0,1
+  v = min(v, (unsigned)__builtin_amdgcn_update_dpp(-1, (int)v, 0x124, 0xF, 0xF, false));  // row_ror 4
+  v = min(v, (unsigned)__builtin_amdgcn_update_dpp(-1, (int)v, 0x128, 0xF, 0xF, false));  // row_ror 8
+  const unsigned r0 = (unsigned)readlane((int)v, 0), r1 = (unsigned)readlane((int)v, 16);
+  const unsigned r2 = (unsigned)readlane((int)v, 32), r3 = (unsigned)readlane((int)v, 48);
+  return min(min(r0, r1), min(r2, r3));
+}
 __device__ __forceinline__ float unif(float x) {
   return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(x)));
 }
@@ -431,8 +454,9 @@ __device__ __forceinline__ u64 wave_blocked_uniform(const Geo& d, int px, int py
       cm &= cm - 1;
       const int e = chunk * kChunk + lane;
       bool rel = false, occ = false;
+      EdgeRec r = {0, 0, 0, 0, 0, 0, 0, 0};
       if (e < d.E) {
-        EdgeRec r = d.edges[e];
+        r = d.edges[e];
         int Eg = mad24(r.a, gx, mad24(r.b, gy, r.c));
         if (Eg < 0) {
           int hiE = mad24(r.a, r.a > 0 ? bx1 : bx0, mad24(r.b, r.b > 0 ? by1 : by0, r.c));
@@ -456,10 +480,11 @@ __device__ __forceinline__ u64 wave_blocked_uniform(const Geo& d, int px, int py
       }
       u64 rm = ballot(rel);
       while (rm) {
-        const int q = chunk * kChunk + first_bit(rm);
+        // the edge's fields from the lane that holds it
+        const int ql = first_bit(rm);
         rm &= rm - 1;
-        const int wx = d.edges[q].wx, wy = d.edges[q].wy, vx = d.edges[q].vx, vy = d.edges[q].vy;
-        const int ea = d.edges[q].a, eb = d.edges[q].b, enc = d.edges[q].nc;
+        const int wx = readlane(r.wx, ql), wy = readlane(r.wy, ql), vx = readlane(r.vx, ql), vy = readlane(r.vy, ql);
+        const int ea = readlane(r.a, ql), eb = readlane(r.b, ql), enc = readlane(r.nc, ql);
         if (STATS) st[5] += (u64)__popcll(need & ~blocked);
         const int ow = mad24(A, wx, mad24(B, wy, C));
         const int ov = mad24(A, vx, mad24(B, vy, C));
@@ -550,8 +575,9 @@ __device__ __forceinline__ u64 wave_blocked_perp(const Geo& d, int px, int py, u
       cm &= cm - 1;
       const int e = chunk * kChunk + lane;
       bool rel = false, occ = false;
+      EdgeRec r = {0, 0, 0, 0, 0, 0, 0, 0};
       if (e < d.E) {
-        EdgeRec r = d.edges[e];
+        r = d.edges[e];
         const int EA = r.a * ax + r.b * ay + r.c, EB = r.a * bx + r.b * by + r.c;
         const int hiE = r.a * (r.a > 0 ? bx1 : bx0) + r.b * (r.b > 0 ? by1 : by0) + r.c;
         const int loE = r.a * (r.a > 0 ? bx0 : bx1) + r.b * (r.b > 0 ? by0 : by1) + r.c;
@@ -573,10 +599,10 @@ __device__ __forceinline__ u64 wave_blocked_perp(const Geo& d, int px, int py, u
       }
       u64 rm = ballot(rel);
       while (rm) {
-        const int q = chunk * kChunk + first_bit(rm);
+        const int ql = first_bit(rm);
         rm &= rm - 1;
-        const int wx = d.edges[q].wx, wy = d.edges[q].wy, vx = d.edges[q].vx, vy = d.edges[q].vy;
-        const int ea = d.edges[q].a, eb = d.edges[q].b, ec = d.edges[q].c;
+        const int wx = readlane(r.wx, ql), wy = readlane(r.wy, ql), vx = readlane(r.vx, ql), vy = readlane(r.vy, ql);
+        const int ea = readlane(r.a, ql), eb = readlane(r.b, ql), ec = readlane(r.c, ql);
         if (STATS) st[5] += (u64)__popcll(need & ~blocked);
         const int Dw = ex * wx + ey * wy, Dv = ex * vx + ey * vy;
         const int lo = min(Dw, Dv), hi = max(Dw, Dv);

@@ -114,9 +114,13 @@ class Timer:
 
 
 class Builder:
-    """Owns the outputs and workspace of one scene's builds."""
+    """Owns the outputs and workspace of one scene's builds.
 
-    def __init__(self, dscene: DeviceScene, tile=(8, 8)):
+    tile: pixel tile of one wavefront; strip: tiles per work item (0 = library
+    default); samples: seed searches per tile (0 = default, -1 = none).
+    strip and samples change speed only."""
+
+    def __init__(self, dscene: DeviceScene, tile=(8, 8), strip: int = 0, samples: int = 0):
         self.ds = dscene
         dev = dscene.t["vx"].device
         self.max_gen, self.ws_bytes = dscene.sizes
@@ -136,13 +140,15 @@ class Builder:
         self.out = C.SpmOut(m.dist.data_ptr(), m.parent.data_ptr(), m.gen_kind.data_ptr(), m.gen_xy.data_ptr(),
                             m.gen_cost.data_ptr(), m.gen_parent.data_ptr(), m.n_gen.data_ptr())
         self.tile = tuple(tile)
+        self.strip = int(strip)
+        self.samples = int(samples)
 
     def build(self, stream=None, timer: Timer = None, stats: torch.Tensor = None) -> Map:
         """Queue one build on `stream` (default: torch's current stream)."""
         if stream is None:
             stream = torch.cuda.current_stream(self.ws.device)
         opts = C.SpmBuildOpts(self.tile[0], self.tile[1], timer.h if timer is not None else None,
-                              stats.data_ptr() if stats is not None else None)
+                              stats.data_ptr() if stats is not None else None, self.strip, self.samples)
         C.check(C.lib().spm_build_ex(ctypes.byref(self.ds.c), ctypes.byref(self.out), self.ws.data_ptr(),
                                      self.ws_bytes, ctypes.c_void_p(stream.cuda_stream), ctypes.byref(opts)))
         return self.map
