@@ -7,10 +7,13 @@
 // source, like the ingest kernels):
 //   k_genvis   every (corner, generator) arc of the visibility graph, as a
 //              bit matrix (one wavefront per 64 arcs, exact predicates);
-//   k_relax    a single-workgroup Bellman-Ford over that matrix in double
-//              precision, iterated to its fixed point (which Dijkstra also
-//              reaches), then each corner's parent: the smallest id among the
-//              visible predecessors that attain its cost;
+//   k_genvis_seg  the columns of segment sources in that matrix;
+//   k_relax_wide, k_relax, k_relax_parents
+//              Bellman-Ford over that matrix in double precision, iterated to
+//              its fixed point (which Dijkstra also reaches): the first rounds
+//              chip-wide, the rest in one workgroup; then each corner's
+//              parent: the smallest id among the visible predecessors that
+//              attain its cost;
 //   k_gsort    the reached generators ordered by (float cost, id), the order
 //              the pixel stage walks them in.
 #include <math.h>
@@ -40,47 +43,63 @@ __device__ __forceinline__ double arc_len(const GenRec& u, int vx, int vy) {
   return 0.5 * fabs((double)cr) / sqrt((double)L);
 }
 
-// One wavefront per (row corner v, block of 64 generators u): bit u of row v
-// is set iff the arc u -> v exists (u a source or another corner that sees v;
-// for a segment source, v sees the segment's closest point to v).  Rows and
-// bits are indexed by spatial position (gorder), so the 64 generators of a
-// wavefront are neighbours in space and share few relevant edges.  LDSE: the
-// edges and chunk boxes are staged in LDS first.  Workgroups never straddle
-// scenes (each scene's wavefronts are padded to whole workgroups).
-template <class S, bool LDSE>
-__global__ __launch_bounds__(256) void k_genvis(S src) {
-  int sc, blk4;
-  if (!src.locate(STG_GVBLK, blockIdx.x, sc, blk4)) return;
-  const Dev& d = src.scene(sc);
-  extern __shared__ int4 smem[];
-  const int E = d.E, NC = d.NC, RW = d.RW;
-  Geo geo{d.edges, d.ext, d.chunks, E, NC};
-  if (LDSE) {
-    EdgeRec* s_edges = (EdgeRec*)smem;
-    int4* s_chunks = (int4*)(s_edges + E);
-    const int4* se = (const int4*)d.edges;
-    for (int k = threadIdx.x; k < E * 2; k += blockDim.x) ((int4*)s_edges)[k] = se[k];
-    for (int k = threadIdx.x; k < NC; k += blockDim.x) s_chunks[k] = d.chunks[k];
-    __syncthreads();
-    geo.edges = s_edges;
-    geo.chunks = s_chunks;
-  }
-  const int wid = blk4 * 4 + (threadIdx.x >> 6);
-  const int r = wid / RW, blk = wid - r * RW;
+// Generator visibility, one launch, two kinds of wavefronts (the matrix was
+// cleared by k_gen_table; every wavefront ORs its bits in):
+//
+// Point columns: one wavefront per (row corner v, gv_sub consecutive
+// generators u): bit u of row v is set iff the arc u -> v exists (u a point
+// source or another corner that sees v).  Rows and bits are indexed by
+// spatial position (gorder), so the generators of a wavefront are
+// neighbours in space and the box that culls the edges stays small.
+//
+// Segment columns: one wavefront per (segment source s, 64 corner positions).
+// A corner v sees s when it sees the closest point q*(v) of s (Section 4).
+// Lanes whose closest point is an endpoint share that endpoint (the
+// wave-level point test); for the others [v, q*] is perpendicular to s (the
+// wave-level perpendicular test).
+//
+// LDSE: the edges and chunk boxes are staged in LDS first.  Workgroups never
+// straddle scenes for the first kind (each scene's wavefronts are padded to
+// whole workgroups).
+template <class S>
+__device__ __forceinline__ void genvis_points(const Dev& d, const Geo& geo, int wid) {
+  const int RW = d.RW;
+  const int sb = d.gv_sub, per_row = 64 / sb;
+  const int r = wid / (RW * per_row), rest = wid - r * (RW * per_row);
+  const int blk = rest / per_row, sub = rest - blk * per_row;
   const int G = uni(d.misc[MISC_G]);
   const int nsrc = d.np + d.ns;
-  if (r >= G || r < nsrc) return;  // only corner rows are read
   const int lane = lane_id();
+  {
+    // the relaxation's starting state, by spatial position: sources at cost 0 and marked
+    // changed, everything else at +inf; generator coordinates
+    const int t = wid * 64 + lane;
+    if (t < G) {
+      const GenRec gt = d.gens[d.gorder[t]];
+      d.costpos[t] = (u64)__double_as_longlong(t < nsrc ? 0.0 : INFINITY);
+      d.gxy[t] = make_int4(gt.x, gt.y, gt.x2, gt.y2);
+    }
+    if (t < 3 * RW) {
+      u64 m = 0;
+      if (t < RW) {
+        const int lo = t * 64, hi = min(nsrc, lo + 64);
+        if (hi > lo) m = (hi - lo == 64) ? ~0ull : ((1ull << (hi - lo)) - 1ull);
+      }
+      d.rmask[t] = m;
+    }
+  }
+  if (r >= G || r < nsrc) return;  // only corner rows are read
   const int v = uni(d.gorder[r]);
   const int gx = uni(d.gens[v].x), gy = uni(d.gens[v].y);
   const int gux = uni(d.gens[v].ux), guy = uni(d.gens[v].uy), gnx = uni(d.gens[v].nx), gny = uni(d.gens[v].ny);
-  const int upos = blk * 64 + lane;
-  const int u = upos < G ? d.gorder[upos] : -1;
+  const int bit = sub * sb + lane;
+  const int upos = blk * 64 + bit;
+  const int u = (lane < sb && upos < G) ? d.gorder[upos] : -1;
   const bool valid = u >= 0 && u != v;
   GenRec gu = {};
   if (valid) gu = d.gens[u];
+  // segment sources are the columns of the other kind of wavefront
   const bool fast = valid && gu.kind != SPM_GEN_SEGMENT;
-  const bool seg = valid && gu.kind == SPM_GEN_SEGMENT;
   bool ok = false;
   const u64 fm = ballot(fast);
   if (fm) {
@@ -92,19 +111,67 @@ __global__ __launch_bounds__(256) void k_genvis(S src) {
                                                gu.uy, gu.nx, gu.ny, bx0, by0, bx1, by1, dummy);
     ok = fast && !((bl >> lane) & 1ull);
   }
-  if (ballot(seg)) {
-    int clamp;
-    const RPt q = seg_closest(gu.x, gu.y, gu.x2, gu.y2, gx, gy, &clamp);
-    const int sx0 = wave_min_i(seg ? min(gu.x, gu.x2) : (1 << 30));
-    const int sx1 = wave_max_i(seg ? max(gu.x, gu.x2) : -(1 << 30));
-    const int sy0 = wave_min_i(seg ? min(gu.y, gu.y2) : (1 << 30));
-    const int sy1 = wave_max_i(seg ? max(gu.y, gu.y2) : -(1 << 30));
-    const bool vs = lane_visible_rational(geo, gx, gy, true, gux, guy, gnx, gny, q, seg, min(sx0, gx),
-                                          min(sy0, gy), max(sx1, gx), max(sy1, gy));
-    if (seg) ok = vs;
-  }
   const u64 bits = ballot(ok);
-  if (lane == 0) d.vis[(size_t)r * RW + blk] = bits;
+  if (lane == 0 && bits) atomicOr(&d.vis[(size_t)r * RW + blk], bits << (sub * sb));
+}
+
+__device__ __forceinline__ void genvis_segments(const Dev& d, const Geo& geo, int item) {
+  const int nsrc = d.np + d.ns;
+  const int nblk = (d.Gmax - nsrc + 63) / 64;
+  const int s = item / nblk, blk = item - s * nblk;
+  const int G = uni(d.misc[MISC_G]);
+  const int lane = lane_id();
+  const int r = nsrc + blk * 64 + lane;   // this lane's corner position
+  const int spos = d.np + s;              // the segment's position (= its id)
+  const bool valid = r < G;
+  GenRec cv = {};
+  if (valid) cv = d.gens[d.gorder[r]];
+  const GenRec sg = d.gens[spos];
+  const int ax = uni(sg.x), ay = uni(sg.y), bx = uni(sg.x2), by = uni(sg.y2);
+  int clamp = 0;
+  const RPt q = seg_closest(ax, ay, bx, by, cv.x, cv.y, &clamp);
+  (void)q;
+  if (!ballot(valid)) return;
+  u64 dummy[8];
+  u64 bl = 0;
+  for (int grp = 0; grp < 3; ++grp) {
+    const bool inm = valid && clamp == grp;
+    const u64 m = ballot(inm);
+    if (!m) continue;
+    const int x0 = wave_min_i(inm ? cv.x : (1 << 30)), x1 = wave_max_i(inm ? cv.x : -(1 << 30));
+    const int y0 = wave_min_i(inm ? cv.y : (1 << 30)), y1 = wave_max_i(inm ? cv.y : -(1 << 30));
+    if (grp < 2)
+      bl |= wave_blocked_uniform<false>(geo, cv.x, cv.y, m, grp ? bx : ax, grp ? by : ay, false, 0, 0, 0, 0, true,
+                                        cv.ux, cv.uy, cv.nx, cv.ny, x0, y0, x1, y1, dummy) & m;
+    else
+      bl |= wave_blocked_perp<false>(geo, cv.x, cv.y, m, ax, ay, bx, by, true, cv.ux, cv.uy, cv.nx, cv.ny, x0, y0,
+                                     x1, y1, dummy) & m;
+  }
+  if (valid && !((bl >> lane) & 1ull)) atomicOr(&d.vis[(size_t)r * d.RW + (spos >> 6)], 1ull << (spos & 63));
+}
+
+template <class S, bool LDSE>
+__global__ __launch_bounds__(256) void k_genvis(S src, int nblk_points) {
+  const bool pts = (int)blockIdx.x < nblk_points;
+  const int wid = (pts ? blockIdx.x : blockIdx.x - nblk_points) * 4 + (threadIdx.x >> 6);
+  int sc, item;
+  // a whole workgroup of point columns belongs to one scene (padded); segment waves locate alone
+  if (!src.locate(pts ? STG_GVBLK : STG_SEGVIS, pts ? (int)blockIdx.x : wid, sc, item)) return;
+  const Dev& d = src.scene(sc);
+  extern __shared__ int4 smem[];
+  Geo geo{d.edges, d.ext, d.chunks, d.E, d.NC};
+  if (LDSE && pts) {
+    EdgeRec* s_edges = (EdgeRec*)smem;
+    int4* s_chunks = (int4*)(s_edges + d.E);
+    const int4* se = (const int4*)d.edges;
+    for (int k = threadIdx.x; k < d.E * 2; k += blockDim.x) ((int4*)s_edges)[k] = se[k];
+    for (int k = threadIdx.x; k < d.NC; k += blockDim.x) s_chunks[k] = d.chunks[k];
+    __syncthreads();
+    geo.edges = s_edges;
+    geo.chunks = s_chunks;
+  }
+  if (pts) genvis_points<S>(d, geo, item * 4 + (threadIdx.x >> 6));
+  else genvis_segments(d, geo, item);
 }
 
 // Arc weight from a generator with doubled coordinates (x, y, x2, y2) --
@@ -118,22 +185,107 @@ __device__ __forceinline__ double arc_len4(int4 u, int vx, int vy) {
 
 constexpr int kRelaxFront = 2048;   // largest frontier kept as a list (push rounds)
 
-// One workgroup per scene: Bellman-Ford over the arc matrix, iterated to its
-// fixed point (the costs Dijkstra reaches).  Sources start at 0.  Each round
-// relaxes the arcs leaving the generators whose cost changed in the previous
-// round:
-//   pull  (large frontier): every corner v scans row v restricted to the
-//         frontier and keeps the best candidate;
-//   push  (small frontier, corners only): for each frontier corner u, every
-//         corner v of row u -- corner-to-corner visibility is symmetric -- takes
-//         cost(u) + |u - v| through an atomic minimum on the IEEE bits of the
-//         non-negative doubles, which order like the values.
-// Positive arc weights make the double-precision fixed point unique, so the
-// result does not depend on thread timing or on the pull/push schedule.
-// LDS: costs, generator coordinates and change masks live in LDS when they
-// fit, else in global memory.  Everything is indexed by spatial position;
-// outputs go back to canonical ids.
-template <class S, bool LDS>
+// A lower bound, in double, of the arc weight from u (doubled coordinates
+// x, y, x2, y2) to the corner (vx, vy): the hardware float square root with a
+// relative margin of 1e-6 (far above its error) when u is a point or corner;
+// 0 for a segment, whose weight is only ever computed exactly.  Lets the
+// relaxation skip the exact double-precision weight of arcs that cannot win.
+__device__ __forceinline__ double arc_lower(int4 u, int vx, int vy) {
+  if (u.x != u.z || u.y != u.w) return 0.0;
+  const float dx = (float)(vx - u.x), dy = (float)(vy - u.y);
+  return (double)(0.5f * __builtin_amdgcn_sqrtf(dx * dx + dy * dy)) * (1.0 - 1e-6);
+}
+
+// One workgroup per scene: the remaining Bellman-Ford rounds, from the costs
+// and change mask the wide rounds left, iterated to the fixed point (the
+// costs Dijkstra reaches).  Each round relaxes the arcs leaving the
+// generators whose cost changed in the previous round:
+//   pull  (large frontier): one item per (corner row v, 64-bit word k): the
+//         best candidate over the changed generators of that word, merged
+//         into cost(v) by an atomic minimum;
+//   push  (small frontier, corners only): one item per (frontier corner u,
+//         word k of row u) -- corner-to-corner visibility is symmetric -- and
+//         every corner v of it takes cost(u) + |u - v| by an atomic minimum.
+// A float lower bound of each weight skips most exact ones.
+// Atomic minima act on the IEEE bits of non-negative doubles, which order like
+// the values.  Positive arc weights make the double-precision fixed point
+// unique, so the result does not depend on thread timing or on the pull/push
+// schedule.  LDS: costs, generator coordinates and change masks live in LDS
+// when they fit, else in global memory; VLDS: the arc matrix too.  Everything is indexed by
+// spatial position; outputs go back to canonical ids.
+// One Bellman-Ford round over the whole chip (the first rounds, whose
+// frontiers are the largest): one thread per (corner row v, byte of word k),
+// pulling the changed generators there into cost(v) by an atomic minimum on
+// the global cost array.  Round r reads change mask r % 3, marks mask
+// (r + 1) % 3 and clears mask (r + 2) % 3 for the round after.
+template <class S>
+__global__ __launch_bounds__(256) void k_relax_wide(S src, int round) {
+  int sc, it;
+  if (!src.locate(STG_RELAXW, blockIdx.x * blockDim.x + threadIdx.x, sc, it)) return;
+  const Dev& d = src.scene(sc);
+  const int RW = d.RW, nsrc = d.np + d.ns;
+  u64* Mc = d.rmask + (round % 3) * RW;
+  u64* Mn = d.rmask + ((round + 1) % 3) * RW;
+  if (it < RW) d.rmask[((round + 2) % 3) * RW + it] = 0;
+  const int vk = it >> 3, sh = (it & 7) * 8;
+  const int v = nsrc + vk / RW, k = vk - (vk / RW) * RW;
+  if (v >= d.misc[MISC_G]) return;
+  const u64 c = (Mc[k] >> sh) & 0xffull;
+  if (!c) return;
+  u64 m = (d.vis[(size_t)v * RW + k] >> sh) & c;
+  if (!m) return;
+  u64* cost = d.costpos;
+  const int4 pv = d.gxy[v];
+  const double old = __longlong_as_double((long long)cost[v]);
+  double best = old;
+  while (m) {
+    const int u = k * 64 + sh + __builtin_ctzll(m);
+    m &= m - 1;
+    const double cu = __longlong_as_double((long long)cost[u]);
+    if (!(cu < best)) continue;
+    const int4 pu = d.gxy[u];
+    if (!(cu + arc_lower(pu, pv.x, pv.y) < best)) continue;
+    const double cand = cu + arc_len4(pu, pv.x, pv.y);
+    if (cand < best) best = cand;
+  }
+  if (best < old) {
+    const u64 ob = atomicMin(&cost[v], (u64)__double_as_longlong(best));
+    if (__longlong_as_double((long long)ob) > best) atomicOr(&Mn[v >> 6], 1ull << (v & 63));
+  }
+}
+
+// Parents over the whole chip, once the costs are final: one thread per
+// (corner row p, byte of word k); the smallest canonical id among the visible
+// predecessors attaining cost(p), merged by an atomic minimum (parcan was set
+// to INT_MAX by k_relax).
+template <class S>
+__global__ __launch_bounds__(256) void k_relax_parents(S src) {
+  int sc, it;
+  if (!src.locate(STG_RELAXW, blockIdx.x * blockDim.x + threadIdx.x, sc, it)) return;
+  const Dev& d = src.scene(sc);
+  const int RW = d.RW, nsrc = d.np + d.ns;
+  const int pk = it >> 3, sh = (it & 7) * 8;
+  const int p = nsrc + pk / RW, k = pk - (pk / RW) * RW;
+  if (p >= d.misc[MISC_G]) return;
+  const double c = __longlong_as_double((long long)d.costpos[p]);
+  if (!(c < INFINITY)) return;
+  u64 m = (d.vis[(size_t)p * RW + k] >> sh) & 0xffull;
+  if (!m) return;
+  const int4 pv = d.gxy[p];
+  int best = 0x7fffffff;
+  while (m) {
+    const int up = k * 64 + sh + __builtin_ctzll(m);
+    m &= m - 1;
+    const double cu = __longlong_as_double((long long)d.costpos[up]);
+    if (!(cu < c)) continue;
+    const int4 pu = d.gxy[up];
+    if (cu + arc_lower(pu, pv.x, pv.y) > c) continue;
+    if (cu + arc_len4(pu, pv.x, pv.y) == c) best = min(best, d.gorder[up]);
+  }
+  if (best != 0x7fffffff) atomicMin(&d.parcan[d.gorder[p]], best);
+}
+
+template <class S, bool LDS, bool VLDS>
 __global__ __launch_bounds__(1024) void k_relax(S src, int Gcap, int RWcap) {
   int sc, one;
   if (!src.locate(STG_SCENE, blockIdx.x, sc, one)) return;
@@ -142,25 +294,30 @@ __global__ __launch_bounds__(1024) void k_relax(S src, int Gcap, int RWcap) {
   __shared__ int any, nfront, reached;
   __shared__ int front[kRelaxFront];
   const int RW = d.RW;
-  const u64* __restrict__ vis = d.vis;
-  const int* __restrict__ gorder = d.gorder;
+  const u64* vis = d.vis;
   u64* chg_a = shm;
   u64* chg_b = shm + RWcap;
   u64* cost = LDS ? (shm + 2 * RWcap) : d.costpos;   // indexed by spatial position
-  int4* gxy = LDS ? (int4*)(shm + 2 * RWcap + Gcap) : d.gxy;
+  const int4* gxy = d.gxy;
   const int tid = threadIdx.x, nt = blockDim.x;
   const int G = d.misc[MISC_G];
   const int nsrc = d.np + d.ns;
-  for (int k = tid; k < RW; k += nt) { chg_a[k] = 0; chg_b[k] = 0; }
-  if (tid == 0) { reached = 0; nfront = -1; }
-  __syncthreads();
-  for (int g = tid; g < G; g += nt) {
-    const GenRec r = d.gens[gorder[g]];
-    const bool srcg = g < nsrc;
-    cost[g] = (u64)__double_as_longlong(srcg ? 0.0 : INFINITY);
-    gxy[g] = make_int4(r.x, r.y, r.x2, r.y2);
-    if (srcg) atomicOr(&chg_a[g >> 6], 1ull << (g & 63));
+  const int ncr = G - nsrc;   // corner rows
+  if (LDS) {
+    int4* s_gxy = (int4*)(shm + 2 * RWcap + Gcap);
+    for (int g = tid; g < G; g += nt) { cost[g] = d.costpos[g]; s_gxy[g] = d.gxy[g]; }
+    gxy = s_gxy;
   }
+  if (VLDS) {
+    // the arc matrix itself in LDS (G rows of RW words)
+    u64* s_vis = shm + 2 * RWcap + 3 * (size_t)Gcap;
+    for (int k = tid; k < G * RW; k += nt) s_vis[k] = d.vis[k];
+    vis = s_vis;
+  }
+  // the change mask left by the wide rounds
+  const u64* m0 = d.rmask + (kRelaxWideRounds % 3) * RW;
+  for (int k = tid; k < RW; k += nt) { chg_a[k] = m0[k]; chg_b[k] = 0; }
+  if (tid == 0) { reached = 0; nfront = -1; }
   __syncthreads();
   u64* cur = chg_a;
   u64* nxt = chg_b;
@@ -170,45 +327,52 @@ __global__ __launch_bounds__(1024) void k_relax(S src, int Gcap, int RWcap) {
     const int nf = nfront;  // frontier list size, or -1 when only the mask is valid
     __syncthreads();
     if (nf < 0) {
-      for (int v = tid; v < G; v += nt) {
-        if (v < nsrc) continue;  // sources keep cost 0
+      // one item per (corner row v, word k)
+      for (int it = tid; it < ncr * RW; it += nt) {
+        const int v = nsrc + it / RW, k = it - (it / RW) * RW;
+        const int sh = 0;
+        const u64 c = cur[k];
+        if (!c) continue;
+        u64 m = vis[(size_t)v * RW + k] & c;
+        if (!m) continue;
         const int4 pv = gxy[v];
         const double old = __longlong_as_double((long long)cost[v]);
         double best = old;
-        const u64* row = vis + (size_t)v * RW;
-        for (int k = 0; k < RW; ++k) {
-          const u64 c = cur[k];
-          if (!c) continue;
-          u64 m = row[k] & c;
-          while (m) {
-            const int u = k * 64 + __builtin_ctzll(m);
-            m &= m - 1;
-            const double cu = __longlong_as_double((long long)cost[u]);
-            if (!(cu < best)) continue;
-            const double cand = cu + arc_len4(gxy[u], pv.x, pv.y);
-            if (cand < best) best = cand;
-          }
+        while (m) {
+          const int u = k * 64 + sh + __builtin_ctzll(m);
+          m &= m - 1;
+          const double cu = __longlong_as_double((long long)cost[u]);
+          if (!(cu < best)) continue;
+          const int4 pu = gxy[u];
+          if (!(cu + arc_lower(pu, pv.x, pv.y) < best)) continue;
+          const double cand = cu + arc_len4(pu, pv.x, pv.y);
+          if (cand < best) best = cand;
         }
         if (best < old) {
-          cost[v] = (u64)__double_as_longlong(best);
-          atomicOr(&nxt[v >> 6], 1ull << (v & 63));
-          any = 1;
+          const u64 ob = atomicMin(&cost[v], (u64)__double_as_longlong(best));
+          if (__longlong_as_double((long long)ob) > best) {
+            atomicOr(&nxt[v >> 6], 1ull << (v & 63));
+            any = 1;
+          }
         }
       }
     } else {
+      // one item per (frontier corner u, word k of row u)
       for (int it = tid; it < nf * RW; it += nt) {
         const int f = it / RW, k = it - f * RW;
+        const int sh = 0;
         const int u = front[f];
         u64 m = vis[(size_t)u * RW + k];
         if (!m) continue;
         const double cu = __longlong_as_double((long long)cost[u]);
         const int4 pu = gxy[u];
         while (m) {
-          const int v = k * 64 + __builtin_ctzll(m);
+          const int v = k * 64 + sh + __builtin_ctzll(m);
           m &= m - 1;
           const double cv = __longlong_as_double((long long)cost[v]);
           if (!(cu < cv)) continue;
           const int4 pv = gxy[v];
+          if (!(cu + arc_lower(pu, pv.x, pv.y) < cv)) continue;
           const double cand = cu + arc_len4(pu, pv.x, pv.y);
           if (cand < cv) {
             const u64 ob = atomicMin(&cost[v], (u64)__double_as_longlong(cand));
@@ -245,40 +409,22 @@ __global__ __launch_bounds__(1024) void k_relax(S src, int Gcap, int RWcap) {
     for (int k = tid; k < RW; k += nt) nxt[k] = 0;
     __syncthreads();
   }
-  // parents (smallest canonical id attaining the cost) and outputs, in canonical order
+  // outputs by canonical id; parents follow in k_relax_parents
   int mine = 0;
   for (int p = tid; p < G; p += nt) {
     const double c = __longlong_as_double((long long)cost[p]);
-    const int v = gorder[p];
-    int par = -1;
-    if (p < nsrc) par = v;
-    else if (c < INFINITY) {
-      const int4 pv = gxy[p];
-      const u64* row = vis + (size_t)p * RW;
-      for (int k = 0; k < RW; ++k) {
-        u64 m = row[k];
-        while (m) {
-          const int up = k * 64 + __builtin_ctzll(m);
-          m &= m - 1;
-          const double cu = __longlong_as_double((long long)cost[up]);
-          if (!(cu < c)) continue;
-          if (cu + arc_len4(gxy[up], pv.x, pv.y) == c) {
-            const int u = gorder[up];
-            if (par < 0 || u < par) par = u;
-          }
-        }
-      }
-    }
+    const int v = d.gorder[p];
+    if (LDS) d.costpos[p] = cost[p];
     d.gen_cost[v] = c;
-    d.gen_parent[v] = par;
     d.cost64[v] = c;
+    d.parcan[v] = 0x7fffffff;
     if (c < INFINITY) ++mine;
   }
   atomicAdd(&reached, mine);
   __syncthreads();
   if (tid == 0) {
     d.misc[MISC_REACHED] = reached;
-    d.misc[MISC_ROUNDS] = rounds;
+    d.misc[MISC_ROUNDS] = kRelaxWideRounds + rounds;
   }
 }
 
@@ -303,6 +449,11 @@ __global__ __launch_bounds__(256) void k_gsort(S src) {
     }
     rank += __popcll(ballot(lt));
   }
+  if (lane == 0) {
+    // the parent found by k_relax_parents; sources are their own parents
+    const int pc = d.parcan[g];
+    d.gen_parent[g] = g < d.np + d.ns ? g : ((cf < INFINITY && pc != 0x7fffffff) ? pc : -1);
+  }
   if (lane == 0 && cf < INFINITY) {
     GenRec r = d.gens[g];
     r.costf = cf;
@@ -326,33 +477,46 @@ static int max_lds_per_block() {
 
 template <class S>
 hipError_t launch_genvis(const S& src, const Plan& p, hipStream_t s) {
-  if (p.total[STG_GVBLK] <= 0) return hipSuccess;
-  const dim3 grid((unsigned)p.total[STG_GVBLK]);
+  const long long nb = p.total[STG_GVBLK], ns = (p.total[STG_SEGVIS] + 3) / 4;
+  if (nb + ns <= 0) return hipSuccess;
+  const dim3 grid((unsigned)(nb + ns));
   if (p.genvis_lds > 0 && p.genvis_lds <= 32768)
-    hipLaunchKernelGGL((k_genvis<S, true>), grid, dim3(256), p.genvis_lds, s, src);
+    hipLaunchKernelGGL((k_genvis<S, true>), grid, dim3(256), p.genvis_lds, s, src, (int)nb);
   else
-    hipLaunchKernelGGL((k_genvis<S, false>), grid, dim3(256), 0, s, src);
+    hipLaunchKernelGGL((k_genvis<S, false>), grid, dim3(256), 0, s, src, (int)nb);
   return hipGetLastError();
 }
 
 template <class S>
 hipError_t launch_relax(const S& src, const Plan& p, hipStream_t s) {
+  const long long nw = p.total[STG_RELAXW];
+  const unsigned wblocks = (unsigned)((nw + 255) / 256);
+  if (nw > 0)
+    for (int r = 0; r < kRelaxWideRounds; ++r)
+      hipLaunchKernelGGL(k_relax_wide<S>, dim3(wblocks), dim3(256), 0, s, src, r);
   const int RWcap = p.maxRW > 0 ? p.maxRW : 1;
   const int Gcap = p.maxGmax > 0 ? p.maxGmax : 1;
   const size_t chg = 2 * (size_t)RWcap * sizeof(u64);
   const size_t shm = chg + (size_t)Gcap * (sizeof(u64) + sizeof(int4));
+  const size_t shm_v = shm + (size_t)Gcap * RWcap * sizeof(u64);
   const size_t static_lds = 4 * 3 + kRelaxFront * 4 + 64;
+  const size_t lim = (size_t)max_lds_per_block();
   const dim3 grid((unsigned)p.total[STG_SCENE]);
-  if (shm + static_lds <= (size_t)max_lds_per_block()) {
-    if (shm > 65536) {
-      hipError_t e = hipFuncSetAttribute((const void*)k_relax<S, true>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                         (int)shm);
-      if (e != hipSuccess) return e;
-    }
-    hipLaunchKernelGGL((k_relax<S, true>), grid, dim3(kRelaxThreads), shm, s, src, Gcap, RWcap);
+  auto big = [&](const void* f, size_t bytes) {
+    return bytes > 65536 ? hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes)
+                         : hipSuccess;
+  };
+  hipError_t e = hipSuccess;
+  if (shm_v + static_lds <= lim) {
+    if ((e = big((const void*)k_relax<S, true, true>, shm_v)) != hipSuccess) return e;
+    hipLaunchKernelGGL((k_relax<S, true, true>), grid, dim3(kRelaxThreads), shm_v, s, src, Gcap, RWcap);
+  } else if (shm + static_lds <= lim) {
+    if ((e = big((const void*)k_relax<S, true, false>, shm)) != hipSuccess) return e;
+    hipLaunchKernelGGL((k_relax<S, true, false>), grid, dim3(kRelaxThreads), shm, s, src, Gcap, RWcap);
   } else {
-    hipLaunchKernelGGL((k_relax<S, false>), grid, dim3(kRelaxThreads), chg, s, src, Gcap, RWcap);
+    hipLaunchKernelGGL((k_relax<S, false, false>), grid, dim3(kRelaxThreads), chg, s, src, Gcap, RWcap);
   }
+  if (nw > 0) hipLaunchKernelGGL(k_relax_parents<S>, dim3(wblocks), dim3(256), 0, s, src);
   return hipGetLastError();
 }
 

@@ -65,6 +65,8 @@ __global__ __launch_bounds__(1024) void k_gen_table(S src) {
   const int tid = threadIdx.x;
   const int lane = tid & 63, wv = tid >> 6;
   const int np = d.np, ns = d.ns, nv = d.nv;
+  // the generator visibility matrix is filled by atomic ORs: clear it
+  for (size_t k = tid; k < (size_t)d.Gmax * d.RW; k += blockDim.x) d.vis[k] = 0;
   for (int g = tid; g < np + ns; g += blockDim.x) {
     GenRec r = {};
     r.id = g;
@@ -195,26 +197,31 @@ __global__ __launch_bounds__(1024) void k_gorder(S src) {
   }
 }
 
-// One thread per chunk of kChunk sorted edges: bounding box of its endpoints.
+// One wavefront per chunk of kChunk sorted edges (one edge per lane): the
+// bounding box of their endpoints.
 template <class S>
 __global__ __launch_bounds__(256) void k_chunk_boxes(S src) {
   int sc, c;
-  if (!src.locate(STG_CHUNK, blockIdx.x * blockDim.x + threadIdx.x, sc, c)) return;
+  if (!src.locate(STG_CHUNK, blockIdx.x * 4 + (threadIdx.x >> 6), sc, c)) return;
   const Dev& d = src.scene(sc);
+  const int e = c * kChunk + lane_id();
   int x0 = 1 << 30, y0 = 1 << 30, x1 = -(1 << 30), y1 = -(1 << 30);
-  const int e1 = min((c + 1) * kChunk, d.E);
-  for (int e = c * kChunk; e < e1; ++e) {
+  if (e < d.E) {
     const EdgeRec r = d.edges[e];
-    x0 = min(x0, min(r.wx, r.vx));
-    x1 = max(x1, max(r.wx, r.vx));
-    y0 = min(y0, min(r.wy, r.vy));
-    y1 = max(y1, max(r.wy, r.vy));
+    x0 = min(r.wx, r.vx);
+    x1 = max(r.wx, r.vx);
+    y0 = min(r.wy, r.vy);
+    y1 = max(r.wy, r.vy);
   }
-  d.chunks[c] = make_int4(x0, y0, x1, y1);
+  x0 = wave_min_i(x0);
+  y0 = wave_min_i(y0);
+  x1 = wave_max_i(x1);
+  y1 = wave_max_i(y1);
+  if (lane_id() == 0) d.chunks[c] = make_int4(x0, y0, x1, y1);
 }
 
-__device__ __forceinline__ long long floor_div(long long a, long long b) {  // b > 0
-  long long q = a / b;
+__device__ __forceinline__ int floor_div(int a, int b) {  // b > 0
+  int q = a / b;
   if ((a % b != 0) && (a < 0)) --q;
   return q;
 }
@@ -232,26 +239,28 @@ __global__ __launch_bounds__(256) void k_inside(S src) {
   const int W = d.W, E = d.E, W32 = d.W32;
   int* tog = sh;                                      // [W + 1]
   unsigned char* on = (unsigned char*)(sh + W + 1);   // [W]
-  __shared__ int part[256];
   const int tid = threadIdx.x;
-  const long long y = 2 * j + 1;
+  const int y = 2 * j + 1;
+  const int lane = tid & 63, wv = tid >> 6, nw = blockDim.x >> 6;
+  __shared__ int wave_tot[4];
   for (int k = tid; k <= W; k += blockDim.x) tog[k] = 0;
   for (int k = tid; k < W; k += blockDim.x) on[k] = 0;
   __syncthreads();
   for (int e = tid; e < E; e += blockDim.x) {
     const EdgeRec r = d.edges_raw[e];
     if ((r.wy > y) == (r.vy > y)) continue;
-    long long Dn = r.vy - r.wy;
-    long long N = (long long)r.wx * Dn + (y - r.wy) * (long long)(r.vx - r.wx);
+    // crossing x = N / Dn; |N| < 2^30 in doubled coordinates
+    int Dn = r.vy - r.wy;
+    int N = r.wx * Dn + (y - r.wy) * (r.vx - r.wx);
     if (Dn < 0) { Dn = -Dn; N = -N; }
-    const long long f = floor_div(N - 1, Dn);       // largest integer strictly left of the crossing
-    long long cnt = floor_div(f + 1, 2);            // pixels i with 2i + 1 < crossing
+    const int f = floor_div(N - 1, Dn);       // largest integer strictly left of the crossing
+    int cnt = floor_div(f + 1, 2);            // pixels i with 2i + 1 < crossing
     cnt = cnt < 0 ? 0 : (cnt > W ? W : cnt);
     atomicXor(&tog[cnt], 1);
     if (N >= 0 && N % Dn == 0) {
-      const long long xc = N / Dn;
+      const int xc = N / Dn;
       if (xc & 1) {
-        const long long i = (xc - 1) / 2;
+        const int i = (xc - 1) / 2;
         if (i >= 0 && i < W) on[i] = 1;
       }
     }
@@ -262,10 +271,18 @@ __global__ __launch_bounds__(256) void k_inside(S src) {
   const int k0 = tid * per, k1 = min(k0 + per, W + 1);
   int x = 0;
   for (int k = k0; k < k1; ++k) x ^= tog[k];
-  part[tid] = x;
+  // xor of x over the threads after this one: within the wavefront by log steps, then the
+  // totals of the later wavefronts
+  int incl = x;   // xor over lanes >= lane
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const int o = __shfl_down(incl, off, 64);
+    if (lane + off < 64) incl ^= o;
+  }
+  if (lane == 0) wave_tot[wv] = incl;
   __syncthreads();
-  int acc = 0;
-  for (int t = tid + 1; t < (int)blockDim.x; ++t) acc ^= part[t];
+  int acc = incl ^ x;
+  for (int w = wv + 1; w < nw; ++w) acc ^= wave_tot[w];
   for (int k = k1 - 1; k >= k0; --k) {
     const int nxt = acc;     // xor of tog[m] for m > k
     acc ^= tog[k];
@@ -300,7 +317,7 @@ hipError_t launch_edge_sort(const S& src, const Plan& p, hipStream_t s) {
     hipLaunchKernelGGL(k_edge_rank<S>, dim3(blocks_for(p.total[STG_EDGE], 4)), dim3(256), 0, s, src);
   hipLaunchKernelGGL(k_gorder<S>, dim3((unsigned)p.total[STG_SCENE]), dim3(1024), 0, s, src);
   if (p.total[STG_CHUNK] > 0)
-    hipLaunchKernelGGL(k_chunk_boxes<S>, dim3(blocks_for(p.total[STG_CHUNK], 256)), dim3(256), 0, s, src);
+    hipLaunchKernelGGL(k_chunk_boxes<S>, dim3(blocks_for(p.total[STG_CHUNK], 4)), dim3(256), 0, s, src);
   return hipGetLastError();
 }
 

@@ -321,12 +321,18 @@ void fill_dev(Dev& d, const spm_scene* s, const spm_out* out, char* ws, const La
   d.vtx2gid = (int*)(ws + L.off_vtx2gid);
   d.gorder = (int*)(ws + L.off_gorder);
   d.costpos = (u64*)(ws + L.off_costpos);
+  d.parcan = (int*)(ws + L.off_parpos);
+  d.rmask = (u64*)(ws + L.off_rmask);
   d.qctr = (int*)(ws + L.off_qctr);
   d.dist = out->dist; d.parent = out->parent; d.gen_kind = out->gen_kind; d.gen_xy = out->gen_xy;
   d.gen_cost = out->gen_cost; d.gen_parent = out->gen_parent; d.n_gen = out->n_gen;
   d.tile_w = tw; d.tile_h = 64 / tw;
   d.strip = kDefaultStrip;
   d.samples = kDefaultSamples;
+  // generator visibility: the narrowest wavefronts (smallest culling boxes) that keep the launch
+  // within about two rounds of resident wavefronts
+  d.gv_sub = 64;
+  while (d.gv_sub > 16 && (long long)L.Gmax * L.RW * (64 / (d.gv_sub / 2)) <= 16384) d.gv_sub /= 2;
   d.stats = stats;
 }
 

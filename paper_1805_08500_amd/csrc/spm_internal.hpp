@@ -22,6 +22,10 @@ typedef unsigned long long u64;
 constexpr int kWave = 64;
 constexpr int kChunk = 64;        // edges per spatial chunk
 constexpr int kRelaxThreads = 1024;
+#ifndef SPM_RELAX_WIDE
+#define SPM_RELAX_WIDE 2
+#endif
+constexpr int kRelaxWideRounds = SPM_RELAX_WIDE;   // Bellman-Ford rounds run chip-wide before the one-workgroup rounds
 constexpr int kDefaultStrip = 1;      // tiles per pixel-stage work item
 constexpr int kDefaultSamples = 3;    // seed searches per pixel tile
 constexpr int kMaxStrip = 64;
@@ -60,7 +64,7 @@ struct Layout {
   int E, NC, Gmax, RW, W32;
   size_t off_edges_raw, off_ext_raw, off_keys, off_edges, off_ext, off_chunks, off_convex;
   size_t off_gens, off_vis, off_sgen, off_sgcost, off_sgbb, off_inside, off_cost64, off_gxy, off_misc;
-  size_t off_vsorted, off_vtx2gid, off_gorder, off_costpos, off_qctr;
+  size_t off_vsorted, off_vtx2gid, off_gorder, off_costpos, off_parpos, off_qctr, off_rmask;
   size_t total;
 };
 
@@ -98,7 +102,9 @@ inline Layout make_layout(int W, int H, int n_polys, int nv, int np, int ns) {
   L.off_vtx2gid = take(E1 * sizeof(int));
   L.off_gorder = take(G1 * sizeof(int));
   L.off_costpos = take(G1 * sizeof(u64));
+  L.off_parpos = take(G1 * sizeof(int));
   L.off_qctr = take(kQueues * kQueueStride * sizeof(int));
+  L.off_rmask = take(3 * (size_t)(L.RW > 0 ? L.RW : 1) * sizeof(u64));
   L.total = o;
   return L;
 }
@@ -134,6 +140,8 @@ struct Dev {
   int* vtx2gid;   // generator id of each convex vertex
   int* gorder;    // generator id at each spatial position (sources first)
   u64* costpos;   // relaxation costs by spatial position (IEEE bits) when they do not fit in LDS
+  int* parcan;    // relaxation parents by canonical id (smallest id attaining the cost)
+  u64* rmask;     // wide relaxation rounds: three rotating change masks of RW words
   int* qctr;      // pixel-stage queue counters, kQueues of them kQueueStride ints apart
   // outputs
   float* dist;
@@ -147,6 +155,7 @@ struct Dev {
   int tile_w, tile_h;
   int strip;       // pixel stage: tiles per wavefront work item (>= 1)
   int samples;     // pixel stage: seed searches per tile (>= 0)
+  int gv_sub;      // generator visibility: columns per wavefront (64, 32 or 16)
   u64* stats;
 };
 
@@ -171,9 +180,11 @@ enum StageKind {
   STG_EDGE,      // one wavefront per edge
   STG_CHUNK,     // one thread per edge chunk
   STG_ROW,       // one workgroup per pixel row
-  STG_GVBLK,     // one 4-wavefront workgroup per 4 generator-visibility words
+  STG_GVBLK,     // one 4-wavefront workgroup per 4 (row, gv_sub columns) generator-visibility items
   STG_GEN,       // one wavefront per generator slot
   STG_SLICE,     // one pixel-tile slice (batched pixel stage)
+  STG_SEGVIS,    // one wavefront per (segment source, 64 corner positions)
+  STG_RELAXW,    // one thread per (corner row, byte of a 64-bit word) of the visibility matrix
   STG_COUNT
 };
 constexpr int kSlice = 64;   // tiles per work item of the batched pixel stage
@@ -190,9 +201,11 @@ __host__ __device__ inline int stage_count(const Dev& d, int stage) {
     case STG_EDGE: return d.E;
     case STG_CHUNK: return d.NC;
     case STG_ROW: return d.H;
-    case STG_GVBLK: return (int)(((long long)d.Gmax * d.RW + 3) / 4);
+    case STG_GVBLK: return (int)(((long long)d.Gmax * d.RW * (64 / d.gv_sub) + 3) / 4);
     case STG_GEN: return d.Gmax;
     case STG_SLICE: return (tiles_of(d.W, d.H, d.tile_w) + kSlice - 1) / kSlice;
+    case STG_SEGVIS: return d.ns * ((d.Gmax - d.np - d.ns + 63) / 64);
+    case STG_RELAXW: return (d.Gmax - d.np - d.ns) * d.RW * 8;
     default: return 0;
   }
 }
@@ -492,7 +505,14 @@ __device__ __forceinline__ u64 wave_blocked_uniform(const Geo& d, int px, int py
         const float prod = (float)ow * (float)ov;
         const int ep = mad24(ea, px, mul24(eb, py));
         blk = blk || (prod < 0.0f && ep > enc);
-        dg = dg || (prod == 0.0f);
+        if (prod == 0.0f) {
+          // an endpoint exactly on line P-g matters only strictly between P and g (the vertex rule
+          // below); P itself is the corner rule checked above, g is not on a front-facing edge
+          const int gpx = gx - px, gpy = gy - py, len2 = mad24(gpx, gpx, mul24(gpy, gpy));
+          const int dw = mad24(wx - px, gpx, mul24(wy - py, gpy));
+          const int dv = mad24(vx - px, gpx, mul24(vy - py, gpy));
+          dg = dg || (ow == 0 && dw > 0 && dw < len2) || (ov == 0 && dv > 0 && dv < len2);
+        }
       }
       blocked = ballot(blk) & need;
       if (blocked == need) return need;
@@ -544,17 +564,23 @@ __device__ __forceinline__ u64 wave_blocked_uniform(const Geo& d, int px, int py
 // sides of line P-q* iff D(P) is strictly between D(w) and D(v); and the
 // obstacle-side sign of q* is the common sign of E(A) and E(B) unless the edge
 // line cuts the segment (then it is computed per lane, exactly, in 64 bits).
-// Lanes with a vertex exactly on their line fall back to the generic test.
+// Lanes with a vertex exactly on their line strictly between P and q* fall
+// back to the generic test.  P may be an obstacle corner (pv, with its
+// neighbours): then the direction toward q* must not enter its own angle.
 // (bx0..by1) is a box containing every needed P.
 template <bool STATS>
 __device__ __forceinline__ u64 wave_blocked_perp(const Geo& d, int px, int py, u64 need, int ax, int ay, int bx,
-                                                 int by, int bx0, int by0, int bx1, int by1, u64* st) {
+                                                 int by, bool pv, int pux, int puy, int pnx, int pny, int bx0,
+                                                 int by0, int bx1, int by1, u64* st) {
   const int lane = lane_id();
   const int ex = bx - ax, ey = by - ay;
   const int L = ex * ex + ey * ey;
   const int DA = ex * ax + ey * ay;
   const int Pp = ex * px + ey * py;  // D(P)
   const long long num = (long long)Pp - DA;  // (P - A) . e, in (0, L) for needed lanes
+  // F(x) = cross(e, x - A): zero on the segment's line, so a vertex w on line P-q* lies strictly
+  // between P and q* iff F(w) lies strictly between 0 and F(P)
+  const int FP = ex * (py - ay) - ey * (px - ax);
   const int Pmin = ex * (ex > 0 ? bx0 : bx1) + ey * (ey > 0 ? by0 : by1);
   const int Pmax = ex * (ex > 0 ? bx1 : bx0) + ey * (ey > 0 ? by1 : by0);
   // culling box: the pixel box and the part of the segment it projects onto
@@ -564,7 +590,13 @@ __device__ __forceinline__ u64 wave_blocked_perp(const Geo& d, int px, int py, u
   const int cx0 = min(bx0, (int)floorf(fminf(qx0, qx1)) - 1), cx1 = max(bx1, (int)ceilf(fmaxf(qx0, qx1)) + 1);
   const int cy0 = min(by0, (int)floorf(fminf(qy0, qy1)) - 1), cy1 = max(by1, (int)ceilf(fmaxf(qy0, qy1)) + 1);
   bool blk = false, dg = false;
-  u64 blocked = 0;
+  if (pv && ((need >> lane) & 1ull)) {
+    // P a corner: the direction toward q* must not enter P's own interior angle
+    const long long qx = (long long)ax * L + num * ex, qy = (long long)ay * L + num * ey;
+    blk = into_interior64(pux, puy, px, py, pnx, pny, qx - (long long)px * L, qy - (long long)py * L);
+  }
+  u64 blocked = ballot(blk) & need;
+  if (blocked == need) return need;
   for (int cb = 0; cb < d.NC; cb += kWave) {
     u64 cls[3];
     chunk_classes(d.chunks, d.NC, cb, cx0, cy0, cx1, cy1, bx0, by0, bx1, by1, cls);
@@ -608,7 +640,12 @@ __device__ __forceinline__ u64 wave_blocked_perp(const Geo& d, int px, int py, u
         const int lo = min(Dw, Dv), hi = max(Dw, Dv);
         const int EA = ea * ax + eb * ay + ec, EB = ea * bx + eb * by + ec;
         const bool str = Pp > lo && Pp < hi;
-        dg = dg || Pp == lo || Pp == hi;
+        if (Pp == lo || Pp == hi) {
+          const int Fw = ex * (wy - ay) - ey * (wx - ax), Fv = ex * (vy - ay) - ey * (vx - ax);
+          const bool bw = Pp == Dw && (FP > 0 ? (Fw > 0 && Fw < FP) : (Fw < 0 && Fw > FP));
+          const bool bv = Pp == Dv && (FP > 0 ? (Fv > 0 && Fv < FP) : (Fv < 0 && Fv > FP));
+          dg = dg || bw || bv;
+        }
         const int ep = mad24(ea, px, mad24(eb, py, ec));
         bool opp;
         if (EA > 0 && EB > 0) opp = ep < 0;
@@ -631,7 +668,7 @@ __device__ __forceinline__ u64 wave_blocked_perp(const Geo& d, int px, int py, u
     int clamp;
     const RPt q = seg_closest(ax, ay, bx, by, px, py, &clamp);
     const bool mine = (slow >> lane) & 1ull;
-    const bool vs = lane_visible_rational(d, px, py, false, 0, 0, 0, 0, q, mine, min(cx0, bx0), min(cy0, by0),
+    const bool vs = lane_visible_rational(d, px, py, pv, pux, puy, pnx, pny, q, mine, min(cx0, bx0), min(cy0, by0),
                                           max(cx1, bx1), max(cy1, by1));
     blk = blk || (mine && !vs);
     blocked = ballot(blk) & need;
