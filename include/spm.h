@@ -200,6 +200,25 @@ int spm_agent_query_ws(const spm_scene* scene, int32_t n_agents, size_t* workspa
 int spm_agent_distance(const spm_scene* scene, const spm_out* map, int32_t n_agents, const float* d_agents_xy,
                        float* d_dist, void* stream);
 
+/* Refined map values and paths at arbitrary points (Section 6: a point near
+ * the border of two regions may take the wrong first turn from its own
+ * pixel; comparing the parents of the neighbouring pixels at the point itself
+ * removes that error).  For query point i (domain units, d_pts[2i], d_pts[2i+1]),
+ * snapped to 1/512 domain unit: among the parents of the 3 x 3 pixels around
+ * it, the least cost + distance that the point sees (exact integer
+ * visibility under the closed-free-space rule; every generator when it sees
+ * none of them).  d_dist[i] (float) and d_parent[i] (generator id) receive
+ * it; +inf / -1 for points outside the domain, in or on an obstacle, or
+ * unreachable.  When d_path_n is not NULL, the path is walked too: the
+ * snapped point, the corners of the parent chain and the source point (a
+ * segment source's closest point to the last corner); d_path_n[i] receives
+ * its number of points (0 when unreachable) and d_path_xy, when not NULL,
+ * its first min(count, cap) points ([n][cap][2] floats).  The scene must be
+ * the one the map was built from (device arrays; read here for the obstacle
+ * edges).  All pointers are device memory, queued on `stream`. */
+int spm_query_points(const spm_scene* dev_scene, const spm_out* map, int32_t n, const float* d_pts, float* d_dist,
+                     int32_t* d_parent, int32_t cap, float* d_path_xy, int32_t* d_path_n, void* stream);
+
 /* Gradient of L with respect to the sources, given dL/dD per agent:
  * d_grad_pts[n_points][2] and d_grad_segs[n_segs][4] (dA then dB) are
  * overwritten.  Contributions are accumulated in double in a fixed order, so

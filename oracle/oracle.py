@@ -63,6 +63,7 @@ def _load():
         L.orc_costs.argtypes = [sp, dp, ip, dp, ctypes.c_int]
         L.orc_pixels.argtypes = [sp, dp, ctypes.c_int, i64p, fp, ip, dp, dp, ctypes.c_int]
         L.orc_inside.argtypes = [sp, ctypes.c_int, i64p, ctypes.POINTER(ctypes.c_ubyte)]
+        L.orc_points.argtypes = [sp, dp, ctypes.c_int, i64p, ctypes.c_int64, dp, ip, dp, ctypes.c_int]
         L.orc_max_threads.argtypes = []
         _lib = L
     return _lib
@@ -148,6 +149,26 @@ def pixels(scene, cost, pix, nthreads: int = 0) -> dict:
                      _ptr(d32, ctypes.c_float), _ptr(par, ctypes.c_int), _ptr(d64, ctypes.c_double),
                      _ptr(sec, ctypes.c_double), int(nthreads))
     return {"dist": d32[:n], "parent": par[:n], "dist64": d64[:n], "second": sec[:n]}
+
+
+def points(scene, cost, qxy, qw: int, nthreads: int = 0) -> dict:
+    """Map value at rational points: qxy (n, 2) int64 numerators of doubled coordinates over qw
+    (so domain x = qxy[k, 0] / (2 qw)).  Returns dist64, parent, second."""
+    L = _load()
+    b = _Bound(scene)
+    q = np.ascontiguousarray(np.asarray(qxy, np.int64).reshape(-1, 2))
+    n = q.shape[0]
+    cost = np.ascontiguousarray(np.asarray(cost, np.float64))
+    if cost.size == 0:
+        cost = np.zeros(1, np.float64)
+    d64 = np.zeros(max(n, 1), np.float64)
+    par = np.zeros(max(n, 1), np.int32)
+    sec = np.zeros(max(n, 1), np.float64)
+    if n:
+        L.orc_points(b.ref, _ptr(cost, ctypes.c_double), n, _ptr(q, ctypes.c_int64), int(qw),
+                     _ptr(d64, ctypes.c_double), _ptr(par, ctypes.c_int), _ptr(sec, ctypes.c_double),
+                     int(nthreads))
+    return {"dist64": d64[:n], "parent": par[:n], "second": sec[:n]}
 
 
 def inside(scene, pix) -> np.ndarray:

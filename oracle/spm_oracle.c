@@ -471,3 +471,103 @@ int orc_max_threads(void) {
   return 1;
 #endif
 }
+
+/* Map value at rational points (Section 6: the exact first turn of a query
+ * point, not its pixel's).  Query k is (qxy[2k] / qw, qxy[2k+1] / qw) in
+ * doubled coordinates.  Same rule as orc_pixels, over every generator:
+ * dist64 / parent / second; a point in or on an obstacle, or outside the
+ * domain, gets +inf / -1. */
+static int in_closed_rational(const oscene *s, i128 X, i128 Y, i128 w) {
+  int parity = 0;
+  for (int i = 0; i < s->nv; ++i) {
+    i128 ax = s->x[i] * w, ay = s->y[i] * w, bx = s->x[s->next[i]] * w, by = s->y[s->next[i]] * w;
+    i128 c = (bx - ax) * (Y - ay) - (by - ay) * (X - ax);
+    if (c == 0 && X >= (ax < bx ? ax : bx) && X <= (ax > bx ? ax : bx) && Y >= (ay < by ? ay : by) &&
+        Y <= (ay > by ? ay : by))
+      return 1;
+    if ((ay > Y) != (by > Y)) {
+      if ((c > 0) == (by > ay)) parity ^= 1;
+    }
+  }
+  return parity;
+}
+
+/* x_g(q) for a rational q and its distance in domain units */
+static hpt gen_point_rational(const oscene *s, int g, int64_t X, int64_t Y, int64_t w, double *d) {
+  int r = s->gref[g];
+  int64_t gx, gy;
+  if (s->gkind[g] == ORC_SEGMENT) {
+    int64_t ax = s->sax[r], ay = s->say[r], ex = s->sbx[r] - ax, ey = s->sby[r] - ay;
+    int64_t L = ex * ex + ey * ey;
+    i128 num = (i128)(X - ax * w) * ex + (i128)(Y - ay * w) * ey; /* (q - A).e * w */
+    if (num > 0 && num < (i128)L * w) {
+      i128 cr = (i128)ex * (Y - ay * w) - (i128)ey * (X - ax * w);
+      *d = 0.5 * fabs((double)cr) / ((double)w * sqrt((double)L));
+      hpt q = {(i128)ax * w * L + num * ex, (i128)ay * w * L + num * ey, (i128)w * L};
+      return q;
+    }
+    gx = num <= 0 ? ax : s->sbx[r];
+    gy = num <= 0 ? ay : s->sby[r];
+  } else if (s->gkind[g] == ORC_POINT) {
+    gx = s->px[r];
+    gy = s->py[r];
+  } else {
+    gx = s->x[r];
+    gy = s->y[r];
+  }
+  double dx = (double)(X - gx * w) / (double)w, dy = (double)(Y - gy * w) / (double)w;
+  *d = 0.5 * sqrt(dx * dx + dy * dy);
+  return hp(gx, gy);
+}
+
+int orc_points(const orc_scene *in, const double *cost, int n, const int64_t *qxy, int64_t qw, double *dist64,
+               int *parent, double *second, int nthreads) {
+  oscene s;
+  load_oscene(in, &s);
+  int G = s.G;
+#ifdef _OPENMP
+  if (nthreads > 0) omp_set_num_threads(nthreads);
+#pragma omp parallel
+#endif
+  {
+    cand_t *cand = (cand_t *)malloc(sizeof(cand_t) * (G + 1));
+#ifdef _OPENMP
+#pragma omp for schedule(dynamic, 16)
+#endif
+    for (int k = 0; k < n; ++k) {
+      int64_t X = qxy[2 * k], Y = qxy[2 * k + 1];
+      double b1 = INFINITY, b2 = INFINITY;
+      int par = -1;
+      int outside = X < 0 || Y < 0 || X > 2 * (int64_t)s.W * qw || Y > 2 * (int64_t)s.H * qw;
+      if (!outside && !in_closed_rational(&s, X, Y, qw)) {
+        int nc = 0;
+        for (int g = 0; g < G; ++g) {
+          if (!isfinite(cost[g])) continue;
+          double d;
+          gen_point_rational(&s, g, X, Y, qw, &d);
+          cand[nc].c = cost[g] + d;
+          cand[nc].cost = cost[g];
+          cand[nc].id = g;
+          ++nc;
+        }
+        qsort(cand, nc, sizeof(cand_t), cand_cmp);
+        int found = 0;
+        hpt q = {X, Y, qw};
+        for (int t = 0; t < nc && found < 2; ++t) {
+          double d;
+          hpt tg = gen_point_rational(&s, cand[t].id, X, Y, qw, &d);
+          if (!visible(&s, q, tg)) continue;
+          if (found == 0) { b1 = cand[t].c; par = cand[t].id; }
+          else b2 = cand[t].c;
+          ++found;
+        }
+      }
+      dist64[k] = b1;
+      parent[k] = par;
+      second[k] = b2;
+    }
+    free(cand);
+  }
+  free_oscene(&s);
+  return ORC_OK;
+}

@@ -13,6 +13,7 @@ from .spm import (  # noqa: F401
     agent_distance,
     build,
     query_path,
+    query_points,
     query_sizes,
     source_gradients,
     validate,

@@ -83,6 +83,7 @@ def lib():
     fpp = P(ctypes.c_float)
     L.spm_agent_query_ws.argtypes = [sp, c_i32, P(ctypes.c_size_t)]
     L.spm_agent_distance.argtypes = [sp, op, c_i32, c_vp, c_vp, c_vp]
+    L.spm_query_points.argtypes = [sp, op, c_i32, c_vp, c_vp, c_vp, c_i32, c_vp, c_vp, c_vp]
     L.spm_backward.argtypes = [sp, op, c_i32, c_vp, c_vp, c_vp, c_vp, c_vp, ctypes.c_size_t, c_vp]
     bp = P(SpmBatch)
     L.spm_batch_query_sizes.argtypes = [bp, P(ctypes.c_size_t)]

@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libspm.so")
-SOURCES = ["spm_api.cpp", "k_ingest.hip", "k_graph.hip", "k_pixel.hip", "k_adjoint.hip"]
+SOURCES = ["spm_api.cpp", "k_ingest.hip", "k_graph.hip", "k_pixel.hip", "k_adjoint.hip", "k_query.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 FLAGS = [
@@ -36,7 +36,7 @@ def _compile(src: str) -> str:
 def build(verbose: bool = False) -> str:
     """Always recompiles every source and relinks libspm.so."""
     os.makedirs(OBJ, exist_ok=True)
-    with ThreadPoolExecutor(max_workers=min(5, len(SOURCES))) as ex:
+    with ThreadPoolExecutor(max_workers=min(6, len(SOURCES))) as ex:
         objs = list(ex.map(_compile, SOURCES))
     tmp = LIB + ".tmp%d" % os.getpid()
     cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp]

@@ -552,6 +552,21 @@ int spm_agent_distance(const spm_scene* s, const spm_out* out, int32_t n_agents,
   return ok();
 }
 
+int spm_query_points(const spm_scene* s, const spm_out* out, int32_t n, const float* d_pts, float* d_dist,
+                     int32_t* d_parent, int32_t cap, float* d_path_xy, int32_t* d_path_n, void* stream) {
+  int rc = check_counts(s);
+  if (rc) return rc;
+  if ((rc = check_ptrs(s))) return rc;
+  if ((rc = check_out(out))) return rc;
+  if (n < 0) return fail(SPM_ERR_INVALID_ARG, "negative query count");
+  if (n > 0 && (!d_pts || !d_dist || !d_parent)) return fail(SPM_ERR_INVALID_ARG, "query arrays are NULL");
+  if (d_path_xy && (!d_path_n || cap < 1)) return fail(SPM_ERR_INVALID_ARG, "path output needs d_path_n and cap >= 1");
+  hipError_t e = launch_query_points(s, out, n, d_pts, cap, d_dist, d_parent, d_path_xy, d_path_n,
+                                     (hipStream_t)stream);
+  if (e != hipSuccess) return fail(SPM_ERR_HIP, "query launch failed: %s", hipGetErrorString(e));
+  return ok();
+}
+
 int spm_backward(const spm_scene* s, const spm_out* out, int32_t n_agents, const float* d_agents_xy,
                  const float* d_dL_dD, float* d_grad_pts, float* d_grad_segs, void* d_ws, size_t ws_bytes,
                  void* stream) {

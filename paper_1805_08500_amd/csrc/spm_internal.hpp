@@ -264,6 +264,8 @@ size_t pixel_lds_bytes(int Gmax, int E, int NC);
 size_t agent_ws_bytes(int Gmax, int n_agents);
 hipError_t launch_agent_dist(int W, int H, int n, const float* agents, const spm_out* out, float* d_out,
                              hipStream_t s);
+hipError_t launch_query_points(const spm_scene* s, const spm_out* out, int n, const float* pts, int cap, float* dist,
+                               int* par, float* path_xy, int* path_n, hipStream_t st);
 hipError_t launch_backward(int W, int H, int Gmax, int np, int ns, int n, const float* agents, const float* dLdD,
                            const spm_out* out, float* grad_pts, float* grad_segs, char* ws, hipStream_t s);
 

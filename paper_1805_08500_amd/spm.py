@@ -167,6 +167,30 @@ def agent_distance(builder: Builder, agents: torch.Tensor, stream=None) -> torch
     return out
 
 
+def query_points(builder: Builder, pts: torch.Tensor, cap: int = 0, stream=None):
+    """Refined map values at arbitrary points (n, 2) float32 on the device: the least cost + distance
+    among the 3 x 3 neighbouring pixels' parents that each point sees.  Returns (dist, parent) and,
+    with cap > 0, also (path_xy (n, cap, 2), path_n (n,)): each point's whole path."""
+    pts = pts.contiguous().to(torch.float32)
+    n = pts.shape[0]
+    dev = pts.device
+    dist = torch.empty((n,), dtype=torch.float32, device=dev)
+    par = torch.empty((n,), dtype=torch.int32, device=dev)
+    pxy = torch.empty((n, max(cap, 1), 2), dtype=torch.float32, device=dev) if cap > 0 else None
+    pn = torch.empty((n,), dtype=torch.int32, device=dev) if cap > 0 else None
+    if stream is None:
+        stream = torch.cuda.current_stream(dev)
+    C.check(C.lib().spm_query_points(ctypes.byref(builder.ds.c), ctypes.byref(builder.out), n,
+                                     pts.data_ptr() if n else None, dist.data_ptr() if n else None,
+                                     par.data_ptr() if n else None, int(cap),
+                                     pxy.data_ptr() if (pxy is not None and n) else None,
+                                     pn.data_ptr() if (pn is not None and n) else None,
+                                     ctypes.c_void_p(stream.cuda_stream)))
+    if cap > 0:
+        return dist, par, pxy, pn
+    return dist, par
+
+
 def source_gradients(builder: Builder, agents: torch.Tensor, dL_dD: torch.Tensor, stream=None):
     """Gradients of a loss w.r.t. the point sources (n_points, 2) and the segment endpoints
     (n_segs, 4), given dL/dD per agent, through the builder's last map."""

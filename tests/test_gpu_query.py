@@ -1,0 +1,147 @@
+"""Refined point queries and device paths (the neighbouring pixels' parents compared at the point
+itself), against the oracle's map value at the same rational points."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from scenegen import Scene, config2, random_small
+from scenegen.scenes import _rect_poly
+from tests.spm_compare import RTOL, ATOL
+
+pytestmark = pytest.mark.gpu
+QW = 256   # the library snaps query points to 1 / (2 * QW) domain units
+
+
+@pytest.fixture(scope="module")
+def spm():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1805_08500_amd as m
+    return m
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _border_points(scene, parent, rng, n):
+    """Lattice points inside pixels whose right or upper neighbour has another parent."""
+    P = parent
+    b = np.zeros_like(P, bool)
+    b[:, :-1] |= (P[:, :-1] != P[:, 1:]) & (P[:, :-1] >= 0) & (P[:, 1:] >= 0)
+    b[:-1, :] |= (P[:-1, :] != P[1:, :]) & (P[:-1, :] >= 0) & (P[1:, :] >= 0)
+    jj, ii = np.nonzero(b)
+    k = rng.choice(len(ii), min(n, len(ii)), replace=False)
+    sub = rng.integers(1, 2 * QW, (len(k), 2))
+    return np.stack([ii[k] * 2 * QW + sub[:, 0], jj[k] * 2 * QW + sub[:, 1]], 1).astype(np.int64)
+
+
+def _run(spm, scene, q):
+    import torch
+    b = spm.Builder(spm.DeviceScene(scene))
+    b.build()
+    pts = torch.from_numpy((q / (2.0 * QW)).astype(np.float32)).cuda()
+    d, p, pxy, pn = spm.query_points(b, pts, cap=64)
+    torch.cuda.synchronize()
+    return b, d.cpu().numpy().astype(np.float64), p.cpu().numpy(), pxy.cpu().numpy(), pn.cpu().numpy()
+
+
+def _check(oracle_mod, spm, scene, q, label):
+    cost, _ = oracle_mod.costs(scene)
+    b, d, p, pxy, pn = _run(spm, scene, q)
+    ref = oracle_mod.points(scene, cost, q, QW)
+    inf_ref = ~np.isfinite(ref["dist64"])
+    assert np.array_equal(~np.isfinite(d), inf_ref), label
+    assert (p[inf_ref] == -1).all() and (pn[inf_ref] == 0).all()
+    f = ~inf_ref
+    D = ref["dist64"][f]
+    tol = RTOL * D + ATOL
+    # every answer is the value of a visible candidate: never below the exact minimum
+    assert (d[f] >= D - tol).all(), label
+    amb = (ref["second"][f] - D) <= tol
+    good = np.abs(d[f] - D) <= tol
+    same = p[f] == ref["parent"][f]
+    exact = good & (same | amb)
+    frac = exact.mean()
+    _say(f"[query] {label}: n={f.sum()} exact={frac:.5f} ambiguous={amb.mean():.2e}")
+    assert frac >= 0.999, (label, frac)
+    return b, d, p, pxy, pn, ref, f
+
+
+def test_query_points_config2(oracle_mod, spm):
+    scene = config2(1)
+    rng = np.random.default_rng(5)
+    q = np.vstack([np.stack([rng.integers(0, 2 * 1024 * QW, 3000), rng.integers(0, 2 * 1024 * QW, 3000)], 1),
+                   _border_points(scene, oracle_mod.full_map(scene)["parent"], rng, 3000)]).astype(np.int64)
+    _check(oracle_mod, spm, scene, q, "convex1024")
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_query_points_fuzz(oracle_mod, spm, seed):
+    scene = random_small(seed)
+    rng = np.random.default_rng(seed)
+    W, H = scene.width, scene.height
+    q = np.stack([rng.integers(0, 2 * W * QW + 1, 1500), rng.integers(0, 2 * H * QW + 1, 1500)], 1).astype(np.int64)
+    _check(oracle_mod, spm, scene, q, f"fuzz-{seed}")
+
+
+def test_refinement_fixes_border_points(oracle_mod, spm):
+    """At region borders the pixel's own parent is often not the point's; the refined one is."""
+    import torch
+    scene = config2(1)
+    rng = np.random.default_rng(9)
+    m = oracle_mod.full_map(scene)
+    q = _border_points(scene, m["parent"], rng, 4000)
+    cost, _ = oracle_mod.costs(scene)
+    ref = oracle_mod.points(scene, cost, q, QW)
+    b, d, p, pxy, pn = _run(spm, scene, q)
+    pix_par = b.map.parent.cpu().numpy()[q[:, 1] // (2 * QW), q[:, 0] // (2 * QW)]
+    D = ref["dist64"]
+    clear = (ref["second"] - D) > RTOL * D + ATOL
+    wrong_pixel = (pix_par != ref["parent"]) & clear
+    _say(f"[query] border points: pixel parent wrong at {wrong_pixel.sum()} of {clear.sum()} clear points")
+    assert wrong_pixel.sum() > 20
+    assert (p[wrong_pixel] == ref["parent"][wrong_pixel]).mean() >= 0.995
+
+
+def test_query_paths(oracle_mod, spm):
+    scene = random_small(4)
+    rng = np.random.default_rng(4)
+    W, H = scene.width, scene.height
+    q = np.stack([rng.integers(0, 2 * W * QW + 1, 400), rng.integers(0, 2 * H * QW + 1, 400)], 1).astype(np.int64)
+    b, d, p, pxy, pn, ref, f = _check(oracle_mod, spm, scene, q, "paths")
+    for k in np.nonzero(f)[0]:
+        n = int(pn[k])
+        assert 2 <= n <= 64
+        path = pxy[k, :n].astype(np.float64)
+        assert np.allclose(path[0], q[k] / (2.0 * QW))
+        L = sum(math.dist(a, c) for a, c in zip(path[:-1], path[1:]))
+        assert abs(L - d[k]) <= 1e-4 * max(1.0, d[k]), (k, L, d[k])
+        # legs that end at lattice points (corners, point sources) are exactly visible
+        for a, c in zip(path[:-1], path[1:]):
+            if np.all(c == np.round(c)):
+                ha = (int(round(a[0] * 2 * QW)), int(round(a[1] * 2 * QW)), QW)
+                hc = (int(2 * c[0]), int(2 * c[1]), 1)
+                assert oracle_mod.visible(scene, ha, hc), (k, a, c)
+
+
+def test_query_edge_cases(oracle_mod, spm):
+    import torch
+    scene = Scene(40, 30, [_rect_poly(10, 10, 20, 20)], np.asarray([[2, 2]]), None)
+    b = spm.Builder(spm.DeviceScene(scene))
+    b.build()
+    pts = torch.tensor([[-1.0, 5.0], [5.0, 31.0], [10.0, 15.0], [15.0, 15.0], [20.0, 20.0], [0.0, 0.0],
+                        [2.0, 2.0], [40.0, 0.0]], device="cuda")
+    d, p, pxy, pn = spm.query_points(b, pts, cap=8)
+    torch.cuda.synchronize()
+    d, p, pn = d.cpu().numpy(), p.cpu().numpy(), pn.cpu().numpy()
+    assert np.isinf(d[:5]).all() and (p[:5] == -1).all() and (pn[:5] == 0).all()   # outside, on, inside
+    assert abs(d[5] - math.hypot(2, 2)) < 1e-5 and p[5] == 0
+    assert d[6] == 0.0 and p[6] == 0 and pn[6] == 2                                   # at the source
+    assert abs(d[7] - math.hypot(38, 2)) < 1e-4 and p[7] == 0                     # the domain's corner
+    d0, p0 = spm.query_points(b, torch.zeros((0, 2), device="cuda"))
+    assert d0.numel() == 0 and p0.numel() == 0

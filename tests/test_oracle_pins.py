@@ -416,3 +416,64 @@ def test_inside_matches_half_planes(oracle_mod, seed):
     assert exp.any()
     got = oracle_mod.inside(scene, np.arange(W * H, dtype=np.int64))
     assert np.array_equal(got, exp)
+
+
+# ------------------------------------------------ map values at rational points
+QW = 256   # query points are numerators over 2 * QW domain units
+
+
+def _rand_q(rng, W, H, n):
+    return np.stack([rng.integers(0, 2 * W * QW + 1, n), rng.integers(0, 2 * H * QW + 1, n)], 1).astype(np.int64)
+
+
+def test_points_free_space_closed_forms(oracle_mod):
+    rng = np.random.default_rng(3)
+    pts = np.asarray([[3, 3], [30, 7], [12, 25]])
+    seg = np.asarray([[4, 5, 27, 19]])
+    s = Scene(34, 31, [], pts, seg)
+    cost, _ = oracle_mod.costs(s)
+    q = _rand_q(rng, 34, 31, 400)
+    r = oracle_mod.points(s, cost, q, QW)
+    x, y = q[:, 0] / (2 * QW), q[:, 1] / (2 * QW)
+    dp = np.stack([np.hypot(x - a, y - b) for a, b in pts])
+    z = ((x + 1j * y) - complex(4, 5)) * np.conj(complex(23, 14)) / abs(complex(23, 14))
+    L = abs(complex(23, 14))
+    ds = np.where((z.real >= 0) & (z.real <= L), np.abs(z.imag), np.minimum(np.abs(z), np.abs(z - L)))
+    ref = np.minimum(dp.min(0), ds)
+    np.testing.assert_allclose(r["dist64"], ref, atol=1e-9)
+    allc = np.vstack([dp, ds[None]])
+    srt = np.sort(allc, 0)
+    clear = srt[1] - srt[0] > 1e-9
+    assert (r["parent"][clear] == allc.argmin(0)[clear]).all()
+
+
+@pytest.mark.parametrize("box,src", [((10, 8, 22, 20), (3, 14)), ((12, 3, 30, 11), (21, 27))])
+def test_points_rectangle_wraparound(oracle_mod, box, src):
+    rng = np.random.default_rng(box[0])
+    W, H = 36, 34
+    s = Scene(W, H, [_rect_poly(*box)], np.asarray([src]), None)
+    cost, _ = oracle_mod.costs(s)
+    q = _rand_q(rng, W, H, 300)
+    # a few points exactly on the rectangle's boundary and on its corner lines
+    q = np.vstack([q, [[2 * QW * box[0], 2 * QW * 15], [2 * QW * 16, 2 * QW * box[3]], [2 * QW * box[2], 0]]])
+    r = oracle_mod.points(s, cost, q, QW)
+    for k, (X, Y) in enumerate(q):
+        p = (F(int(X), 2 * QW), F(int(Y), 2 * QW))
+        if box[0] <= p[0] <= box[2] and box[1] <= p[1] <= box[3]:
+            assert np.isinf(r["dist64"][k]) and r["parent"][k] == -1
+            continue
+        assert abs(r["dist64"][k] - _rect_geodesic(p, src, box)) < 1e-9, (X, Y)
+
+
+def test_points_agree_with_pixels_at_centres(oracle_mod):
+    from scenegen import random_small
+    for seed in range(4):
+        s = random_small(seed)
+        cost, _ = oracle_mod.costs(s)
+        W, H = s.width, s.height
+        pix = np.arange(W * H, dtype=np.int64)[:: max(1, (W * H) // 500)]
+        q = np.stack([(2 * (pix % W) + 1) * QW, (2 * (pix // W) + 1) * QW], 1)
+        a = oracle_mod.points(s, cost, q, QW)
+        b = oracle_mod.pixels(s, cost, pix)
+        assert np.array_equal(a["parent"], b["parent"])
+        np.testing.assert_array_equal(a["dist64"], b["dist64"])
