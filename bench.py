@@ -9,9 +9,15 @@ value = W * H * G / t_step / 1e6  (Mpixel*generator/s; G = point sources +
 segment sources + corner generators, the dense pair count the paper's method
 shades).
 
-Prints one JSON line.  roofline.achieved = arithmetic lane-ops of the pixel
-kernel (work counts from one instrumented build x fixed ops per unit) / its
-average launch time, against 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz.
+Prints one JSON line.  roofline.achieved = the pixel kernel's algorithmic
+lane-ops per launch / its average launch time, against 256 CUs x 4 SIMDs x
+16 lanes x 2.4 GHz.  Algorithmic work per unit (what the method computes,
+not what culling avoids): 8 lane-ops per pixel-generator pair (the cone
+bound of every pair), 20 more per pixel-segment pair (the closest point),
+8 per accepted candidate and 9 per examined lane-edge visibility test; the
+last two counted by one instrumented build outside the timed region.
+executed_ops_frac gives the same ratio for the operations the kernel
+actually executes after culling.
 """
 from __future__ import annotations
 
@@ -28,6 +34,14 @@ sys.path.insert(0, ROOT)
 METRIC = "SPM build Mpixel·gen/s + % VALU roofline; batched & backward vs plain"
 PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9      # CUs x SIMDs x lanes x clock: one 32-bit VALU op per lane per cycle
 # arithmetic lane-ops per counted unit of the instrumented pixel kernel
+# algorithmic lane-ops per unit of the method
+ALG = {
+    "pair": 8,          # per (pixel, generator): the cone bound cost + |p - g| against the current value
+    "segment_pair": 20, # per (pixel, segment source): the clamped closest point
+    "accept": 8,        # per accepted candidate: square root, add, compare, select
+    "lane_edge": 9,     # per examined (pixel, generator, edge): orientations and compares
+}
+# lane-ops per unit of what the culled kernel executes (instrumented counters)
 OPS = {
     "tile_bound": 12,    # per generator per tile: box gap (4 sub/max), squares, sqrt, scale, add, compare
     "lane_bound": 9,     # per (pixel, generator): 2 sub, mul+mad, sub, cvt, 2 mul, compare
@@ -241,8 +255,11 @@ def main():
     b.build(stream, stats=stats)
     torch.cuda.synchronize()
     s = stats.cpu().numpy().astype(np.float64)
-    ops = (s[1] * 64 * OPS["tile_bound"] + s[2] * OPS["lane_bound"] + s[4] * 64 * OPS["relevance"]
-           + s[5] * OPS["lane_edge"] + s[7] * OPS["accept"])
+    executed = (s[1] * 64 * OPS["tile_bound"] + s[2] * OPS["lane_bound"] + s[4] * 64 * OPS["relevance"]
+                + s[5] * OPS["lane_edge"] + s[7] * OPS["accept"])
+    n_segs = 0 if scene.segs is None else len(scene.segs)
+    ops = (W * H * G * ALG["pair"] + W * H * n_segs * ALG["segment_pair"] + s[7] * ALG["accept"]
+           + s[5] * ALG["lane_edge"])
     t_pix = stage_avg["pixel"] * 1e-3
     achieved = ops / t_pix / 1e12
     peak = PEAK_LANE_OPS / 1e12
@@ -267,6 +284,7 @@ def main():
                    "W": W, "H": H, "G": G, "E": scene.n_vertices, "tile": args.tile},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TOP/s",
                      "frac": achieved / peak, "traffic": _traffic(src_hash), "kernel": "k_pixel",
+                     "executed_ops_frac": executed / t_pix / 1e12 / peak,
                      "ops_per_launch": ops},
         "stages_ms": stage_avg,
         "k_pixel_Mpixel_gen_per_s": pairs / t_pix / 1e6,

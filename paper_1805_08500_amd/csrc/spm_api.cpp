@@ -343,6 +343,7 @@ void plan_add(Plan& p, const Dev& d) {
   p.maxW = std::max(p.maxW, d.W);
   p.maxE = std::max(p.maxE, d.E);
   p.maxNC = std::max(p.maxNC, d.NC);
+  p.tw_mask |= d.tile_w == 4 ? 1 : (d.tile_w == 16 ? 4 : 2);
   p.pixel_lds = std::max(p.pixel_lds, pixel_lds_bytes(d.Gmax, d.E, d.NC));
   p.genvis_lds = std::max(p.genvis_lds, (size_t)d.E * sizeof(EdgeRec) + (size_t)d.NC * 16);
 }

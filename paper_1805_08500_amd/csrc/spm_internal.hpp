@@ -248,6 +248,7 @@ struct BatchSrc {
 struct Plan {
   long long total[STG_COUNT];
   int maxGmax, maxRW, maxW, maxE, maxNC;
+  int tw_mask;   // tile widths present: 1 = 4, 2 = 8, 4 = 16
   size_t pixel_lds, genvis_lds;
 };
 
