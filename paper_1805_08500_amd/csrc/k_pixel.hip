@@ -115,6 +115,10 @@ __device__ __forceinline__ bool box_may_win(float c, int x0, int y0, int x1, int
 
 constexpr int kMaxTried = 8;    // seeds remembered per tile (skipped by the walk)
 constexpr int kSeedTries = 128; // candidates one seed search may reject
+#ifndef SPM_SEED_TRIES_WIDE
+#define SPM_SEED_TRIES_WIDE 4
+#endif
+constexpr int kSeedTriesWide = SPM_SEED_TRIES_WIDE;   // the same when each try recomputes every estimate
 constexpr int kEstCache = 8;    // seed-search estimates kept in registers per lane
 constexpr int kPrioTries = 6;   // candidates after which a seed search raises its wave's priority
 
@@ -159,6 +163,7 @@ __device__ int seed_search(const Geo& geo, const GenRec* sgen, const float* sgco
   float lastv = -INFINITY;
   int lastk = -1;
   for (int it = 0; it < kSeedTries; ++it) {
+    if (!cached && it >= kSeedTriesWide) return -1;
     if (it == kPrioTries) __builtin_amdgcn_s_setprio(2);
     float bv = INFINITY;
     int bk = 0x7fffffff;
