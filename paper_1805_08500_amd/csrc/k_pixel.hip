@@ -369,92 +369,74 @@ __device__ __forceinline__ int tile_work(int tile, int W, int H, int W32, int G,
         UB = fmaxf(fmaxf(ubq[0], ubq[1]), fmaxf(ubq[2], ubq[3]));
       }
     };
-    // Candidates come from three sources, in this order: the previous tile's
-    // winners (distinct values), seed searches from pixels that still have no
-    // value, then the walk in (cost, id) order.  One loop serves all
-    // three so that try_gen is instantiated once.
-    u64 pm = ballot(prevpos >= 0 && prevpos < G);
-    int phase = 0;
-    int samples_left = samples;
-    int base = -64;
-    u64 cm = 0;
-    const int g = lane;   // this lane's generator within a walk batch is base + g
-    float c = INFINITY;
-    int4 bb = make_int4(0, 0, 0, 0);
-    auto bound = [&]() {
-      return base + g < G && (box_may_win(c, bb.x, bb.y, bb.z, bb.w, qx0, qy0, qx1 - 2, qy1 - 2, ubq[0]) ||
-                              box_may_win(c, bb.x, bb.y, bb.z, bb.w, qx1, qy0, qx1 + TW - 2, qy1 - 2, ubq[1]) ||
-                              box_may_win(c, bb.x, bb.y, bb.z, bb.w, qx0, qy1, qx1 - 2, qy1 + TH - 2, ubq[2]) ||
-                              box_may_win(c, bb.x, bb.y, bb.z, bb.w, qx1, qy1, qx1 + TW - 2, qy1 + TH - 2, ubq[3]));
-    };
-    for (;;) {
-      int k = -1;
-      if (phase == 0) {
-        if (pm && ntried < kMaxTried) {
+    // Seeds first: the previous tile's winners (distinct values), then seed
+    // searches from pixels that still have no value.  Each is evaluated
+    // exactly for every lane and remembered, so the walk skips it.
+    {
+      u64 pm = ballot(prevpos >= 0 && prevpos < G);
+      int samples_left = samples;
+      while (ntried < kMaxTried) {
+        int k = -1;
+        if (pm) {
           k = readlane_i(prevpos, first_bit(pm));
           pm &= ~ballot(prevpos == k);
         } else {
-          phase = 1;
-        }
-      }
-      if (phase == 1) {
-        const u64 un = ballot(active && best == INFINITY);
-        if (samples_left > 0 && ntried < kMaxTried && un) {
+          const u64 un = ballot(active && best == INFINITY);
+          if (samples_left <= 0 || !un) break;
           --samples_left;
           // sample the first pixel without a value, starting from the tile centre
           const u64 hi = un & ~((1ull << ((TH / 2) * TW + TW / 2)) - 1ull);
           const int l = first_bit(hi ? hi : un);
-          const int k2 = seed_search<STATS>(geo, sgen, sgcost, sgbb, G, readlane_i(px, l), readlane_i(py, l), st);
-          bool seen = k2 < 0;
+          k = seed_search<STATS>(geo, sgen, sgcost, sgbb, G, readlane_i(px, l), readlane_i(py, l), st);
+          bool seen = k < 0;
 #pragma unroll
-          for (int t = 0; t < kMaxTried; ++t) seen |= t < ntried && tried[t] == k2;
-          if (seen) phase = 2;   // nothing new to try: the walk decides
-          else k = k2;
-        } else {
-          phase = 2;
+          for (int t = 0; t < kMaxTried; ++t) seen |= t < ntried && tried[t] == k;
+          if (seen) break;   // nothing new to try: the walk decides
         }
-      }
-      float gc;
-      int x0, y0, x1, y1;
-      if (phase < 2) {
-        // a seed: remember it so that the walk skips it
 #pragma unroll
         for (int t = 0; t < kMaxTried; ++t)
           if (t == ntried) tried[t] = k;
         ntried = min(ntried + 1, kMaxTried);
         const int4 kb = sgbb[k];
-        gc = unif(sgcost[k]);
-        x0 = uni(kb.x); y0 = uni(kb.y); x1 = uni(kb.z); y1 = uni(kb.w);
-      } else {
-        if (!cm) {
-          // next batch of the walk: lane-parallel tile bound against the four quadrants
-          base += 64;
-          if (base >= G || sgcost[base] > UB) break;
-          if (STATS) st[ST_BATCHES] += 1;
-          c = INFINITY;
-          bb = make_int4(0, 0, 0, 0);
-          if (base + g < G) {
-            c = sgcost[base + g];
-            bb = sgbb[base + g];
-          }
-          cm = ballot(bound());
+        try_gen(k, unif(sgcost[k]), uni(kb.x), uni(kb.y), uni(kb.z), uni(kb.w));
+      }
+    }
+    // the walk in (cost, id) order
+    const int g = lane;   // this lane's generator within a walk batch is base + g
+    for (int base = 0; base < G; base += 64) {
+      if (sgcost[base] > UB) break;
+      if (STATS) st[ST_BATCHES] += 1;
+      // lane-parallel tile bound against the four quadrants
+      float c = INFINITY;
+      int4 bb = make_int4(0, 0, 0, 0);
+      if (base + g < G) {
+        c = sgcost[base + g];
+        bb = sgbb[base + g];
+      }
+      auto bound = [&]() {
+        return base + g < G && (box_may_win(c, bb.x, bb.y, bb.z, bb.w, qx0, qy0, qx1 - 2, qy1 - 2, ubq[0]) ||
+                                box_may_win(c, bb.x, bb.y, bb.z, bb.w, qx1, qy0, qx1 + TW - 2, qy1 - 2, ubq[1]) ||
+                                box_may_win(c, bb.x, bb.y, bb.z, bb.w, qx0, qy1, qx1 - 2, qy1 + TH - 2, ubq[2]) ||
+                                box_may_win(c, bb.x, bb.y, bb.z, bb.w, qx1, qy1, qx1 + TW - 2, qy1 + TH - 2, ubq[3]));
+      };
+      u64 cm = ballot(bound());
 #pragma unroll
-          for (int t = 0; t < kMaxTried; ++t) {
-            const int o = tried[t] - base;
-            if (t < ntried && o >= 0 && o < 64) cm &= ~(1ull << o);
-          }
-          continue;
-        }
+      for (int t = 0; t < kMaxTried; ++t) {
+        const int o = tried[t] - base;
+        if (t < ntried && o >= 0 && o < 64) cm &= ~(1ull << o);
+      }
+      bool done = false;
+      while (cm) {
         const int jl = first_bit(cm);
         cm &= cm - 1;
-        gc = readlane_f(c, jl);
-        if (gc > UB) break;
-        k = base + jl;
-        x0 = readlane_i(bb.x, jl); y0 = readlane_i(bb.y, jl); x1 = readlane_i(bb.z, jl); y1 = readlane_i(bb.w, jl);
+        const float gc = readlane_f(c, jl);
+        if (gc > UB) { done = true; break; }
+        const float ub0 = UB;
+        try_gen(base + jl, gc, readlane_i(bb.x, jl), readlane_i(bb.y, jl), readlane_i(bb.z, jl),
+                readlane_i(bb.w, jl));
+        if (UB != ub0) cm &= ballot(bound());   // the bounds tightened: drop what they now exclude
       }
-      const float ub0 = UB;
-      try_gen(k, gc, x0, y0, x1, y1);
-      if (phase == 2 && UB != ub0) cm &= ballot(bound());   // the bounds tightened: drop what they now exclude
+      if (done) break;
     }
   }
   if (valid) {
