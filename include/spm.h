@@ -77,7 +77,8 @@ typedef struct {
 } spm_scene;
 
 /* Outputs of a build: device memory owned by the caller.  max_gen comes from
- * spm_query_sizes. */
+ * spm_query_sizes; the generator arrays hold *n_gen entries, and their entries
+ * from *n_gen up to max_gen are left as they were (unspecified). */
 typedef struct {
   float* dist;          /* [H * W] lambda* in domain units; +inf inside or on an obstacle, or unreachable */
   int32_t* parent;      /* [H * W] generator id of the winning cone; -1 where dist is +inf */

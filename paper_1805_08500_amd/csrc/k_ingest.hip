@@ -135,6 +135,7 @@ __global__ __launch_bounds__(1024) void k_gen_table(S src) {
     d.n_gen[0] = running;
   }
   if (tid < kQueues) d.qctr[tid * kQueueStride] = 0;
+  if (tid < kOrderBins) d.obins[tid] = 0;
 }
 
 // One wavefront per edge: its rank among the Morton keys, then a scatter into

@@ -115,12 +115,183 @@ __device__ __forceinline__ bool box_may_win(float c, int x0, int y0, int x1, int
 
 constexpr int kMaxTried = 8;    // seeds remembered per tile (skipped by the walk)
 constexpr int kSeedTries = 128; // candidates one seed search may reject
-#ifndef SPM_SEED_TRIES_WIDE
-#define SPM_SEED_TRIES_WIDE 4
+#ifndef SPM_SEED_TRIES_UNCACHED
+#define SPM_SEED_TRIES_UNCACHED 4
 #endif
-constexpr int kSeedTriesWide = SPM_SEED_TRIES_WIDE;   // the same when each try recomputes every estimate
+constexpr int kSeedTriesUncached = SPM_SEED_TRIES_UNCACHED;   // the same when each try recomputes every estimate
 constexpr int kEstCache = 8;    // seed-search estimates kept in registers per lane
 constexpr int kPrioTries = 6;   // candidates after which a seed search raises its wave's priority
+#ifndef SPM_SEED_WIDE
+#define SPM_SEED_WIDE 4
+#endif
+constexpr int kSeedWide = SPM_SEED_WIDE;   // candidates per round once a seed search has made kPrioTries tries
+#ifndef SPM_SEED_SHARE
+#define SPM_SEED_SHARE 1   // later seed searches of a tile skip the candidates earlier ones tried
+#endif
+
+// The segment [P, q] for the cheap seed test: a proper crossing with edge r
+// (endpoints strictly on opposite sides of line P-q and P, q strictly on
+// opposite sides of the edge line).
+__device__ __forceinline__ bool seed_crosses(const EdgeRec& r, int px, int py, float qx, float qy) {
+  const float dqx = qx - px, dqy = qy - py;
+  const float o1 = dqx * (float)(r.wy - py) - dqy * (float)(r.wx - px);
+  const float o2 = dqx * (float)(r.vy - py) - dqy * (float)(r.vx - px);
+  const float e1 = (float)(r.a * px + r.b * py + r.c);
+  const float e2 = r.a * qx + r.b * qy + (float)r.c;
+  return o1 * o2 < 0.0f && e1 * e2 < 0.0f;
+}
+
+// The point of generator h that P sees (the generator, or a segment's closest
+// point); false when h is a corner and the direction toward P enters its own
+// interior angle (P cannot see it).
+__device__ __forceinline__ bool seed_target(const GenRec* sgen, int h, int px, int py, float& qx, float& qy) {
+  const int kind = sgen[h].kind;
+  const int gx = sgen[h].x, gy = sgen[h].y;
+  qx = (float)gx;
+  qy = (float)gy;
+  if (kind == SPM_GEN_SEGMENT) {
+    const float ex = (float)(sgen[h].x2 - gx), ey = (float)(sgen[h].y2 - gy);
+    const float t = fminf(fmaxf(((px - gx) * ex + (py - gy) * ey) * frcp(ex * ex + ey * ey), 0.0f), 1.0f);
+    qx = gx + t * ex;
+    qy = gy + t * ey;
+    return true;
+  }
+  return !(kind == SPM_GEN_VERTEX &&
+           into_interior(sgen[h].ux, sgen[h].uy, gx, gy, sgen[h].nx, sgen[h].ny, px - gx, py - gy));
+}
+
+// Takes the least (estimate, generator) pair out of the register cache (lane l,
+// slot s holds generator l + 64 s) and returns its generator, or -1 when the
+// cache is empty; v = its estimate.
+__device__ __forceinline__ int seed_pop(float (&ec)[kEstCache], unsigned& rej, float& v) {
+  const int lane = lane_id();
+  float bv = INFINITY;
+  int bs = 0;
+#pragma unroll
+  for (int s = 0; s < kEstCache; ++s)
+    if (ec[s] < bv) { bv = ec[s]; bs = s; }
+  // estimates are >= 0, so their bits order as unsigned; ties go to the lower lane (the lower generator
+  // among equal estimates of one slot)
+  const unsigned key = __float_as_uint(bv);
+  const unsigned mk = wave_min_u32(key);
+  if (mk >= 0x7f800000u) return -1;
+  const u64 wm = ballot(key == mk);
+  if (!wm) return -1;
+  const int wl = first_bit(wm);
+  const int ws = readlane(bs, wl);
+#pragma unroll
+  for (int s = 0; s < kEstCache; ++s)
+    if (lane == wl && s == ws) { ec[s] = INFINITY; rej |= 1u << s; }
+  v = __uint_as_float(mk);
+  return wl + 64 * ws;
+}
+
+// Puts generator k with estimate v back into the cache (undoes seed_pop).
+__device__ __forceinline__ void seed_unpop(float (&ec)[kEstCache], unsigned& rej, int k, float v) {
+  const int lane = lane_id();
+#pragma unroll
+  for (int s = 0; s < kEstCache; ++s)
+    if (lane + 64 * s == k) { ec[s] = v; rej &= ~(1u << s); }
+}
+
+// One round of a long seed search: the next kSeedWide candidates at once, the
+// wavefront split into groups of 64 / kSeedWide lanes, group g testing the
+// g-th least remaining candidate against the edges of the chunks its segment's
+// box meets (each lane kSeedWide edges of a chunk per step).  Returns the
+// least candidate of the round that passes (the one a one-at-a-time search
+// would return), -1 if none does, -2 if the cache is empty; n = candidates
+// taken.  Candidates after the one returned go back into the cache.
+template <bool STATS>
+__device__ int seed_round_wide(const Geo& geo, const GenRec* sgen, int px, int py, float (&ec)[kEstCache],
+                               unsigned& rej, int& n, u64* st) {
+  constexpr int GL = 64 / kSeedWide;   // lanes per group
+  const int lane = lane_id();
+  const int grp = lane / GL, gl = lane % GL;
+  int my = -1;
+  int pk[kSeedWide];
+  float pv[kSeedWide];
+  n = 0;
+#pragma unroll
+  for (int r = 0; r < kSeedWide; ++r) {
+    pk[r] = seed_pop(ec, rej, pv[r]);
+    if (pk[r] < 0) break;
+    if (grp == r) my = pk[r];
+    ++n;
+  }
+  if (n == 0) return -2;
+  // the candidate of group g passes: give back the later ones
+  auto found = [&](int g) -> int {
+#pragma unroll
+    for (int r = 0; r < kSeedWide; ++r)
+      if (r > g && r < n) seed_unpop(ec, rej, pk[r], pv[r]);
+    n = g + 1;
+    int k = pk[0];
+#pragma unroll
+    for (int r = 1; r < kSeedWide; ++r)
+      if (r == g) k = pk[r];
+    return k;
+  };
+  float qx = (float)px, qy = (float)py;
+  bool live = my >= 0 && seed_target(sgen, my, px, py, qx, qy);
+  const int bx0 = min(px, (int)floorf(qx)), bx1 = max(px, (int)ceilf(qx));
+  const int by0 = min(py, (int)floorf(qy)), by1 = max(py, (int)ceilf(qy));
+  // groups still in the running (bit g), as seen by every lane
+  unsigned alive = 0;
+  {
+    const u64 lb = ballot(live);
+#pragma unroll
+    for (int g = 0; g < kSeedWide; ++g)
+      if ((lb >> (g * GL)) & 1ull) alive |= 1u << g;
+  }
+  for (int cb = 0; cb < geo.NC && alive; cb += kWave) {
+    const bool last = cb + kWave >= geo.NC;
+    const int ci = cb + lane;
+    int4 cbx = make_int4(1, 1, 0, 0);
+    if (ci < geo.NC) cbx = geo.chunks[ci];
+    u64 hm[kSeedWide];
+#pragma unroll
+    for (int g = 0; g < kSeedWide; ++g) {
+      const int gx0 = readlane(bx0, g * GL), gx1 = readlane(bx1, g * GL);
+      const int gy0 = readlane(by0, g * GL), gy1 = readlane(by1, g * GL);
+      hm[g] = ((alive >> g) & 1u) ? ballot(ci < geo.NC && cbx.x <= gx1 && cbx.z >= gx0 && cbx.y <= gy1 &&
+                                           cbx.w >= gy0)
+                                  : 0ull;
+    }
+    for (;;) {
+      // the least live candidate has no chunk left: nothing can block it any more
+      if (last && alive) {
+        const int g0 = __builtin_ctz(alive);
+        if (!hm[g0]) return found(g0);
+      }
+      int c = -1;
+      bool any = false;
+#pragma unroll
+      for (int g = 0; g < kSeedWide; ++g) {
+        if (hm[g]) {
+          const int cg = cb + first_bit(hm[g]);
+          hm[g] &= hm[g] - 1;
+          if (grp == g) c = cg;
+          any = true;
+        }
+      }
+      if (!any) break;
+      if (STATS) st[ST_RELEV] += 1;
+      bool x = false;
+      if (c >= 0) {
+#pragma unroll
+        for (int m = 0; m < kSeedWide; ++m) {
+          const int e = c * kChunk + gl + GL * m;
+          if (e < geo.E) x = x || seed_crosses(geo.edges[e], px, py, qx, qy);
+        }
+      }
+      const u64 xb = ballot(x);
+#pragma unroll
+      for (int g = 0; g < kSeedWide; ++g)
+        if ((xb >> (g * GL)) & ((GL == 64) ? ~0ull : ((1ull << GL) - 1ull))) { alive &= ~(1u << g); hm[g] = 0; }
+    }
+  }
+  return alive ? found(__builtin_ctz(alive)) : -1;
+}
 
 // Seed search for one free pixel P (doubled coordinates, wave-uniform): try
 // generators in order of cost + |P - x_g(P)| -- the exact value whenever g is
@@ -129,11 +300,14 @@ constexpr int kPrioTries = 6;   // candidates after which a seed search raises i
 // crossing of [P, x_g] with an edge, or a start into a corner's own interior
 // angle, blocks.  It may accept a grazing path the exact rule rejects; such a
 // seed costs time, never correctness, because the tile re-evaluates every
-// seed exactly.  Returns the sorted position, or -1 after kSeedTries
-// rejections.
+// seed exactly.  After kPrioTries single tries a search that is still going
+// takes its candidates kSeedWide at a time.  Returns the sorted position, or
+// -1 after about kSeedTries rejections.
+//   rej: per lane, the cache slots that earlier searches of the tile have
+//        taken; they are not tried again.
 template <bool STATS>
 __device__ int seed_search(const Geo& geo, const GenRec* sgen, const float* sgcost, const int4* sgbb, int G, int px,
-                           int py, u64* st) {
+                           int py, unsigned& rej, u64* st) {
   const int lane = lane_id();
   // cost + |P - x_g(P)| of sorted generator h
   auto est_of = [&](int h) -> float {
@@ -157,63 +331,48 @@ __device__ int seed_search(const Geo& geo, const GenRec* sgen, const float* sgco
 #pragma unroll
   for (int s = 0; s < kEstCache; ++s) {
     const int h = lane + 64 * s;
-    ec[s] = (cached && h < G) ? est_of(h) : INFINITY;
+    ec[s] = (cached && h < G && !(SPM_SEED_SHARE && ((rej >> s) & 1u))) ? est_of(h) : INFINITY;
   }
   if (STATS && cached) st[ST_BATCHES] += (G + 63) / 64;
   float lastv = -INFINITY;
   int lastk = -1;
-  for (int it = 0; it < kSeedTries; ++it) {
-    if (!cached && it >= kSeedTriesWide) return -1;
-    if (it == kPrioTries) __builtin_amdgcn_s_setprio(2);
-    float bv = INFINITY;
-    int bk = 0x7fffffff;
+  for (int it = 0; it < kSeedTries;) {
+    if (!cached && it >= kSeedTriesUncached) return -1;
+    if (it >= kPrioTries) __builtin_amdgcn_s_setprio(2);
+    if (cached && it >= kPrioTries) {
+      int n = 0;
+      const int k = seed_round_wide<STATS>(geo, sgen, px, py, ec, rej, n, st);
+      if (k >= 0) return k;
+      if (k == -2) return -1;
+      it += n;
+      continue;
+    }
+    ++it;
+    int bk;
     if (cached) {
-#pragma unroll
-      for (int s = 0; s < kEstCache; ++s)
-        if (ec[s] < bv) { bv = ec[s]; bk = lane + 64 * s; }
+      float v;
+      bk = seed_pop(ec, rej, v);
+      if (bk < 0) return -1;
     } else {
       if (STATS) st[ST_BATCHES] += (G + 63) / 64;
+      float bv = INFINITY;
+      bk = 0x7fffffff;
       for (int h = lane; h < G; h += 64) {
         const float v = est_of(h);
         // the least (v, h) above the previous candidate
         if ((v > lastv || (v == lastv && h > lastk)) && (v < bv || (v == bv && h < bk))) { bv = v; bk = h; }
       }
-    }
-    // the least candidate over the wavefront (estimates are >= 0, so their bits order as unsigned)
-    const unsigned key = __float_as_uint(bv);
-    const unsigned mk = wave_min_u32(key);
-    if (mk >= 0x7f800000u) return -1;   // none left
-    if (cached) {
-      const u64 wm = ballot(key == mk);
-      if (!wm) return -1;
-      bk = readlane(bk, first_bit(wm));
-    } else {
+      const unsigned key = __float_as_uint(bv);
+      const unsigned mk = wave_min_u32(key);
+      if (mk >= 0x7f800000u) return -1;   // none left
       // lanes holding the least estimate: the least generator among them
       bk = (int)wave_min_u32(key == mk ? (unsigned)bk : 0xffffffffu);
+      if (bk < 0 || bk >= G) return -1;
+      lastv = __uint_as_float(mk);
+      lastk = bk;
     }
-    if (bk < 0 || bk >= G) return -1;
-    lastv = __uint_as_float(mk);
-    lastk = bk;
-    if (cached) {
-#pragma unroll
-      for (int s = 0; s < kEstCache; ++s)
-        if (lane + 64 * s == bk) ec[s] = INFINITY;
-    }
-    // the candidate's point seen from P: the generator, or the segment's closest point
-    const int kind = uni(sgen[bk].kind);
-    const int gx = uni(sgen[bk].x), gy = uni(sgen[bk].y);
-    float qx = (float)gx, qy = (float)gy;
-    if (kind == SPM_GEN_SEGMENT) {
-      const float ex = (float)(uni(sgen[bk].x2) - gx), ey = (float)(uni(sgen[bk].y2) - gy);
-      const float t = fminf(fmaxf(((px - gx) * ex + (py - gy) * ey) * frcp(ex * ex + ey * ey), 0.0f), 1.0f);
-      qx = gx + t * ex;
-      qy = gy + t * ey;
-    } else if (kind == SPM_GEN_VERTEX &&
-               into_interior(uni(sgen[bk].ux), uni(sgen[bk].uy), gx, gy, uni(sgen[bk].nx), uni(sgen[bk].ny),
-                             px - gx, py - gy)) {
-      continue;
-    }
-    const float dqx = qx - px, dqy = qy - py;
+    float qx, qy;
+    if (!seed_target(sgen, bk, px, py, qx, qy)) continue;
     const int bx0 = min(px, (int)floorf(qx)), bx1 = max(px, (int)ceilf(qx));
     const int by0 = min(py, (int)floorf(qy)), by1 = max(py, (int)ceilf(qy));
     bool blocked = false;
@@ -229,15 +388,7 @@ __device__ int seed_search(const Geo& geo, const GenRec* sgen, const float* sgco
         const int e = (cb + first_bit(cm)) * kChunk + lane;
         cm &= cm - 1;
         if (STATS) st[ST_RELEV] += 1;
-        bool x = false;
-        if (e < geo.E) {
-          const EdgeRec r = geo.edges[e];
-          const float o1 = dqx * (float)(r.wy - py) - dqy * (float)(r.wx - px);
-          const float o2 = dqx * (float)(r.vy - py) - dqy * (float)(r.vx - px);
-          const float e1 = (float)(r.a * px + r.b * py + r.c);
-          const float e2 = r.a * qx + r.b * qy + (float)r.c;
-          x = o1 * o2 < 0.0f && e1 * e2 < 0.0f;
-        }
+        const bool x = e < geo.E && seed_crosses(geo.edges[e], px, py, qx, qy);
         if (ballot(x)) {
           blocked = true;
           break;
@@ -375,6 +526,7 @@ __device__ __forceinline__ int tile_work(int tile, int W, int H, int W32, int G,
     {
       u64 pm = ballot(prevpos >= 0 && prevpos < G);
       int samples_left = samples;
+      unsigned rej = 0;   // per lane: estimate-cache slots an earlier search of this tile has tried
       while (ntried < kMaxTried) {
         int k = -1;
         if (pm) {
@@ -387,7 +539,7 @@ __device__ __forceinline__ int tile_work(int tile, int W, int H, int W32, int G,
           // sample the first pixel without a value, starting from the tile centre
           const u64 hi = un & ~((1ull << ((TH / 2) * TW + TW / 2)) - 1ull);
           const int l = first_bit(hi ? hi : un);
-          k = seed_search<STATS>(geo, sgen, sgcost, sgbb, G, readlane_i(px, l), readlane_i(py, l), st);
+          k = seed_search<STATS>(geo, sgen, sgcost, sgbb, G, readlane_i(px, l), readlane_i(py, l), rej, st);
           bool seen = k < 0;
 #pragma unroll
           for (int t = 0; t < kMaxTried; ++t) seen |= t < ntried && tried[t] == k;
@@ -449,6 +601,9 @@ __device__ __forceinline__ int tile_work(int tile, int W, int H, int W32, int G,
 }
 
 constexpr int kPixelThreads = 512;
+#ifndef SPM_TILE_ORDER
+#define SPM_TILE_ORDER 1   // hand out work items by k_tile_order's classes (0: row-major)
+#endif
 constexpr size_t kPixelLdsMax = 64 * 1024;
 #ifndef SPM_PIXEL_MIN_WAVES
 #define SPM_PIXEL_MIN_WAVES 4   // waves per SIMD the register budget of k_pixel is sized for
@@ -458,6 +613,69 @@ size_t pixel_lds_bytes(int Gmax, int E, int NC) {
   return (size_t)Gmax * (sizeof(GenRec) + 4 + 16) + 16 + (size_t)E * sizeof(EdgeRec) + (size_t)NC * 16;
 }
 
+// Work order of the pixel stage.  How long a tile takes grows with how many
+// generators come near to winning in it: far (in geodesic terms) from the
+// sources, behind obstacles, the cost-ordered walk and the seed searches meet
+// many candidates that the tile cannot see.  The lower bound
+//   lb = min_g cost(g) + |c - box(g)|
+// at the centre c of a work item ranks items well by that time, so items are
+// handed out class by class, largest lb first (kOrderBins classes of equal
+// width over 0 .. (W + H) / 2 domain units, the last one open-ended): the long
+// items start at the beginning of the launch instead of ending it.  No output
+// depends on the order in which items run.  One wavefront per item, lanes
+// over the cost-sorted generators; each workgroup takes kOrderItems items and
+// appends them to their classes with one atomic per class.
+constexpr int kOrderThreads = 512;
+constexpr int kOrderItems = 64;
+
+template <int TW>
+__global__ __launch_bounds__(kOrderThreads) void k_tile_order(int W, int H, int strip, const int* __restrict__ misc,
+                                                              const float* __restrict__ sgcost,
+                                                              const int4* __restrict__ sgbb, int* __restrict__ obins,
+                                                              int* __restrict__ order, int ocap) {
+  constexpr int TH = 64 / TW;
+  constexpr int kPerWave = kOrderItems / (kOrderThreads / 64);
+  __shared__ int lcount[kOrderBins], lbase[kOrderBins];
+  __shared__ int icls[kOrderItems], islot[kOrderItems];
+  const int tid = threadIdx.x, lane = lane_id(), wv = tid / 64;
+  if (tid < kOrderBins) lcount[tid] = 0;
+  __syncthreads();
+  const int G = misc[MISC_REACHED];
+  const int ntx = (W + TW - 1) / TW, nty = (H + TH - 1) / TH;
+  const int spr = (ntx + strip - 1) / strip;
+  const int nitems = spr * nty;
+  const float scale = (float)(2 * kOrderBins) / (float)(W + H);
+  for (int k = 0; k < kPerWave; ++k) {
+    const int li = wv * kPerWave + k;
+    const int item = blockIdx.x * kOrderItems + li;
+    if (item >= nitems) break;
+    const int ty = item / spr, sx = item - ty * spr;
+    const int t0 = sx * strip, t1 = min(t0 + strip, ntx);
+    const int cx = (t0 + t1) * TW, cy = (2 * ty + 1) * TH;   // item centre, doubled coordinates
+    float lb = INFINITY;
+    for (int h = lane; h < G; h += 64) {
+      const int4 b = sgbb[h];
+      const float dx = (float)max(max(b.x - cx, cx - b.z), 0), dy = (float)max(max(b.y - cy, cy - b.w), 0);
+      lb = fminf(lb, sgcost[h] + 0.5f * fsqrt(dx * dx + dy * dy));
+    }
+    // lb >= 0, so its bits order as unsigned
+    const float f = __uint_as_float(wave_min_u32(__float_as_uint(lb))) * scale;
+    const int c = f < (float)(kOrderBins - 1) ? (int)f : kOrderBins - 1;
+    if (lane == 0) {
+      const int cls = kOrderBins - 1 - c;
+      icls[li] = cls;
+      islot[li] = atomicAdd(&lcount[cls], 1);
+    }
+  }
+  __syncthreads();
+  if (tid < kOrderBins) lbase[tid] = lcount[tid] ? atomicAdd(&obins[tid], lcount[tid]) : 0;
+  __syncthreads();
+  if (tid < kOrderItems) {
+    const int item = blockIdx.x * kOrderItems + tid;
+    if (item < nitems) order[(size_t)icls[tid] * ocap + lbase[icls[tid]] + islot[tid]] = item;
+  }
+}
+
 // Persistent kernel.  A work item is a strip of `strip` consecutive tiles of
 // one tile row, done left to right, so that each tile after the first is
 // seeded with the winners of the tile to its left.  Every wavefront takes its
@@ -465,7 +683,8 @@ size_t pixel_lds_bytes(int Gmax, int E, int NC) {
 // queues (qctr), one per group of workgroups that the dispatcher places on
 // the same XCD, each handing out every kQueues-th item.  That keeps the
 // number of contended atomics small: a single queue for every wavefront of
-// the chip serialises at one address.  LDSD: the cost-sorted generator
+// the chip serialises at one address.  Queue positions map to items through
+// the work order of k_tile_order when one is given (order != nullptr).  LDSD: the cost-sorted generator
 // table, the edges and the chunk boxes are first staged in LDS, so the
 // wave-uniform reads of the hot loops are LDS broadcasts instead of L2 round
 // trips.
@@ -480,9 +699,12 @@ __global__ __launch_bounds__(kPixelThreads, SPM_PIXEL_MIN_WAVES) void k_pixel(in
                                                          const int4* __restrict__ chunks_g, int E, int NC,
                                                          float* __restrict__ dist, int* __restrict__ parent,
                                                          int strip, int samples, int* __restrict__ qctr,
+                                                         const int* __restrict__ obins,
+                                                         const int* __restrict__ order, int ocap,
                                                          u64* __restrict__ stats) {
   constexpr int TH = 64 / TW;
   extern __shared__ int4 smem[];
+  __shared__ int opre[kOrderBins];   // first queue position of each work class
   const int G = misc[MISC_REACHED];
   const GenRec* sgen = sgen_g;
   const float* sgcost = sgcost_g;
@@ -508,6 +730,18 @@ __global__ __launch_bounds__(kPixelThreads, SPM_PIXEL_MIN_WAVES) void k_pixel(in
     geo.edges = s_edges;
     geo.chunks = s_chunks;
   }
+  if (order && threadIdx.x < 64) {
+    // exclusive prefix of the class sizes
+    const int l = lane_id();
+    int v = l < kOrderBins ? obins[l] : 0;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const int u = __shfl_up(v, o, 64);
+      if (l >= o) v += u;
+    }
+    if (l < kOrderBins) opre[l] = v - obins[l];
+  }
+  __syncthreads();
   const int ntx = (W + TW - 1) / TW, nty = (H + TH - 1) / TH;
   const int spr = (ntx + strip - 1) / strip;   // strips per tile row
   const int nitems = spr * nty;
@@ -516,8 +750,17 @@ __global__ __launch_bounds__(kPixelThreads, SPM_PIXEL_MIN_WAVES) void k_pixel(in
   const int nw = gridDim.x * wpb;                       // wavefronts in the grid
   const int nq = min(kQueues, (int)gridDim.x);          // queues in use (each has a workgroup)
   const int q = blockIdx.x % nq;
-  int item = blockIdx.x * wpb + (threadIdx.x / kWave);  // first item: the wavefront's index
-  while (item < nitems) {
+  // the item at queue position n: the (n - opre[c])-th of class c, the last class starting at or before n
+  auto item_at = [&](int n) -> int {
+    if (!order) return n;
+    const int l = lane_id();
+    const int c = __popcll(ballot(l < kOrderBins && opre[l] <= n)) - 1;
+    const int it = order[(size_t)c * ocap + (n - opre[c])];
+    return (unsigned)it < (unsigned)nitems ? it : n;
+  };
+  int pos = blockIdx.x * wpb + (threadIdx.x / kWave);  // first position: the wavefront's index
+  while (pos < nitems) {
+    const int item = uni(item_at(pos));
     const int ty = item / spr, sx = item - ty * spr;
     const int t0 = sx * strip, t1 = min(t0 + strip, ntx);
     int prev = -1;
@@ -527,7 +770,7 @@ __global__ __launch_bounds__(kPixelThreads, SPM_PIXEL_MIN_WAVES) void k_pixel(in
     int n = 0;
     if (lane_id() == 0) n = atomicAdd(&qctr[q * kQueueStride], 1);
     n = __shfl(n, 0, 64);
-    item = nw + q + nq * n;
+    pos = nw + q + nq * n;
   }
   if (STATS && lane_id() == 0) {
 #pragma unroll
@@ -560,9 +803,17 @@ static hipError_t launch_variant(const Dev& d, hipStream_t s, size_t shm) {
   const long long max_blocks = (waves_needed + (kPixelThreads / 64) - 1) / (kPixelThreads / 64);
   if (blocks > max_blocks) blocks = max_blocks;
   if (blocks < 1) blocks = 1;
+  // the work order matters only when some items wait for a free wavefront
+  const int* order = nullptr;
+  if (SPM_TILE_ORDER && waves_needed > blocks * (kPixelThreads / 64)) {
+    hipLaunchKernelGGL(k_tile_order<TW>, dim3((unsigned)((waves_needed + kOrderItems - 1) / kOrderItems)),
+                       dim3(kOrderThreads), 0, s, d.W, d.H, d.strip, d.misc, d.sgcost, d.sgbb, d.obins, d.order,
+                       d.ocap);
+    order = d.order;
+  }
   hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(kPixelThreads), shm, s, d.W, d.H, d.W32, d.Gmax, d.misc,
                      d.inside, d.sgen, d.sgcost, d.sgbb, d.edges, d.ext, d.chunks, d.E, d.NC, d.dist, d.parent,
-                     d.strip, d.samples, d.qctr, d.stats);
+                     d.strip, d.samples, d.qctr, d.obins, order, d.ocap, d.stats);
   return hipGetLastError();
 }
 

@@ -324,6 +324,9 @@ void fill_dev(Dev& d, const spm_scene* s, const spm_out* out, char* ws, const La
   d.parcan = (int*)(ws + L.off_parpos);
   d.rmask = (u64*)(ws + L.off_rmask);
   d.qctr = (int*)(ws + L.off_qctr);
+  d.obins = (int*)(ws + L.off_obins);
+  d.order = (int*)(ws + L.off_order);
+  d.ocap = L.ocap;
   d.dist = out->dist; d.parent = out->parent; d.gen_kind = out->gen_kind; d.gen_xy = out->gen_xy;
   d.gen_cost = out->gen_cost; d.gen_parent = out->gen_parent; d.n_gen = out->n_gen;
   d.tile_w = tw; d.tile_h = 64 / tw;

@@ -31,6 +31,7 @@ constexpr int kDefaultSamples = 3;    // seed searches per pixel tile
 constexpr int kMaxStrip = 64;
 constexpr int kQueues = 8;         // pixel-stage work queues (one per XCD)
 constexpr int kQueueStride = 32;   // ints between queue counters (one 128-byte line each)
+constexpr int kOrderBins = 32;     // pixel-stage work classes (tiles ranked by a distance lower bound)
 
 // One obstacle edge w -> v (obstacle on the left), with its line function
 // E(x, y) = a x + b y + c, positive on the obstacle side.
@@ -59,12 +60,19 @@ static_assert(sizeof(GenRec) == 64, "GenRec must be 64 bytes");
 // misc ints in the workspace
 enum { MISC_G = 0, MISC_REACHED = 1, MISC_ROUNDS = 2, MISC_TILE_CTR = 3, MISC_N = 16 };
 
+__host__ __device__ inline int tiles_of(int W, int H, int tw) {
+  const int th = 64 / tw;
+  return ((W + tw - 1) / tw) * ((H + th - 1) / th);
+}
+
 struct Layout {
   int W, H, nv, np, ns, np_polys;
   int E, NC, Gmax, RW, W32;
   size_t off_edges_raw, off_ext_raw, off_keys, off_edges, off_ext, off_chunks, off_convex;
   size_t off_gens, off_vis, off_sgen, off_sgcost, off_sgbb, off_inside, off_cost64, off_gxy, off_misc;
   size_t off_vsorted, off_vtx2gid, off_gorder, off_costpos, off_parpos, off_qctr, off_rmask;
+  size_t off_obins, off_order;
+  int ocap;   // capacity of each work class (the most tiles any tile shape gives)
   size_t total;
 };
 
@@ -105,6 +113,11 @@ inline Layout make_layout(int W, int H, int n_polys, int nv, int np, int ns) {
   L.off_parpos = take(G1 * sizeof(int));
   L.off_qctr = take(kQueues * kQueueStride * sizeof(int));
   L.off_rmask = take(3 * (size_t)(L.RW > 0 ? L.RW : 1) * sizeof(u64));
+  L.ocap = tiles_of(W, H, 4);
+  if (tiles_of(W, H, 8) > L.ocap) L.ocap = tiles_of(W, H, 8);
+  if (tiles_of(W, H, 16) > L.ocap) L.ocap = tiles_of(W, H, 16);
+  L.off_obins = take(kOrderBins * sizeof(int));
+  L.off_order = take((size_t)kOrderBins * (size_t)(L.ocap > 0 ? L.ocap : 1) * sizeof(int));
   L.total = o;
   return L;
 }
@@ -143,6 +156,9 @@ struct Dev {
   int* parcan;    // relaxation parents by canonical id (smallest id attaining the cost)
   u64* rmask;     // wide relaxation rounds: three rotating change masks of RW words
   int* qctr;      // pixel-stage queue counters, kQueues of them kQueueStride ints apart
+  int* obins;     // pixel-stage work classes: item count of each (kOrderBins)
+  int* order;     // work items of class c at order[c * ocap ...], in no particular order within it
+  int ocap;
   // outputs
   float* dist;
   int* parent;
@@ -188,11 +204,6 @@ enum StageKind {
   STG_COUNT
 };
 constexpr int kSlice = 64;   // tiles per work item of the batched pixel stage
-
-__host__ __device__ inline int tiles_of(int W, int H, int tw) {
-  const int th = 64 / tw;
-  return ((W + tw - 1) / tw) * ((H + th - 1) / th);
-}
 
 __host__ __device__ inline int stage_count(const Dev& d, int stage) {
   switch (stage) {
