@@ -108,7 +108,7 @@ __device__ __forceinline__ void genvis_points(const Dev& d, const Geo& geo, int 
     u64 dummy[8];
     const bool pv = gu.kind == SPM_GEN_VERTEX;
     const u64 bl = wave_blocked_uniform<false>(geo, gu.x, gu.y, fm, gx, gy, true, gux, guy, gnx, gny, pv, gu.ux,
-                                               gu.uy, gu.nx, gu.ny, bx0, by0, bx1, by1, dummy);
+                                               gu.uy, gu.nx, gu.ny, bx0, by0, bx1, by1, nullptr, dummy);
     ok = fast && !((bl >> lane) & 1ull);
   }
   const u64 bits = ballot(ok);
@@ -142,7 +142,7 @@ __device__ __forceinline__ void genvis_segments(const Dev& d, const Geo& geo, in
     const int y0 = wave_min_i(inm ? cv.y : (1 << 30)), y1 = wave_max_i(inm ? cv.y : -(1 << 30));
     if (grp < 2)
       bl |= wave_blocked_uniform<false>(geo, cv.x, cv.y, m, grp ? bx : ax, grp ? by : ay, false, 0, 0, 0, 0, true,
-                                        cv.ux, cv.uy, cv.nx, cv.ny, x0, y0, x1, y1, dummy) & m;
+                                        cv.ux, cv.uy, cv.nx, cv.ny, x0, y0, x1, y1, nullptr, dummy) & m;
     else
       bl |= wave_blocked_perp<false>(geo, cv.x, cv.y, m, ax, ay, bx, by, true, cv.ux, cv.uy, cv.nx, cv.ny, x0, y0,
                                      x1, y1, dummy) & m;

@@ -203,7 +203,7 @@ __device__ __forceinline__ void seed_unpop(float (&ec)[kEstCache], unsigned& rej
 // taken.  Candidates after the one returned go back into the cache.
 template <bool STATS>
 __device__ int seed_round_wide(const Geo& geo, const GenRec* sgen, int px, int py, float (&ec)[kEstCache],
-                               unsigned& rej, int& n, u64* st) {
+                               unsigned& rej, int& sblk, int& n, u64* st) {
   constexpr int GL = 64 / kSeedWide;   // lanes per group
   const int lane = lane_id();
   const int grp = lane / GL, gl = lane % GL;
@@ -233,6 +233,7 @@ __device__ int seed_round_wide(const Geo& geo, const GenRec* sgen, int px, int p
   };
   float qx = (float)px, qy = (float)py;
   bool live = my >= 0 && seed_target(sgen, my, px, py, qx, qy);
+  if (live && sblk >= 0 && seed_crosses(geo.edges[sblk], px, py, qx, qy)) live = false;
   const int bx0 = min(px, (int)floorf(qx)), bx1 = max(px, (int)ceilf(qx));
   const int by0 = min(py, (int)floorf(qy)), by1 = max(py, (int)ceilf(qy));
   // groups still in the running (bit g), as seen by every lane
@@ -277,14 +278,16 @@ __device__ int seed_round_wide(const Geo& geo, const GenRec* sgen, int px, int p
       if (!any) break;
       if (STATS) st[ST_RELEV] += 1;
       bool x = false;
+      int xe = -1;
       if (c >= 0) {
 #pragma unroll
         for (int m = 0; m < kSeedWide; ++m) {
           const int e = c * kChunk + gl + GL * m;
-          if (e < geo.E) x = x || seed_crosses(geo.edges[e], px, py, qx, qy);
+          if (!x && e < geo.E && seed_crosses(geo.edges[e], px, py, qx, qy)) { x = true; xe = e; }
         }
       }
       const u64 xb = ballot(x);
+      if (xb) sblk = readlane(xe, first_bit(xb));
 #pragma unroll
       for (int g = 0; g < kSeedWide; ++g)
         if ((xb >> (g * GL)) & ((GL == 64) ? ~0ull : ((1ull << GL) - 1ull))) { alive &= ~(1u << g); hm[g] = 0; }
@@ -303,11 +306,14 @@ __device__ int seed_round_wide(const Geo& geo, const GenRec* sgen, int px, int p
 // seed exactly.  After kPrioTries single tries a search that is still going
 // takes its candidates kSeedWide at a time.  Returns the sorted position, or
 // -1 after about kSeedTries rejections.
-//   rej: per lane, the cache slots that earlier searches of the tile have
-//        taken; they are not tried again.
+//   rej:  per lane, the cache slots that earlier searches of the tile have
+//         taken; they are not tried again.
+//   sblk: an edge index (or -1) tried first against each candidate; set to
+//         the last edge that blocked one (nearby candidates tend to hide
+//         behind the same obstacle).
 template <bool STATS>
 __device__ int seed_search(const Geo& geo, const GenRec* sgen, const float* sgcost, const int4* sgbb, int G, int px,
-                           int py, unsigned& rej, u64* st) {
+                           int py, unsigned& rej, int& sblk, u64* st) {
   const int lane = lane_id();
   // cost + |P - x_g(P)| of sorted generator h
   auto est_of = [&](int h) -> float {
@@ -341,7 +347,7 @@ __device__ int seed_search(const Geo& geo, const GenRec* sgen, const float* sgco
     if (it >= kPrioTries) __builtin_amdgcn_s_setprio(2);
     if (cached && it >= kPrioTries) {
       int n = 0;
-      const int k = seed_round_wide<STATS>(geo, sgen, px, py, ec, rej, n, st);
+      const int k = seed_round_wide<STATS>(geo, sgen, px, py, ec, rej, sblk, n, st);
       if (k >= 0) return k;
       if (k == -2) return -1;
       it += n;
@@ -373,6 +379,7 @@ __device__ int seed_search(const Geo& geo, const GenRec* sgen, const float* sgco
     }
     float qx, qy;
     if (!seed_target(sgen, bk, px, py, qx, qy)) continue;
+    if (sblk >= 0 && ballot(seed_crosses(geo.edges[sblk], px, py, qx, qy))) continue;
     const int bx0 = min(px, (int)floorf(qx)), bx1 = max(px, (int)ceilf(qx));
     const int by0 = min(py, (int)floorf(qy)), by1 = max(py, (int)ceilf(qy));
     bool blocked = false;
@@ -389,7 +396,9 @@ __device__ int seed_search(const Geo& geo, const GenRec* sgen, const float* sgco
         cm &= cm - 1;
         if (STATS) st[ST_RELEV] += 1;
         const bool x = e < geo.E && seed_crosses(geo.edges[e], px, py, qx, qy);
-        if (ballot(x)) {
+        const u64 xb = ballot(x);
+        if (xb) {
+          sblk = e - lane + first_bit(xb);
           blocked = true;
           break;
         }
@@ -443,6 +452,8 @@ __device__ __forceinline__ int tile_work(int tile, int W, int H, int W32, int G,
     int tried[kMaxTried] = {};
     int ntried = 0;
     int nvis = 0;
+    int occ = -1;    // the edge that last hid the whole tile from a generator
+    int sblk = -1;   // the edge that last blocked a seed candidate
 
     // Evaluate sorted generator k (cost gc, bounding box x0..y1) for every
     // lane that it could still improve: per-lane filter, wave-level exact
@@ -498,7 +509,7 @@ __device__ __forceinline__ int tile_work(int tile, int W, int H, int W32, int G,
         const int gx = grp ? bx : ax, gy = grp ? by : ay;
         bl |= wave_blocked_uniform<STATS>(geo, px, py, m, gx, gy, gv, gv ? sgen[k].ux : 0, gv ? sgen[k].uy : 0,
                                           gv ? sgen[k].nx : 0, gv ? sgen[k].ny : 0, false, 0, 0, 0, 0, bx0, by0,
-                                          bx1, by1, st);
+                                          bx1, by1, &occ, st);
       }
       if (mI) {
         if (STATS) st[ST_VISWAVE] += 1;
@@ -539,7 +550,7 @@ __device__ __forceinline__ int tile_work(int tile, int W, int H, int W32, int G,
           // sample the first pixel without a value, starting from the tile centre
           const u64 hi = un & ~((1ull << ((TH / 2) * TW + TW / 2)) - 1ull);
           const int l = first_bit(hi ? hi : un);
-          k = seed_search<STATS>(geo, sgen, sgcost, sgbb, G, readlane_i(px, l), readlane_i(py, l), rej, st);
+          k = seed_search<STATS>(geo, sgen, sgcost, sgbb, G, readlane_i(px, l), readlane_i(py, l), rej, sblk, st);
           bool seen = k < 0;
 #pragma unroll
           for (int t = 0; t < kMaxTried; ++t) seen |= t < ntried && tried[t] == k;

@@ -453,11 +453,38 @@ __device__ __forceinline__ void chunk_classes(const int4* chunks, int NC, int cb
 //     endpoint exactly on line P-g flags the lane for the exact vertex rule.
 //   * g being a corner: the direction toward P must not enter g's own
 //     interior angle; P being a corner (pv): likewise toward g.
+// Edge r against the cone from g to the box (bx0..by1; rx0..ry1 = the box
+// relative to g): rel = it can block some segment [P, g] with P in the box;
+// occ = it properly crosses every such segment with the box on its obstacle
+// side (it hides the whole box from g).
+__device__ __forceinline__ void edge_vs_cone(const EdgeRec& r, int gx, int gy, int bx0, int by0, int bx1, int by1,
+                                             int rx0, int rx1, int ry0, int ry1, bool& rel, bool& occ) {
+  rel = occ = false;
+  const int Eg = mad24(r.a, gx, mad24(r.b, gy, r.c));
+  if (Eg < 0) {
+    const int hiE = mad24(r.a, r.a > 0 ? bx1 : bx0, mad24(r.b, r.b > 0 ? by1 : by0, r.c));
+    const int loE = mad24(r.a, r.a > 0 ? bx0 : bx1, mad24(r.b, r.b > 0 ? by0 : by1, r.c));
+    // f_w(P) = cross(w - g, P - g), affine in P; range over the box
+    const int aw = gy - r.wy, bw = r.wx - gx;
+    const int hiw = mul24(aw, aw > 0 ? rx1 : rx0) + mul24(bw, bw > 0 ? ry1 : ry0);
+    const int low = mul24(aw, aw > 0 ? rx0 : rx1) + mul24(bw, bw > 0 ? ry0 : ry1);
+    const int av = gy - r.vy, bv = r.vx - gx;
+    const int hiv = mul24(av, av > 0 ? rx1 : rx0) + mul24(bv, bv > 0 ? ry1 : ry0);
+    const int lov = mul24(av, av > 0 ? rx0 : rx1) + mul24(bv, bv > 0 ? ry0 : ry1);
+    const bool same = (low > 0 && lov > 0) || (hiw < 0 && hiv < 0);
+    rel = hiE > 0 && !same;
+    occ = loE > 0 && ((low > 0 && hiv < 0) || (hiw < 0 && lov > 0));
+  }
+}
+
+//   occ_hint: when not null, an edge index (or -1) to try first as an
+//             occluder of the whole box; updated with the occluder found.
+//             Neighbouring generators are often hidden by the same edge.
 template <bool STATS>
 __device__ __forceinline__ u64 wave_blocked_uniform(const Geo& d, int px, int py, u64 need, int gx, int gy, bool gvert,
                                                     int gux, int guy, int gnx, int gny, bool pv, int pux, int puy,
                                                     int pnx, int pny, int bx0, int by0, int bx1, int by1,
-                                                    u64* st) {
+                                                    int* occ_hint, u64* st) {
   const int lane = lane_id();
   const bool me = (need >> lane) & 1ull;
   bool blk = false;
@@ -471,6 +498,14 @@ __device__ __forceinline__ u64 wave_blocked_uniform(const Geo& d, int px, int py
   bool dg = false;
   const int cx0 = min(bx0, gx), cy0 = min(by0, gy), cx1 = max(bx1, gx), cy1 = max(by1, gy);
   const int rx0 = bx0 - gx, rx1 = bx1 - gx, ry0 = by0 - gy, ry1 = by1 - gy;
+  if (occ_hint && *occ_hint >= 0) {
+    bool rel, occ;
+    edge_vs_cone(d.edges[*occ_hint], gx, gy, bx0, by0, bx1, by1, rx0, rx1, ry0, ry1, rel, occ);
+    if (ballot(occ)) {
+      if (STATS) st[6] += 1;
+      return need;
+    }
+  }
   for (int cb = 0; cb < d.NC; cb += kWave) {
     u64 cls[3];
     chunk_classes(d.chunks, d.NC, cb, cx0, cy0, cx1, cy1, bx0, by0, bx1, by1, cls);
@@ -484,25 +519,13 @@ __device__ __forceinline__ u64 wave_blocked_uniform(const Geo& d, int px, int py
       EdgeRec r = {0, 0, 0, 0, 0, 0, 0, 0};
       if (e < d.E) {
         r = d.edges[e];
-        int Eg = mad24(r.a, gx, mad24(r.b, gy, r.c));
-        if (Eg < 0) {
-          int hiE = mad24(r.a, r.a > 0 ? bx1 : bx0, mad24(r.b, r.b > 0 ? by1 : by0, r.c));
-          int loE = mad24(r.a, r.a > 0 ? bx0 : bx1, mad24(r.b, r.b > 0 ? by0 : by1, r.c));
-          // f_w(P) = cross(w - g, P - g), affine in P; range over the box
-          int aw = gy - r.wy, bw = r.wx - gx;
-          int hiw = mul24(aw, aw > 0 ? rx1 : rx0) + mul24(bw, bw > 0 ? ry1 : ry0);
-          int low = mul24(aw, aw > 0 ? rx0 : rx1) + mul24(bw, bw > 0 ? ry0 : ry1);
-          int av = gy - r.vy, bv = r.vx - gx;
-          int hiv = mul24(av, av > 0 ? rx1 : rx0) + mul24(bv, bv > 0 ? ry1 : ry0);
-          int lov = mul24(av, av > 0 ? rx0 : rx1) + mul24(bv, bv > 0 ? ry0 : ry1);
-          bool same = (low > 0 && lov > 0) || (hiw < 0 && hiv < 0);
-          rel = hiE > 0 && !same;
-          occ = loE > 0 && ((low > 0 && hiv < 0) || (hiw < 0 && lov > 0));
-        }
+        edge_vs_cone(r, gx, gy, bx0, by0, bx1, by1, rx0, rx1, ry0, ry1, rel, occ);
       }
       if (STATS) st[4] += 1;
-      if (ballot(occ)) {
+      const u64 om = ballot(occ);
+      if (om) {
         if (STATS) st[6] += 1;
+        if (occ_hint) *occ_hint = chunk * kChunk + first_bit(om);
         return need;
       }
       u64 rm = ballot(rel);
