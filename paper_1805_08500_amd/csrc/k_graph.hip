@@ -61,6 +61,27 @@ __device__ __forceinline__ double arc_len(const GenRec& u, int vx, int vy) {
 // LDSE: the edges and chunk boxes are staged in LDS first.  Workgroups never
 // straddle scenes for the first kind (each scene's wavefronts are padded to
 // whole workgroups).
+// The relaxation's starting state, by spatial position (entry wid * 64 + lane
+// of it; the point-column wavefronts cover all of it): sources at cost 0 and
+// marked changed, everything else at +inf; generator coordinates.
+__device__ __forceinline__ void relax_init(const Dev& d, int wid, int G, int nsrc) {
+  const int RW = d.RW;
+  const int t = wid * 64 + lane_id();
+  if (t < G) {
+    const GenRec gt = d.gens[d.gorder[t]];
+    d.costpos[t] = (u64)__double_as_longlong(t < nsrc ? 0.0 : INFINITY);
+    d.gxy[t] = make_int4(gt.x, gt.y, gt.x2, gt.y2);
+  }
+  if (t < 3 * RW) {
+    u64 m = 0;
+    if (t < RW) {
+      const int lo = t * 64, hi = min(nsrc, lo + 64);
+      if (hi > lo) m = (hi - lo == 64) ? ~0ull : ((1ull << (hi - lo)) - 1ull);
+    }
+    d.rmask[t] = m;
+  }
+}
+
 template <class S>
 __device__ __forceinline__ void genvis_points(const Dev& d, const Geo& geo, int wid) {
   const int RW = d.RW;
@@ -70,24 +91,7 @@ __device__ __forceinline__ void genvis_points(const Dev& d, const Geo& geo, int 
   const int G = uni(d.misc[MISC_G]);
   const int nsrc = d.np + d.ns;
   const int lane = lane_id();
-  {
-    // the relaxation's starting state, by spatial position: sources at cost 0 and marked
-    // changed, everything else at +inf; generator coordinates
-    const int t = wid * 64 + lane;
-    if (t < G) {
-      const GenRec gt = d.gens[d.gorder[t]];
-      d.costpos[t] = (u64)__double_as_longlong(t < nsrc ? 0.0 : INFINITY);
-      d.gxy[t] = make_int4(gt.x, gt.y, gt.x2, gt.y2);
-    }
-    if (t < 3 * RW) {
-      u64 m = 0;
-      if (t < RW) {
-        const int lo = t * 64, hi = min(nsrc, lo + 64);
-        if (hi > lo) m = (hi - lo == 64) ? ~0ull : ((1ull << (hi - lo)) - 1ull);
-      }
-      d.rmask[t] = m;
-    }
-  }
+  relax_init(d, wid, G, nsrc);
   if (r >= G || r < nsrc) return;  // only corner rows are read
   const int v = uni(d.gorder[r]);
   const int gx = uni(d.gens[v].x), gy = uni(d.gens[v].y);
@@ -113,6 +117,105 @@ __device__ __forceinline__ void genvis_points(const Dev& d, const Geo& geo, int 
   }
   const u64 bits = ballot(ok);
   if (lane == 0 && bits) atomicOr(&d.vis[(size_t)r * RW + blk], bits << (sub * sb));
+}
+
+
+// Closed-segment visibility of one pair, P (a point source or a corner) and
+// the corner g, lanes over edges -- the exact rules of wave_blocked_uniform
+// for a single P: the segment is blocked when it enters an obstacle through
+// the interior of an edge front-facing to g (endpoints strictly on opposite
+// sides of line P-g, P strictly on the obstacle side), or through a vertex
+// strictly between P and g (the vertex rule), or leaves P or g into their own
+// interior angle.  Only the chunks whose box meets the segment's box and
+// straddles or touches its line can hold such an edge or vertex.
+__device__ __forceinline__ bool pair_visible(const Geo& geo, int px, int py, bool pvert, int pux, int puy, int pnx,
+                                             int pny, int gx, int gy, int gux, int guy, int gnx, int gny) {
+  const int lane = lane_id();
+  if (into_interior(gux, guy, gx, gy, gnx, gny, px - gx, py - gy)) return false;
+  if (pvert && into_interior(pux, puy, px, py, pnx, pny, gx - px, gy - py)) return false;
+  // line through P and g: o(x) = A x + B y + C = cross(g - P, x - P)
+  const int A = py - gy, B = gx - px;
+  const int C = -(mul24(A, px) + mul24(B, py));
+  const int len2 = mad24(B, B, mul24(A, A));
+  const int sx0 = min(px, gx), sx1 = max(px, gx), sy0 = min(py, gy), sy1 = max(py, gy);
+  for (int cb = 0; cb < geo.NC; cb += kWave) {
+    const int ci = cb + lane;
+    bool hit = false;
+    if (ci < geo.NC) {
+      const int4 bb = geo.chunks[ci];
+      if (bb.x <= sx1 && bb.z >= sx0 && bb.y <= sy1 && bb.w >= sy0) {
+        const int o00 = mad24(A, bb.x, mad24(B, bb.y, C)), o10 = mad24(A, bb.z, mad24(B, bb.y, C));
+        const int o01 = mad24(A, bb.x, mad24(B, bb.w, C)), o11 = mad24(A, bb.z, mad24(B, bb.w, C));
+        hit = !((o00 > 0 && o10 > 0 && o01 > 0 && o11 > 0) || (o00 < 0 && o10 < 0 && o01 < 0 && o11 < 0));
+      }
+    }
+    u64 cm = ballot(hit);
+    while (cm) {
+      const int e = (cb + first_bit(cm)) * kChunk + lane;
+      cm &= cm - 1;
+      bool blk = false;
+      if (e < geo.E) {
+        const EdgeRec r = geo.edges[e];
+        const int ow = mad24(A, r.wx, mad24(B, r.wy, C));
+        const int ov = mad24(A, r.vx, mad24(B, r.vy, C));
+        const int Eg = mad24(r.a, gx, mad24(r.b, gy, r.c));
+        // sign of ow * ov: converting to float keeps every sign and every zero exact
+        blk = Eg < 0 && (float)ow * (float)ov < 0.0f && mad24(r.a, px, mul24(r.b, py)) > r.nc;
+        if (ow == 0) {
+          const int dw = mad24(r.wx - px, B, mul24(r.wy - py, -A));
+          if (dw > 0 && dw < len2) {
+            const EdgeExt x = geo.ext[e];
+            blk = blk || into_interior(x.ux, x.uy, r.wx, r.wy, r.vx, r.vy, px - r.wx, py - r.wy) ||
+                  into_interior(x.ux, x.uy, r.wx, r.wy, r.vx, r.vy, gx - r.wx, gy - r.wy);
+          }
+        }
+      }
+      if (ballot(blk)) return false;
+    }
+  }
+  return true;
+}
+
+// Point columns by pairs (few edges): one wavefront per row of a
+// kGvPairRows x kGvPairRows block of the lower triangle of the matrix (blocks
+// numbered row by row), testing its pairs (row corner v, column u < v) one at
+// a time.  Corner-corner visibility is symmetric, so a visible pair sets both
+// v's bit u and u's bit v; point-source columns set v's bit only (source rows
+// are never read) and segment columns are left to the segment wavefronts.
+template <class S>
+__device__ __forceinline__ void genvis_pairs(const Dev& d, const Geo& geo, int wid) {
+  const int RW = d.RW;
+  const int G = uni(d.misc[MISC_G]);
+  const int nsrc = d.np + d.ns;
+  const int lane = lane_id();
+  relax_init(d, wid, G, nsrc);
+  const int b = wid / kGvPairRows, i = wid - b * kGvPairRows;
+  // block row R of block b: R (R + 1) / 2 <= b < (R + 1) (R + 2) / 2
+  int R = (int)((sqrtf(8.0f * (float)b + 1.0f) - 1.0f) * 0.5f);
+  while (R > 0 && R * (R + 1) / 2 > b) --R;
+  while ((R + 1) * (R + 2) / 2 <= b) ++R;
+  const int Cb = b - R * (R + 1) / 2;
+  const int r = R * kGvPairRows + i, u0 = Cb * kGvPairRows;
+  if (r >= G || r < nsrc || u0 >= r) return;
+  const int v = uni(d.gorder[r]);
+  const int gx = uni(d.gens[v].x), gy = uni(d.gens[v].y);
+  const int gux = uni(d.gens[v].ux), guy = uni(d.gens[v].uy), gnx = uni(d.gens[v].nx), gny = uni(d.gens[v].ny);
+  // lane j < kGvPairRows holds column u0 + j
+  const int nu = min(kGvPairRows, r - u0);
+  GenRec gu = {};
+  if (lane < nu) gu = d.gens[d.gorder[u0 + lane]];
+  unsigned bits = 0;
+  for (int j = 0; j < nu; ++j) {
+    if (readlane(gu.kind, j) == SPM_GEN_SEGMENT) continue;
+    const bool pv = readlane(gu.kind, j) == SPM_GEN_VERTEX;
+    if (pair_visible(geo, readlane(gu.x, j), readlane(gu.y, j), pv, readlane(gu.ux, j), readlane(gu.uy, j),
+                     readlane(gu.nx, j), readlane(gu.ny, j), gx, gy, gux, guy, gnx, gny))
+      bits |= 1u << j;
+  }
+  if (!bits) return;
+  if (lane == 0) atomicOr(&d.vis[(size_t)r * RW + (u0 >> 6)], (u64)bits << (u0 & 63));
+  const int u = u0 + lane;
+  if (lane < nu && ((bits >> lane) & 1u) && u >= nsrc) atomicOr(&d.vis[(size_t)u * RW + (r >> 6)], 1ull << (r & 63));
 }
 
 __device__ __forceinline__ void genvis_segments(const Dev& d, const Geo& geo, int item) {
@@ -170,8 +273,12 @@ __global__ __launch_bounds__(256) void k_genvis(S src, int nblk_points) {
     geo.edges = s_edges;
     geo.chunks = s_chunks;
   }
-  if (pts) genvis_points<S>(d, geo, item * 4 + (threadIdx.x >> 6));
-  else genvis_segments(d, geo, item);
+  if (pts) {
+    if (d.gv_sub == 0) genvis_pairs<S>(d, geo, item * 4 + (threadIdx.x >> 6));
+    else genvis_points<S>(d, geo, item * 4 + (threadIdx.x >> 6));
+  } else {
+    genvis_segments(d, geo, item);
+  }
 }
 
 // Arc weight from a generator with doubled coordinates (x, y, x2, y2) --
@@ -230,22 +337,29 @@ __global__ __launch_bounds__(256) void k_relax_wide(S src, int round) {
   const int vk = it >> 3, sh = (it & 7) * 8;
   const int v = nsrc + vk / RW, k = vk - (vk / RW) * RW;
   if (v >= d.misc[MISC_G]) return;
-  const u64 c = (Mc[k] >> sh) & 0xffull;
-  if (!c) return;
-  u64 m = (d.vis[(size_t)v * RW + k] >> sh) & c;
+  const u64 m = (Mc[k] >> sh) & (d.vis[(size_t)v * RW + k] >> sh) & 0xffull;
   if (!m) return;
   u64* cost = d.costpos;
+  // the (up to eight) candidates' costs and coordinates, all requested before any is used
+  const int u0 = k * 64 + sh;
+  double cu[8];
+  int4 pu[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    cu[j] = INFINITY;
+    if ((m >> j) & 1ull) {
+      cu[j] = __longlong_as_double((long long)cost[u0 + j]);
+      pu[j] = d.gxy[u0 + j];
+    }
+  }
   const int4 pv = d.gxy[v];
   const double old = __longlong_as_double((long long)cost[v]);
   double best = old;
-  while (m) {
-    const int u = k * 64 + sh + __builtin_ctzll(m);
-    m &= m - 1;
-    const double cu = __longlong_as_double((long long)cost[u]);
-    if (!(cu < best)) continue;
-    const int4 pu = d.gxy[u];
-    if (!(cu + arc_lower(pu, pv.x, pv.y) < best)) continue;
-    const double cand = cu + arc_len4(pu, pv.x, pv.y);
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    if (!(cu[j] < best)) continue;
+    if (!(cu[j] + arc_lower(pu[j], pv.x, pv.y) < best)) continue;
+    const double cand = cu[j] + arc_len4(pu[j], pv.x, pv.y);
     if (cand < best) best = cand;
   }
   if (best < old) {
@@ -269,18 +383,27 @@ __global__ __launch_bounds__(256) void k_relax_parents(S src) {
   if (p >= d.misc[MISC_G]) return;
   const double c = __longlong_as_double((long long)d.costpos[p]);
   if (!(c < INFINITY)) return;
-  u64 m = (d.vis[(size_t)p * RW + k] >> sh) & 0xffull;
+  const u64 m = (d.vis[(size_t)p * RW + k] >> sh) & 0xffull;
   if (!m) return;
+  // the candidates' costs and coordinates, all requested before any is used
+  const int u0 = k * 64 + sh;
+  double cu[8];
+  int4 pu[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    cu[j] = INFINITY;
+    if ((m >> j) & 1ull) {
+      cu[j] = __longlong_as_double((long long)d.costpos[u0 + j]);
+      pu[j] = d.gxy[u0 + j];
+    }
+  }
   const int4 pv = d.gxy[p];
   int best = 0x7fffffff;
-  while (m) {
-    const int up = k * 64 + sh + __builtin_ctzll(m);
-    m &= m - 1;
-    const double cu = __longlong_as_double((long long)d.costpos[up]);
-    if (!(cu < c)) continue;
-    const int4 pu = d.gxy[up];
-    if (cu + arc_lower(pu, pv.x, pv.y) > c) continue;
-    if (cu + arc_len4(pu, pv.x, pv.y) == c) best = min(best, d.gorder[up]);
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    if (!(cu[j] < c)) continue;
+    if (cu[j] + arc_lower(pu[j], pv.x, pv.y) > c) continue;
+    if (cu[j] + arc_len4(pu[j], pv.x, pv.y) == c) best = min(best, d.gorder[u0 + j]);
   }
   if (best != 0x7fffffff) atomicMin(&d.parcan[d.gorder[p]], best);
 }

@@ -23,7 +23,7 @@ constexpr int kWave = 64;
 constexpr int kChunk = 64;        // edges per spatial chunk
 constexpr int kRelaxThreads = 1024;
 #ifndef SPM_RELAX_WIDE
-#define SPM_RELAX_WIDE 2
+#define SPM_RELAX_WIDE 6
 #endif
 constexpr int kRelaxWideRounds = SPM_RELAX_WIDE;   // Bellman-Ford rounds run chip-wide before the one-workgroup rounds
 constexpr int kDefaultStrip = 1;      // tiles per pixel-stage work item
@@ -32,6 +32,13 @@ constexpr int kMaxStrip = 64;
 constexpr int kQueues = 8;         // pixel-stage work queues (one per XCD)
 constexpr int kQueueStride = 32;   // ints between queue counters (one 128-byte line each)
 constexpr int kOrderBins = 32;     // pixel-stage work classes (tiles ranked by a distance lower bound)
+#ifndef SPM_GV_PAIR_ROWS
+#define SPM_GV_PAIR_ROWS 16
+#endif
+constexpr int kGvPairRows = SPM_GV_PAIR_ROWS;   // generator visibility by pairs: rows (and columns) per triangle block
+#ifndef SPM_GV_PAIR_MIN_GEN
+#define SPM_GV_PAIR_MIN_GEN 128    // generator visibility by pairs from this many generators on
+#endif
 
 // One obstacle edge w -> v (obstacle on the left), with its line function
 // E(x, y) = a x + b y + c, positive on the obstacle side.
@@ -171,7 +178,8 @@ struct Dev {
   int tile_w, tile_h;
   int strip;       // pixel stage: tiles per wavefront work item (>= 1)
   int samples;     // pixel stage: seed searches per tile (>= 0)
-  int gv_sub;      // generator visibility: columns per wavefront (64, 32 or 16)
+  int gv_sub;      // generator visibility: columns per wavefront (64, 32 or 16); 0: one pair at a time,
+                   // lanes over edges (kGvPairRows x kGvPairRows blocks of the lower triangle)
   u64* stats;
 };
 
@@ -212,7 +220,13 @@ __host__ __device__ inline int stage_count(const Dev& d, int stage) {
     case STG_EDGE: return d.E;
     case STG_CHUNK: return d.NC;
     case STG_ROW: return d.H;
-    case STG_GVBLK: return (int)(((long long)d.Gmax * d.RW * (64 / d.gv_sub) + 3) / 4);
+    case STG_GVBLK: {
+      if (d.gv_sub == 0) {
+        const long long B = (d.Gmax + kGvPairRows - 1) / kGvPairRows;
+        return (int)((kGvPairRows * (B * (B + 1) / 2) + 3) / 4);
+      }
+      return (int)(((long long)d.Gmax * d.RW * (64 / d.gv_sub) + 3) / 4);
+    }
     case STG_GEN: return d.Gmax;
     case STG_SLICE: return (tiles_of(d.W, d.H, d.tile_w) + kSlice - 1) / kSlice;
     case STG_SEGVIS: return d.ns * ((d.Gmax - d.np - d.ns + 63) / 64);
