@@ -561,24 +561,31 @@ __global__ __launch_bounds__(256) void k_gsort(S src) {
   const int G = uni(d.misc[MISC_G]);
   if (g >= G) return;
   const int lane = lane_id();
+  // requested up front: this generator's record and parent (written after the rank)
+  GenRec r = d.gens[g];
+  const int pc = d.parcan[g];
   const float cf = (float)d.cost64[g];
   const u64 key = ((u64)__float_as_uint(cf) << 32) | (u64)(unsigned)g;
   int rank = 0;
-  for (int h = lane; h - lane < G; h += 64) {
-    bool lt = false;
-    if (h < G) {
-      const float ch = (float)d.cost64[h];
-      lt = (((u64)__float_as_uint(ch) << 32) | (u64)(unsigned)h) < key;
+  for (int base = 0; base < G; base += 256) {
+    // four batches of 64 keys requested together
+    float ch[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int h = base + 64 * q + lane;
+      ch[q] = h < G ? (float)d.cost64[h] : INFINITY;
     }
-    rank += __popcll(ballot(lt));
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int h = base + 64 * q + lane;
+      rank += __popcll(ballot(h < G && (((u64)__float_as_uint(ch[q]) << 32) | (u64)(unsigned)h) < key));
+    }
   }
   if (lane == 0) {
     // the parent found by k_relax_parents; sources are their own parents
-    const int pc = d.parcan[g];
     d.gen_parent[g] = g < d.np + d.ns ? g : ((cf < INFINITY && pc != 0x7fffffff) ? pc : -1);
   }
   if (lane == 0 && cf < INFINITY) {
-    GenRec r = d.gens[g];
     r.costf = cf;
     d.sgen[rank] = r;
     d.sgcost[rank] = cf;

@@ -634,24 +634,37 @@ size_t pixel_lds_bytes(int Gmax, int E, int NC) {
 // width over 0 .. (W + H) / 2 domain units, the last one open-ended): the long
 // items start at the beginning of the launch instead of ending it.  No output
 // depends on the order in which items run.  One wavefront per item, lanes
-// over the cost-sorted generators; each workgroup takes kOrderItems items and
-// appends them to their classes with one atomic per class.
+// over the cost-sorted generators (staged in LDS when LDS is set); each
+// workgroup takes kOrderItems items and appends them to their classes with
+// one atomic per class.
 constexpr int kOrderThreads = 512;
 constexpr int kOrderItems = 64;
+constexpr size_t kOrderLdsMax = 48 * 1024;
 
-template <int TW>
-__global__ __launch_bounds__(kOrderThreads) void k_tile_order(int W, int H, int strip, const int* __restrict__ misc,
-                                                              const float* __restrict__ sgcost,
-                                                              const int4* __restrict__ sgbb, int* __restrict__ obins,
+template <int TW, bool LDS>
+__global__ __launch_bounds__(kOrderThreads) void k_tile_order(int W, int H, int strip, int Gcap,
+                                                              const int* __restrict__ misc,
+                                                              const float* __restrict__ sgcost_g,
+                                                              const int4* __restrict__ sgbb_g, int* __restrict__ obins,
                                                               int* __restrict__ order, int ocap) {
   constexpr int TH = 64 / TW;
   constexpr int kPerWave = kOrderItems / (kOrderThreads / 64);
+  extern __shared__ int4 osm[];
   __shared__ int lcount[kOrderBins], lbase[kOrderBins];
   __shared__ int icls[kOrderItems], islot[kOrderItems];
   const int tid = threadIdx.x, lane = lane_id(), wv = tid / 64;
   if (tid < kOrderBins) lcount[tid] = 0;
-  __syncthreads();
   const int G = misc[MISC_REACHED];
+  const float* sgcost = sgcost_g;
+  const int4* sgbb = sgbb_g;
+  if (LDS) {
+    int4* s_bb = osm;
+    float* s_cost = (float*)(osm + Gcap);
+    for (int k = tid; k < G; k += kOrderThreads) { s_bb[k] = sgbb_g[k]; s_cost[k] = sgcost_g[k]; }
+    sgbb = s_bb;
+    sgcost = s_cost;
+  }
+  __syncthreads();
   const int ntx = (W + TW - 1) / TW, nty = (H + TH - 1) / TH;
   const int spr = (ntx + strip - 1) / strip;
   const int nitems = spr * nty;
@@ -817,9 +830,14 @@ static hipError_t launch_variant(const Dev& d, hipStream_t s, size_t shm) {
   // the work order matters only when some items wait for a free wavefront
   const int* order = nullptr;
   if (SPM_TILE_ORDER && waves_needed > blocks * (kPixelThreads / 64)) {
-    hipLaunchKernelGGL(k_tile_order<TW>, dim3((unsigned)((waves_needed + kOrderItems - 1) / kOrderItems)),
-                       dim3(kOrderThreads), 0, s, d.W, d.H, d.strip, d.misc, d.sgcost, d.sgbb, d.obins, d.order,
-                       d.ocap);
+    const dim3 og((unsigned)((waves_needed + kOrderItems - 1) / kOrderItems));
+    const size_t osh = (size_t)d.Gmax * (sizeof(int4) + sizeof(float));
+    if (osh <= kOrderLdsMax)
+      hipLaunchKernelGGL((k_tile_order<TW, true>), og, dim3(kOrderThreads), osh, s, d.W, d.H, d.strip, d.Gmax, d.misc,
+                         d.sgcost, d.sgbb, d.obins, d.order, d.ocap);
+    else
+      hipLaunchKernelGGL((k_tile_order<TW, false>), og, dim3(kOrderThreads), 0, s, d.W, d.H, d.strip, d.Gmax, d.misc,
+                         d.sgcost, d.sgbb, d.obins, d.order, d.ocap);
     order = d.order;
   }
   hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(kPixelThreads), shm, s, d.W, d.H, d.W32, d.Gmax, d.misc,
