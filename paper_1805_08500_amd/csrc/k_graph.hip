@@ -248,7 +248,7 @@ __device__ __forceinline__ void genvis_segments(const Dev& d, const Geo& geo, in
                                         cv.ux, cv.uy, cv.nx, cv.ny, x0, y0, x1, y1, nullptr, dummy) & m;
     else
       bl |= wave_blocked_perp<false>(geo, cv.x, cv.y, m, ax, ay, bx, by, true, cv.ux, cv.uy, cv.nx, cv.ny, x0, y0,
-                                     x1, y1, dummy) & m;
+                                     x1, y1, nullptr, dummy) & m;
   }
   if (valid && !((bl >> lane) & 1ull)) atomicOr(&d.vis[(size_t)r * d.RW + (spos >> 6)], 1ull << (spos & 63));
 }

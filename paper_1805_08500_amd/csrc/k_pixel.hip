@@ -515,7 +515,7 @@ __device__ __forceinline__ int tile_work(int tile, int W, int H, int W32, int G,
         if (STATS) st[ST_VISWAVE] += 1;
         int bx0, by0, bx1, by1;
         mask_box<TW>(mI, i0, j0, bx0, by0, bx1, by1);
-        bl |= wave_blocked_perp<STATS>(geo, px, py, mI, ax, ay, bx, by, false, 0, 0, 0, 0, bx0, by0, bx1, by1, st);
+        bl |= wave_blocked_perp<STATS>(geo, px, py, mI, ax, ay, bx, by, false, 0, 0, 0, 0, bx0, by0, bx1, by1, &occ, st);
       }
       bool upd = false;
       if (need && !((bl >> lane) & 1ull)) {

@@ -619,10 +619,34 @@ __device__ __forceinline__ u64 wave_blocked_uniform(const Geo& d, int px, int py
 // back to the generic test.  P may be an obstacle corner (pv, with its
 // neighbours): then the direction toward q* must not enter its own angle.
 // (bx0..by1) is a box containing every needed P.
+// Edge r against the band between the pixel box (bx0..by1) and the segment
+// source A-B (direction e = B - A; Pmin..Pmax = the box's range of e . P):
+// rel = it can block some perpendicular [P, q*(P)]; occ = it crosses every
+// such segment with the box on its obstacle side.
+__device__ __forceinline__ void edge_vs_band(const EdgeRec& r, int ax, int ay, int bx, int by, int ex, int ey,
+                                             int Pmin, int Pmax, int bx0, int by0, int bx1, int by1, bool& rel,
+                                             bool& occ) {
+  const int EA = r.a * ax + r.b * ay + r.c, EB = r.a * bx + r.b * by + r.c;
+  const int hiE = r.a * (r.a > 0 ? bx1 : bx0) + r.b * (r.b > 0 ? by1 : by0) + r.c;
+  const int loE = r.a * (r.a > 0 ? bx0 : bx1) + r.b * (r.b > 0 ? by0 : by1) + r.c;
+  const int Dw = ex * r.wx + ey * r.wy, Dv = ex * r.vx + ey * r.vy;
+  const int lo = min(Dw, Dv), hi = max(Dw, Dv);
+  const bool strad = Pmax >= lo && Pmin <= hi;
+  bool side, full;
+  if (EA > 0 && EB > 0) { side = loE < 0; full = hiE < 0; }
+  else if (EA < 0 && EB < 0) { side = hiE > 0; full = loE > 0; }
+  else if (EA == 0 && EB == 0) { side = false; full = false; }
+  else { side = loE < 0 || hiE > 0; full = false; }
+  rel = strad && side;
+  occ = full && lo < Pmin && Pmax < hi;
+}
+
+//   occ_hint: as for wave_blocked_uniform (an edge tried first as an occluder
+//             of the whole band, updated with the occluder found).
 template <bool STATS>
 __device__ __forceinline__ u64 wave_blocked_perp(const Geo& d, int px, int py, u64 need, int ax, int ay, int bx,
                                                  int by, bool pv, int pux, int puy, int pnx, int pny, int bx0,
-                                                 int by0, int bx1, int by1, u64* st) {
+                                                 int by0, int bx1, int by1, int* occ_hint, u64* st) {
   const int lane = lane_id();
   const int ex = bx - ax, ey = by - ay;
   const int L = ex * ex + ey * ey;
@@ -648,6 +672,14 @@ __device__ __forceinline__ u64 wave_blocked_perp(const Geo& d, int px, int py, u
   }
   u64 blocked = ballot(blk) & need;
   if (blocked == need) return need;
+  if (occ_hint && *occ_hint >= 0) {
+    bool rel, occ;
+    edge_vs_band(d.edges[*occ_hint], ax, ay, bx, by, ex, ey, Pmin, Pmax, bx0, by0, bx1, by1, rel, occ);
+    if (ballot(occ)) {
+      if (STATS) st[6] += 1;
+      return need;
+    }
+  }
   for (int cb = 0; cb < d.NC; cb += kWave) {
     u64 cls[3];
     chunk_classes(d.chunks, d.NC, cb, cx0, cy0, cx1, cy1, bx0, by0, bx1, by1, cls);
@@ -661,23 +693,13 @@ __device__ __forceinline__ u64 wave_blocked_perp(const Geo& d, int px, int py, u
       EdgeRec r = {0, 0, 0, 0, 0, 0, 0, 0};
       if (e < d.E) {
         r = d.edges[e];
-        const int EA = r.a * ax + r.b * ay + r.c, EB = r.a * bx + r.b * by + r.c;
-        const int hiE = r.a * (r.a > 0 ? bx1 : bx0) + r.b * (r.b > 0 ? by1 : by0) + r.c;
-        const int loE = r.a * (r.a > 0 ? bx0 : bx1) + r.b * (r.b > 0 ? by0 : by1) + r.c;
-        const int Dw = ex * r.wx + ey * r.wy, Dv = ex * r.vx + ey * r.vy;
-        const int lo = min(Dw, Dv), hi = max(Dw, Dv);
-        const bool strad = Pmax >= lo && Pmin <= hi;
-        bool side, full;
-        if (EA > 0 && EB > 0) { side = loE < 0; full = hiE < 0; }
-        else if (EA < 0 && EB < 0) { side = hiE > 0; full = loE > 0; }
-        else if (EA == 0 && EB == 0) { side = false; full = false; }
-        else { side = loE < 0 || hiE > 0; full = false; }
-        rel = strad && side;
-        occ = full && lo < Pmin && Pmax < hi;
+        edge_vs_band(r, ax, ay, bx, by, ex, ey, Pmin, Pmax, bx0, by0, bx1, by1, rel, occ);
       }
       if (STATS) st[4] += 1;
-      if (ballot(occ)) {
+      const u64 om = ballot(occ);
+      if (om) {
         if (STATS) st[6] += 1;
+        if (occ_hint) *occ_hint = chunk * kChunk + first_bit(om);
         return need;
       }
       u64 rm = ballot(rel);
