@@ -452,7 +452,9 @@ __device__ __forceinline__ int tile_work(int tile, int W, int H, int W32, int G,
     int tried[kMaxTried] = {};
     int ntried = 0;
     int nvis = 0;
-    int occ = -1;    // the edge that last hid the whole tile from a generator
+    int occ[kOccHints];   // the edges that last hid the whole tile from a generator (most recent first)
+#pragma unroll
+    for (int h = 0; h < kOccHints; ++h) occ[h] = -1;
     int sblk = -1;   // the edge that last blocked a seed candidate
 
     // Evaluate sorted generator k (cost gc, bounding box x0..y1) for every
@@ -509,13 +511,13 @@ __device__ __forceinline__ int tile_work(int tile, int W, int H, int W32, int G,
         const int gx = grp ? bx : ax, gy = grp ? by : ay;
         bl |= wave_blocked_uniform<STATS>(geo, px, py, m, gx, gy, gv, gv ? sgen[k].ux : 0, gv ? sgen[k].uy : 0,
                                           gv ? sgen[k].nx : 0, gv ? sgen[k].ny : 0, false, 0, 0, 0, 0, bx0, by0,
-                                          bx1, by1, &occ, st);
+                                          bx1, by1, occ, st);
       }
       if (mI) {
         if (STATS) st[ST_VISWAVE] += 1;
         int bx0, by0, bx1, by1;
         mask_box<TW>(mI, i0, j0, bx0, by0, bx1, by1);
-        bl |= wave_blocked_perp<STATS>(geo, px, py, mI, ax, ay, bx, by, false, 0, 0, 0, 0, bx0, by0, bx1, by1, &occ, st);
+        bl |= wave_blocked_perp<STATS>(geo, px, py, mI, ax, ay, bx, by, false, 0, 0, 0, 0, bx0, by0, bx1, by1, occ, st);
       }
       bool upd = false;
       if (need && !((bl >> lane) & 1ull)) {

@@ -467,6 +467,25 @@ __device__ __forceinline__ void chunk_classes(const int4* chunks, int NC, int cb
 //     endpoint exactly on line P-g flags the lane for the exact vertex rule.
 //   * g being a corner: the direction toward P must not enter g's own
 //     interior angle; P being a corner (pv): likewise toward g.
+#ifndef SPM_OCC_HINTS
+#define SPM_OCC_HINTS 3
+#endif
+constexpr int kOccHints = SPM_OCC_HINTS;   // occluding edges a tile remembers (most recent first)
+
+// Occluder list updates: move entry h to the front; put a new edge in front.
+__device__ __forceinline__ void occ_hint_front(int* hint, int h) {
+  const int e = hint[h];
+#pragma unroll
+  for (int k = kOccHints - 1; k > 0; --k)
+    if (k <= h) hint[k] = hint[k - 1];
+  hint[0] = e;
+}
+__device__ __forceinline__ void occ_hint_push(int* hint, int e) {
+#pragma unroll
+  for (int k = kOccHints - 1; k > 0; --k) hint[k] = hint[k - 1];
+  hint[0] = e;
+}
+
 // Edge r against the cone from g to the box (bx0..by1; rx0..ry1 = the box
 // relative to g): rel = it can block some segment [P, g] with P in the box;
 // occ = it properly crosses every such segment with the box on its obstacle
@@ -491,9 +510,10 @@ __device__ __forceinline__ void edge_vs_cone(const EdgeRec& r, int gx, int gy, i
   }
 }
 
-//   occ_hint: when not null, an edge index (or -1) to try first as an
-//             occluder of the whole box; updated with the occluder found.
-//             Neighbouring generators are often hidden by the same edge.
+//   occ_hint: when not null, kOccHints edge indices (or -1), the most recent
+//             first, tried before the scan as occluders of the whole box;
+//             the occluder found goes to the front.  Neighbouring generators
+//             are often hidden by the same few edges.
 template <bool STATS>
 __device__ __forceinline__ u64 wave_blocked_uniform(const Geo& d, int px, int py, u64 need, int gx, int gy, bool gvert,
                                                     int gux, int guy, int gnx, int gny, bool pv, int pux, int puy,
@@ -512,12 +532,17 @@ __device__ __forceinline__ u64 wave_blocked_uniform(const Geo& d, int px, int py
   bool dg = false;
   const int cx0 = min(bx0, gx), cy0 = min(by0, gy), cx1 = max(bx1, gx), cy1 = max(by1, gy);
   const int rx0 = bx0 - gx, rx1 = bx1 - gx, ry0 = by0 - gy, ry1 = by1 - gy;
-  if (occ_hint && *occ_hint >= 0) {
-    bool rel, occ;
-    edge_vs_cone(d.edges[*occ_hint], gx, gy, bx0, by0, bx1, by1, rx0, rx1, ry0, ry1, rel, occ);
-    if (ballot(occ)) {
-      if (STATS) st[6] += 1;
-      return need;
+  if (occ_hint) {
+#pragma unroll
+    for (int h = 0; h < kOccHints; ++h) {
+      if (occ_hint[h] < 0) break;
+      bool rel, occ;
+      edge_vs_cone(d.edges[occ_hint[h]], gx, gy, bx0, by0, bx1, by1, rx0, rx1, ry0, ry1, rel, occ);
+      if (ballot(occ)) {
+        if (STATS) st[6] += 1;
+        occ_hint_front(occ_hint, h);
+        return need;
+      }
     }
   }
   for (int cb = 0; cb < d.NC; cb += kWave) {
@@ -539,7 +564,7 @@ __device__ __forceinline__ u64 wave_blocked_uniform(const Geo& d, int px, int py
       const u64 om = ballot(occ);
       if (om) {
         if (STATS) st[6] += 1;
-        if (occ_hint) *occ_hint = chunk * kChunk + first_bit(om);
+        if (occ_hint) occ_hint_push(occ_hint, chunk * kChunk + first_bit(om));
         return need;
       }
       u64 rm = ballot(rel);
@@ -672,12 +697,17 @@ __device__ __forceinline__ u64 wave_blocked_perp(const Geo& d, int px, int py, u
   }
   u64 blocked = ballot(blk) & need;
   if (blocked == need) return need;
-  if (occ_hint && *occ_hint >= 0) {
-    bool rel, occ;
-    edge_vs_band(d.edges[*occ_hint], ax, ay, bx, by, ex, ey, Pmin, Pmax, bx0, by0, bx1, by1, rel, occ);
-    if (ballot(occ)) {
-      if (STATS) st[6] += 1;
-      return need;
+  if (occ_hint) {
+#pragma unroll
+    for (int h = 0; h < kOccHints; ++h) {
+      if (occ_hint[h] < 0) break;
+      bool rel, occ;
+      edge_vs_band(d.edges[occ_hint[h]], ax, ay, bx, by, ex, ey, Pmin, Pmax, bx0, by0, bx1, by1, rel, occ);
+      if (ballot(occ)) {
+        if (STATS) st[6] += 1;
+        occ_hint_front(occ_hint, h);
+        return need;
+      }
     }
   }
   for (int cb = 0; cb < d.NC; cb += kWave) {
@@ -699,7 +729,7 @@ __device__ __forceinline__ u64 wave_blocked_perp(const Geo& d, int px, int py, u
       const u64 om = ballot(occ);
       if (om) {
         if (STATS) st[6] += 1;
-        if (occ_hint) *occ_hint = chunk * kChunk + first_bit(om);
+        if (occ_hint) occ_hint_push(occ_hint, chunk * kChunk + first_bit(om));
         return need;
       }
       u64 rm = ballot(rel);
