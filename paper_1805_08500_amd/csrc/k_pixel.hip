@@ -125,6 +125,9 @@ constexpr int kPrioTries = 6;   // candidates after which a seed search raises i
 #define SPM_SEED_WIDE 4
 #endif
 constexpr int kSeedWide = SPM_SEED_WIDE;   // candidates per round once a seed search has made kPrioTries tries
+#ifndef SPM_EST_WALK
+#define SPM_EST_WALK 1   // up to kEstCache * 64 generators: walk them in lower-bound order, without seed searches
+#endif
 #ifndef SPM_SEED_SHARE
 #define SPM_SEED_SHARE 1   // later seed searches of a tile skip the candidates earlier ones tried
 #endif
@@ -533,6 +536,45 @@ __device__ __forceinline__ int tile_work(int tile, int W, int H, int W32, int G,
         UB = fmaxf(fmaxf(ubq[0], ubq[1]), fmaxf(ubq[2], ubq[3]));
       }
     };
+    if (SPM_EST_WALK && G <= kEstCache * 64) {
+      // Up to kEstCache * 64 generators: all of them in order of a lower bound
+      // of their value over the active pixels' box, cost + |box - box(g)|
+      // (shaded down by 4e-6 so that rounding keeps it below every pixel's
+      // float value), kept in registers and taken out least first.  Once the
+      // least remaining bound exceeds the tile's largest value no generator
+      // can improve any pixel.  The first candidates are the likely winners,
+      // so the bounds tighten at once and no seed search is needed.
+      int bx0, by0, bx1, by1;
+      mask_box<TW>(act, i0, j0, bx0, by0, bx1, by1);
+      float ec[kEstCache];
+#pragma unroll
+      for (int s = 0; s < kEstCache; ++s) {
+        const int h = lane + 64 * s;
+        float v = INFINITY;
+        if (h < G) {
+          const int4 b = sgbb[h];
+          const float dx = (float)max(max(b.x - bx1, bx0 - b.z), 0), dy = (float)max(max(b.y - by1, by0 - b.w), 0);
+          v = (sgcost[h] + 0.5f * fsqrt(dx * dx + dy * dy)) * (1.0f - 4e-6f);
+        }
+        ec[s] = v;
+      }
+      unsigned rej = 0;
+      for (;;) {
+        float m;
+        const int k = seed_pop(ec, rej, m);
+        if (k < 0 || m > UB) break;
+        if (STATS) st[ST_BATCHES] += 1;
+        const int4 kb = sgbb[k];
+        const float kc = unif(sgcost[k]);
+        const int kx0 = uni(kb.x), ky0 = uni(kb.y), kx1 = uni(kb.z), ky1 = uni(kb.w);
+        if (!(box_may_win(kc, kx0, ky0, kx1, ky1, qx0, qy0, qx1 - 2, qy1 - 2, ubq[0]) ||
+              box_may_win(kc, kx0, ky0, kx1, ky1, qx1, qy0, qx1 + TW - 2, qy1 - 2, ubq[1]) ||
+              box_may_win(kc, kx0, ky0, kx1, ky1, qx0, qy1, qx1 - 2, qy1 + TH - 2, ubq[2]) ||
+              box_may_win(kc, kx0, ky0, kx1, ky1, qx1, qy1, qx1 + TW - 2, qy1 + TH - 2, ubq[3])))
+          continue;
+        try_gen(k, kc, kx0, ky0, kx1, ky1);
+      }
+    } else {
     // Seeds first: the previous tile's winners (distinct values), then seed
     // searches from pixels that still have no value.  Each is evaluated
     // exactly for every lane and remembered, so the walk skips it.
@@ -602,6 +644,7 @@ __device__ __forceinline__ int tile_work(int tile, int W, int H, int W32, int G,
         if (UB != ub0) cm &= ballot(bound());   // the bounds tightened: drop what they now exclude
       }
       if (done) break;
+    }
     }
   }
   if (valid) {
