@@ -125,9 +125,18 @@ constexpr int kPrioTries = 6;   // candidates after which a seed search raises i
 #define SPM_SEED_WIDE 4
 #endif
 constexpr int kSeedWide = SPM_SEED_WIDE;   // candidates per round once a seed search has made kPrioTries tries
-#ifndef SPM_EST_WALK
-#define SPM_EST_WALK 1   // up to kEstCache * 64 generators: walk them in lower-bound order, without seed searches
-#endif
+// How a tile walks the generators (a template parameter chosen on the host
+// from the scene's largest possible generator count):
+//   kWalkCached  up to kEstCache * 64 generators: lower-bound order, every
+//                estimate in registers;
+//   kWalkRefill  up to kEstWalkMax: lower-bound order, the least kEstCache
+//                per lane in registers, refilled when needed;
+//   kWalkCost    beyond: seed searches, then (cost, id) order.
+enum { kWalkCached = 0, kWalkRefill = 1, kWalkCost = 2 };
+constexpr int kEstWalkMax = 64 * 64;
+inline int walk_mode(int gmax) {
+  return gmax <= kEstCache * 64 ? kWalkCached : (gmax <= kEstWalkMax ? kWalkRefill : kWalkCost);
+}
 #ifndef SPM_SEED_SHARE
 #define SPM_SEED_SHARE 1   // later seed searches of a tile skip the candidates earlier ones tried
 #endif
@@ -423,7 +432,7 @@ __device__ int seed_search(const Geo& geo, const GenRec* sgen, const float* sgco
 //   samples: how many seed searches (seed_search) to run, each from a pixel
 //            still without a value after the seeds tried so far.
 // Returns this tile's per-lane winner position (for the next tile).
-template <int TW, bool STATS>
+template <int TW, bool STATS, int WALK>
 __device__ __forceinline__ int tile_work(int tile, int W, int H, int W32, int G, const unsigned* __restrict__ inside,
                                          const GenRec* sgen, const float* sgcost, const int4* sgbb, const Geo& geo,
                                          float* __restrict__ dist, int* __restrict__ parent, int prevpos,
@@ -536,33 +545,117 @@ __device__ __forceinline__ int tile_work(int tile, int W, int H, int W32, int G,
         UB = fmaxf(fmaxf(ubq[0], ubq[1]), fmaxf(ubq[2], ubq[3]));
       }
     };
-    if (SPM_EST_WALK && G <= kEstCache * 64) {
-      // Up to kEstCache * 64 generators: all of them in order of a lower bound
-      // of their value over the active pixels' box, cost + |box - box(g)|
-      // (shaded down by 4e-6 so that rounding keeps it below every pixel's
-      // float value), kept in registers and taken out least first.  Once the
-      // least remaining bound exceeds the tile's largest value no generator
-      // can improve any pixel.  The first candidates are the likely winners,
-      // so the bounds tighten at once and no seed search is needed.
+    if constexpr (WALK == kWalkCached) {
+      // Up to kEstCache * 64 generators: every estimate fits in the registers
+      // (lane l, slot q: generator l + 64 q), the same order as below without
+      // refills.
       int bx0, by0, bx1, by1;
       mask_box<TW>(act, i0, j0, bx0, by0, bx1, by1);
       float ec[kEstCache];
 #pragma unroll
-      for (int s = 0; s < kEstCache; ++s) {
-        const int h = lane + 64 * s;
+      for (int q = 0; q < kEstCache; ++q) {
+        const int h = lane + 64 * q;
         float v = INFINITY;
         if (h < G) {
           const int4 b = sgbb[h];
           const float dx = (float)max(max(b.x - bx1, bx0 - b.z), 0), dy = (float)max(max(b.y - by1, by0 - b.w), 0);
           v = (sgcost[h] + 0.5f * fsqrt(dx * dx + dy * dy)) * (1.0f - 4e-6f);
         }
-        ec[s] = v;
+        ec[q] = v;
       }
       unsigned rej = 0;
       for (;;) {
         float m;
         const int k = seed_pop(ec, rej, m);
         if (k < 0 || m > UB) break;
+        if (STATS) st[ST_BATCHES] += 1;
+        const int4 kb = sgbb[k];
+        const float kc = unif(sgcost[k]);
+        const int kx0 = uni(kb.x), ky0 = uni(kb.y), kx1 = uni(kb.z), ky1 = uni(kb.w);
+        if (!(box_may_win(kc, kx0, ky0, kx1, ky1, qx0, qy0, qx1 - 2, qy1 - 2, ubq[0]) ||
+              box_may_win(kc, kx0, ky0, kx1, ky1, qx1, qy0, qx1 + TW - 2, qy1 - 2, ubq[1]) ||
+              box_may_win(kc, kx0, ky0, kx1, ky1, qx0, qy1, qx1 - 2, qy1 + TH - 2, ubq[2]) ||
+              box_may_win(kc, kx0, ky0, kx1, ky1, qx1, qy1, qx1 + TW - 2, qy1 + TH - 2, ubq[3])))
+          continue;
+        try_gen(k, kc, kx0, ky0, kx1, ky1);
+      }
+    } else if constexpr (WALK == kWalkRefill) {
+      // All generators in order of a lower bound of their value over the
+      // active pixels' box, cost + |box - box(g)| (shaded down by 4e-6 so that
+      // rounding keeps it below every pixel's float value).  Lane l owns the
+      // generators l + 64 j; it keeps the kEstCache least of those not yet
+      // taken in registers, and T is the least estimate left out of every
+      // lane's cache: while the least cached estimate is at most T it is the
+      // least of all, else the caches are refilled.  Once the least estimate
+      // exceeds the tile's largest value no generator can improve any pixel.
+      // The first candidates are the likely winners, so the bounds tighten at
+      // once and no seed search is needed.
+      int bx0, by0, bx1, by1;
+      mask_box<TW>(act, i0, j0, bx0, by0, bx1, by1);
+      auto est_box = [&](int h) -> float {
+        const int4 b = sgbb[h];
+        const float dx = (float)max(max(b.x - bx1, bx0 - b.z), 0), dy = (float)max(max(b.y - by1, by0 - b.w), 0);
+        return (sgcost[h] + 0.5f * fsqrt(dx * dx + dy * dy)) * (1.0f - 4e-6f);
+      };
+      const int nj = lane < G ? (G - lane + 63) / 64 : 0;   // generators this lane owns
+      float ec[kEstCache];
+      int ej[kEstCache];
+      u64 taken = 0;        // per lane: the j already taken out
+      float T = INFINITY;   // least estimate left out of the caches (wave-uniform)
+      auto refill = [&]() {
+        float tl = INFINITY;
+#pragma unroll
+        for (int q = 0; q < kEstCache; ++q) {
+          ec[q] = (q < nj && !((taken >> q) & 1ull)) ? est_box(lane + 64 * q) : INFINITY;
+          ej[q] = q;
+        }
+        for (int j = kEstCache; j < nj; ++j) {
+          if ((taken >> j) & 1ull) continue;
+          const float v = est_box(lane + 64 * j);
+          float mx = ec[0];
+          int ms = 0;
+#pragma unroll
+          for (int q = 1; q < kEstCache; ++q)
+            if (ec[q] > mx) { mx = ec[q]; ms = q; }
+          if (v < mx) {
+            tl = fminf(tl, mx);
+#pragma unroll
+            for (int q = 0; q < kEstCache; ++q)
+              if (q == ms) { ec[q] = v; ej[q] = j; }
+          } else {
+            tl = fminf(tl, v);
+          }
+        }
+        T = __uint_as_float(wave_min_u32(__float_as_uint(tl)));
+      };
+      refill();
+      // every pass takes a generator out or refills (after which the least cached estimate is at most T)
+      for (int pass = 0; pass < 2 * G + 2; ++pass) {
+        float bv = INFINITY;
+        int bs = 0;
+#pragma unroll
+        for (int q = 0; q < kEstCache; ++q)
+          if (ec[q] < bv) { bv = ec[q]; bs = q; }
+        const unsigned key = __float_as_uint(bv);
+        const unsigned mk = wave_min_u32(key);
+        const float m = __uint_as_float(mk);
+        if (m > T) {   // a generator left out of the caches may come first
+          refill();
+          continue;
+        }
+        if (mk >= 0x7f800000u || m > UB) break;
+        const int wl = first_bit(ballot(key == mk));
+        int jq = ej[0];
+#pragma unroll
+        for (int q = 1; q < kEstCache; ++q)
+          if (q == bs) jq = ej[q];
+        if (lane == wl) {
+          taken |= 1ull << jq;
+#pragma unroll
+          for (int q = 0; q < kEstCache; ++q)
+            if (q == bs) ec[q] = INFINITY;
+        }
+        const int k = wl + 64 * readlane_i(jq, wl);
         if (STATS) st[ST_BATCHES] += 1;
         const int4 kb = sgbb[k];
         const float kc = unif(sgcost[k]);
@@ -664,6 +757,9 @@ constexpr size_t kPixelLdsMax = 64 * 1024;
 #ifndef SPM_PIXEL_MIN_WAVES
 #define SPM_PIXEL_MIN_WAVES 4   // waves per SIMD the register budget of k_pixel is sized for
 #endif
+#ifndef SPM_PIXEL_MIN_WAVES_CACHED
+#define SPM_PIXEL_MIN_WAVES_CACHED 6   // the same for the register-cached walk (80 VGPRs)
+#endif
 
 size_t pixel_lds_bytes(int Gmax, int E, int NC) {
   return (size_t)Gmax * (sizeof(GenRec) + 4 + 16) + 16 + (size_t)E * sizeof(EdgeRec) + (size_t)NC * 16;
@@ -757,8 +853,8 @@ __global__ __launch_bounds__(kOrderThreads) void k_tile_order(int W, int H, int 
 // table, the edges and the chunk boxes are first staged in LDS, so the
 // wave-uniform reads of the hot loops are LDS broadcasts instead of L2 round
 // trips.
-template <int TW, bool STATS, bool LDSD>
-__global__ __launch_bounds__(kPixelThreads, SPM_PIXEL_MIN_WAVES) void k_pixel(int W, int H, int W32, int Gmax, int* misc,
+template <int TW, bool STATS, bool LDSD, int WALK>
+__global__ __launch_bounds__(kPixelThreads, WALK == kWalkCached ? SPM_PIXEL_MIN_WAVES_CACHED : SPM_PIXEL_MIN_WAVES) void k_pixel(int W, int H, int W32, int Gmax, int* misc,
                                                          const unsigned* __restrict__ inside,
                                                          const GenRec* __restrict__ sgen_g,
                                                          const float* __restrict__ sgcost_g,
@@ -834,7 +930,7 @@ __global__ __launch_bounds__(kPixelThreads, SPM_PIXEL_MIN_WAVES) void k_pixel(in
     const int t0 = sx * strip, t1 = min(t0 + strip, ntx);
     int prev = -1;
     for (int t = t0; t < t1; ++t)
-      prev = tile_work<TW, STATS>(ty * ntx + t, W, H, W32, G, inside, sgen, sgcost, sgbb, geo, dist, parent, prev,
+      prev = tile_work<TW, STATS, WALK>(ty * ntx + t, W, H, W32, G, inside, sgen, sgcost, sgbb, geo, dist, parent, prev,
                                   samples, st);
     int n = 0;
     if (lane_id() == 0) n = atomicAdd(&qctr[q * kQueueStride], 1);
@@ -859,9 +955,9 @@ static int device_cus() {
   return cached[dev];
 }
 
-template <int TW, bool STATS, bool LDSD>
+template <int TW, bool STATS, bool LDSD, int WALK>
 static hipError_t launch_variant(const Dev& d, hipStream_t s, size_t shm) {
-  auto kern = k_pixel<TW, STATS, LDSD>;
+  auto kern = k_pixel<TW, STATS, LDSD, WALK>;
   int per_cu = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kPixelThreads, shm) != hipSuccess || per_cu < 1)
     per_cu = 1;
@@ -891,12 +987,22 @@ static hipError_t launch_variant(const Dev& d, hipStream_t s, size_t shm) {
   return hipGetLastError();
 }
 
-template <int TW>
-static hipError_t launch_tw(const Dev& d, hipStream_t s) {
+template <int TW, int WALK>
+static hipError_t launch_tw_walk(const Dev& d, hipStream_t s) {
   const size_t shm = pixel_lds_bytes(d.Gmax, d.E, d.NC);
   const bool lds = shm <= kPixelLdsMax;
-  if (d.stats) return lds ? launch_variant<TW, true, true>(d, s, shm) : launch_variant<TW, true, false>(d, s, 0);
-  return lds ? launch_variant<TW, false, true>(d, s, shm) : launch_variant<TW, false, false>(d, s, 0);
+  if (d.stats)
+    return lds ? launch_variant<TW, true, true, WALK>(d, s, shm) : launch_variant<TW, true, false, WALK>(d, s, 0);
+  return lds ? launch_variant<TW, false, true, WALK>(d, s, shm) : launch_variant<TW, false, false, WALK>(d, s, 0);
+}
+
+template <int TW>
+static hipError_t launch_tw(const Dev& d, hipStream_t s) {
+  switch (walk_mode(d.Gmax)) {
+    case kWalkCached: return launch_tw_walk<TW, kWalkCached>(d, s);
+    case kWalkRefill: return launch_tw_walk<TW, kWalkRefill>(d, s);
+    default: return launch_tw_walk<TW, kWalkCost>(d, s);
+  }
 }
 
 hipError_t launch_pixel(const Dev& d, hipStream_t s) {
@@ -912,7 +1018,7 @@ hipError_t launch_pixel(const Dev& d, hipStream_t s) {
 // scene's generator table and edges in LDS when it differs from the scene
 // already staged, and its wavefronts share the slice's tiles through an LDS
 // counter.
-template <bool LDSD, int TW>
+template <bool LDSD, int TW, int WALK>
 __global__ __launch_bounds__(kPixelThreads, SPM_PIXEL_MIN_WAVES) void k_pixel_batch(BatchSrc src, int* ctr) {
   extern __shared__ int4 smem[];
   __shared__ int item_scene, item_t0, item_t1, staged, next_tile;
@@ -976,7 +1082,7 @@ __global__ __launch_bounds__(kPixelThreads, SPM_PIXEL_MIN_WAVES) void k_pixel_ba
         const int tb = min(ta + d.strip, item_t1);
         int prev = -1;
         for (int tile = ta; tile < tb; ++tile)
-          prev = tile_work<TW, false>(tile, d.W, d.H, d.W32, G, d.inside, sgen, sgcost, sgbb, geo, d.dist, d.parent,
+          prev = tile_work<TW, false, WALK>(tile, d.W, d.H, d.W32, G, d.inside, sgen, sgcost, sgbb, geo, d.dist, d.parent,
                                       prev, d.samples, st);
       }
     }
@@ -988,11 +1094,11 @@ __global__ void k_reset_counters(int* ctr) {
   if (threadIdx.x < 3) ctr[16 * threadIdx.x] = 0;
 }
 
-template <int TW>
-static hipError_t launch_batch_tw(const BatchSrc& b, const Plan& p, int* ctr, hipStream_t s) {
+template <int TW, int WALK>
+static hipError_t launch_batch_tw_walk(const BatchSrc& b, const Plan& p, int* ctr, hipStream_t s) {
   const size_t shm = p.pixel_lds;
   const bool lds = shm > 0 && shm <= kPixelLdsMax;
-  auto kern = lds ? k_pixel_batch<true, TW> : k_pixel_batch<false, TW>;
+  auto kern = lds ? k_pixel_batch<true, TW, WALK> : k_pixel_batch<false, TW, WALK>;
   const size_t use = lds ? shm : 0;
   int per_cu = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kPixelThreads, use) != hipSuccess || per_cu < 1)
@@ -1002,6 +1108,15 @@ static hipError_t launch_batch_tw(const BatchSrc& b, const Plan& p, int* ctr, hi
   if (blocks < 1) blocks = 1;
   hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(kPixelThreads), use, s, b, ctr);
   return hipGetLastError();
+}
+
+template <int TW>
+static hipError_t launch_batch_tw(const BatchSrc& b, const Plan& p, int* ctr, hipStream_t s) {
+  switch (walk_mode(p.maxGmax)) {
+    case kWalkCached: return launch_batch_tw_walk<TW, kWalkCached>(b, p, ctr, s);
+    case kWalkRefill: return launch_batch_tw_walk<TW, kWalkRefill>(b, p, ctr, s);
+    default: return launch_batch_tw_walk<TW, kWalkCost>(b, p, ctr, s);
+  }
 }
 
 // ctr: three queue counters, 16 ints apart (one per tile shape)
