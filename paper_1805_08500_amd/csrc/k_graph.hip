@@ -52,7 +52,7 @@ __device__ __forceinline__ double arc_len(const GenRec& u, int vx, int vy) {
 // spatial position (gorder), so the generators of a wavefront are
 // neighbours in space and the box that culls the edges stays small.
 //
-// Segment columns: one wavefront per (segment source s, 64 corner positions).
+// Segment columns: one wavefront per (segment source s, kSegCols corner positions).
 // A corner v sees s when it sees the closest point q*(v) of s (Section 4).
 // Lanes whose closest point is an endpoint share that endpoint (the
 // wave-level point test); for the others [v, q*] is perpendicular to s (the
@@ -220,13 +220,13 @@ __device__ __forceinline__ void genvis_pairs(const Dev& d, const Geo& geo, int w
 
 __device__ __forceinline__ void genvis_segments(const Dev& d, const Geo& geo, int item) {
   const int nsrc = d.np + d.ns;
-  const int nblk = (d.Gmax - nsrc + 63) / 64;
+  const int nblk = (d.Gmax - nsrc + kSegCols - 1) / kSegCols;
   const int s = item / nblk, blk = item - s * nblk;
   const int G = uni(d.misc[MISC_G]);
   const int lane = lane_id();
-  const int r = nsrc + blk * 64 + lane;   // this lane's corner position
-  const int spos = d.np + s;              // the segment's position (= its id)
-  const bool valid = r < G;
+  const int r = nsrc + blk * kSegCols + lane;   // this lane's corner position (lanes below kSegCols)
+  const int spos = d.np + s;                    // the segment's position (= its id)
+  const bool valid = lane < kSegCols && r < G;
   GenRec cv = {};
   if (valid) cv = d.gens[d.gorder[r]];
   const GenRec sg = d.gens[spos];

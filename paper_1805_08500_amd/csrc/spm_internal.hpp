@@ -32,6 +32,10 @@ constexpr int kMaxStrip = 64;
 constexpr int kQueues = 8;         // pixel-stage work queues (one per XCD)
 constexpr int kQueueStride = 32;   // ints between queue counters (one 128-byte line each)
 constexpr int kOrderBins = 32;     // pixel-stage work classes (tiles ranked by a distance lower bound)
+#ifndef SPM_SEG_COLS
+#define SPM_SEG_COLS 16
+#endif
+constexpr int kSegCols = SPM_SEG_COLS;   // corners per segment-column wavefront of generator visibility
 #ifndef SPM_GV_PAIR_ROWS
 #define SPM_GV_PAIR_ROWS 16
 #endif
@@ -207,7 +211,7 @@ enum StageKind {
   STG_GVBLK,     // one 4-wavefront workgroup per 4 (row, gv_sub columns) generator-visibility items
   STG_GEN,       // one wavefront per generator slot
   STG_SLICE,     // one pixel-tile slice (batched pixel stage)
-  STG_SEGVIS,    // one wavefront per (segment source, 64 corner positions)
+  STG_SEGVIS,    // one wavefront per (segment source, kSegCols corner positions)
   STG_RELAXW,    // one thread per (corner row, byte of a 64-bit word) of the visibility matrix
   STG_COUNT
 };
@@ -229,7 +233,7 @@ __host__ __device__ inline int stage_count(const Dev& d, int stage) {
     }
     case STG_GEN: return d.Gmax;
     case STG_SLICE: return (tiles_of(d.W, d.H, d.tile_w) + kSlice - 1) / kSlice;
-    case STG_SEGVIS: return d.ns * ((d.Gmax - d.np - d.ns + 63) / 64);
+    case STG_SEGVIS: return d.ns * ((d.Gmax - d.np - d.ns + kSegCols - 1) / kSegCols);
     case STG_RELAXW: return (d.Gmax - d.np - d.ns) * d.RW * 8;
     default: return 0;
   }
