@@ -120,7 +120,10 @@ constexpr int kSeedTries = 128; // candidates one seed search may reject
 #endif
 constexpr int kSeedTriesUncached = SPM_SEED_TRIES_UNCACHED;   // the same when each try recomputes every estimate
 constexpr int kEstCache = 8;    // seed-search estimates kept in registers per lane
-constexpr int kPrioTries = 6;   // candidates after which a seed search raises its wave's priority
+#ifndef SPM_PRIO_TRIES
+#define SPM_PRIO_TRIES 3
+#endif
+constexpr int kPrioTries = SPM_PRIO_TRIES;   // tests after which a tile raises its wave's priority
 #ifndef SPM_SEED_WIDE
 #define SPM_SEED_WIDE 4
 #endif
