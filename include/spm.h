@@ -112,9 +112,10 @@ int spm_build(const spm_scene* dev_scene, const spm_out* out, void* d_ws, size_t
 /* Optional per-stage timing: a timer records HIP events around each build
  * stage on the build's stream.  spm_timer_elapsed synchronises on the last
  * recorded event and returns the per-stage milliseconds summed over every
- * build recorded since the last reset (stage order: ingest, edge sort,
- * inside mask, generator visibility, relaxation, generator sort, pixel
- * propagation, total) and the number of builds. */
+ * build recorded since the last reset (stage order: ingest, edge sort and
+ * inside mask, generator order and chunk boxes, generator visibility,
+ * relaxation, generator sort, pixel propagation (with its work order), total)
+ * and the number of builds. */
 typedef struct spm_timer spm_timer;
 int spm_timer_create(spm_timer** t);
 int spm_timer_destroy(spm_timer* t);

@@ -22,7 +22,7 @@ SPM_N_STAGES = 8
 SPM_MAX_SIDE = 8192
 GEN_POINT, GEN_SEGMENT, GEN_VERTEX = 0, 1, 2
 
-STAGES = ("ingest", "edge_sort", "inside", "genvis", "relax", "gsort", "pixel", "total")
+STAGES = ("ingest", "edge_sort", "gorder", "genvis", "relax", "gsort", "pixel", "total")
 
 c_i32 = ctypes.c_int32
 c_vp = ctypes.c_void_p

@@ -142,9 +142,9 @@ __global__ __launch_bounds__(1024) void k_gen_table(S src) {
 // sorted order.  Any edge order gives the same result; the sort only makes
 // each chunk of consecutive edges spatially compact for culling.
 template <class S>
-__global__ __launch_bounds__(256) void k_edge_rank(S src) {
+__device__ __forceinline__ void edge_rank_wave(const S& src, int wid) {
   int sc, w;
-  if (!src.locate(STG_EDGE, blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6), sc, w)) return;
+  if (!src.locate(STG_EDGE, wid, sc, w)) return;
   const Dev& d = src.scene(sc);
   const int lane = lane_id();
   const int E = d.E;
@@ -165,12 +165,10 @@ __global__ __launch_bounds__(256) void k_edge_rank(S src) {
 // generator-graph kernels.  Sources keep their ids as positions; then come the
 // convex corners in the Morton order of their outgoing edges.
 template <class S>
-__global__ __launch_bounds__(1024) void k_gorder(S src) {
+__device__ __forceinline__ void gorder_block(const S& src, int item, int* wave_tot, int& running) {
   int sc, one;
-  if (!src.locate(STG_SCENE, blockIdx.x, sc, one)) return;
+  if (!src.locate(STG_SCENE, item, sc, one)) return;
   const Dev& d = src.scene(sc);
-  __shared__ int wave_tot[16];
-  __shared__ int running;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int nsrc = d.np + d.ns, E = d.E;
   for (int g = tid; g < nsrc; g += blockDim.x) d.gorder[g] = g;
@@ -201,9 +199,9 @@ __global__ __launch_bounds__(1024) void k_gorder(S src) {
 // One wavefront per chunk of kChunk sorted edges (one edge per lane): the
 // bounding box of their endpoints.
 template <class S>
-__global__ __launch_bounds__(256) void k_chunk_boxes(S src) {
+__device__ __forceinline__ void chunk_box_wave(const S& src, int wid) {
   int sc, c;
-  if (!src.locate(STG_CHUNK, blockIdx.x * 4 + (threadIdx.x >> 6), sc, c)) return;
+  if (!src.locate(STG_CHUNK, wid, sc, c)) return;
   const Dev& d = src.scene(sc);
   const int e = c * kChunk + lane_id();
   int x0 = 1 << 30, y0 = 1 << 30, x1 = -(1 << 30), y1 = -(1 << 30);
@@ -232,18 +230,16 @@ __device__ __forceinline__ int floor_div(int a, int b) {  // b > 0
 // passes through a vertex; each edge crossing it toggles the parity of the
 // pixels to its left, and a centre exactly on an edge counts as inside.
 template <class S>
-__global__ __launch_bounds__(256) void k_inside(S src) {
+__device__ __forceinline__ void inside_row(const S& src, int item, int* sh, int* wave_tot) {
   int sc, j;
-  if (!src.locate(STG_ROW, blockIdx.x, sc, j)) return;
+  if (!src.locate(STG_ROW, item, sc, j)) return;
   const Dev& d = src.scene(sc);
-  extern __shared__ int sh[];
   const int W = d.W, E = d.E, W32 = d.W32;
   int* tog = sh;                                      // [W + 1]
   unsigned char* on = (unsigned char*)(sh + W + 1);   // [W]
   const int tid = threadIdx.x;
   const int y = 2 * j + 1;
   const int lane = tid & 63, wv = tid >> 6, nw = blockDim.x >> 6;
-  __shared__ int wave_tot[4];
   for (int k = tid; k <= W; k += blockDim.x) tog[k] = 0;
   for (int k = tid; k < W; k += blockDim.x) on[k] = 0;
   __syncthreads();
@@ -304,6 +300,28 @@ static inline unsigned blocks_for(long long items, int per_block) {
   return (unsigned)((items + per_block - 1) / per_block);
 }
 
+// Two independent steps in one launch: the first nrank workgroups rank the
+// edges (one wavefront per edge), the others build the inside mask (one
+// workgroup per pixel row, from the raw edges).
+template <class S>
+__global__ __launch_bounds__(256) void k_rank_inside(S src, int nrank) {
+  extern __shared__ int sh[];
+  __shared__ int wave_tot[4];
+  if ((int)blockIdx.x < nrank) edge_rank_wave(src, blockIdx.x * 4 + (threadIdx.x >> 6));
+  else inside_row(src, blockIdx.x - nrank, sh, wave_tot);
+}
+
+// Two independent steps on the sorted edges in one launch: the first
+// ngorder workgroups order the generators (one per scene), the others box the
+// edge chunks (one wavefront per chunk).
+template <class S>
+__global__ __launch_bounds__(1024) void k_gorder_boxes(S src, int ngorder) {
+  __shared__ int wave_tot[16];
+  __shared__ int running;
+  if ((int)blockIdx.x < ngorder) gorder_block(src, blockIdx.x, wave_tot, running);
+  else chunk_box_wave(src, (blockIdx.x - ngorder) * 16 + (threadIdx.x >> 6));
+}
+
 template <class S>
 hipError_t launch_ingest(const S& src, const Plan& p, hipStream_t s) {
   if (p.total[STG_VTX] > 0)
@@ -312,20 +330,21 @@ hipError_t launch_ingest(const S& src, const Plan& p, hipStream_t s) {
   return hipGetLastError();
 }
 
+// Stage "edge sort": edge ranks and the inside mask.
 template <class S>
 hipError_t launch_edge_sort(const S& src, const Plan& p, hipStream_t s) {
-  if (p.total[STG_EDGE] > 0)
-    hipLaunchKernelGGL(k_edge_rank<S>, dim3(blocks_for(p.total[STG_EDGE], 4)), dim3(256), 0, s, src);
-  hipLaunchKernelGGL(k_gorder<S>, dim3((unsigned)p.total[STG_SCENE]), dim3(1024), 0, s, src);
-  if (p.total[STG_CHUNK] > 0)
-    hipLaunchKernelGGL(k_chunk_boxes<S>, dim3(blocks_for(p.total[STG_CHUNK], 4)), dim3(256), 0, s, src);
+  const unsigned nrank = p.total[STG_EDGE] > 0 ? blocks_for(p.total[STG_EDGE], 4) : 0u;
+  const size_t shm = (size_t)(p.maxW + 1) * sizeof(int) + (size_t)p.maxW + 16;
+  hipLaunchKernelGGL(k_rank_inside<S>, dim3(nrank + (unsigned)p.total[STG_ROW]), dim3(256), shm, s, src, (int)nrank);
   return hipGetLastError();
 }
 
+// Stage "generator order": the spatial generator order and the chunk boxes.
 template <class S>
-hipError_t launch_inside(const S& src, const Plan& p, hipStream_t s) {
-  const size_t shm = (size_t)(p.maxW + 1) * sizeof(int) + (size_t)p.maxW + 16;
-  hipLaunchKernelGGL(k_inside<S>, dim3((unsigned)p.total[STG_ROW]), dim3(256), shm, s, src);
+hipError_t launch_gorder(const S& src, const Plan& p, hipStream_t s) {
+  const unsigned ng = (unsigned)p.total[STG_SCENE];
+  const unsigned nb = p.total[STG_CHUNK] > 0 ? blocks_for(p.total[STG_CHUNK], 16) : 0u;
+  hipLaunchKernelGGL(k_gorder_boxes<S>, dim3(ng + nb), dim3(1024), 0, s, src, (int)ng);
   return hipGetLastError();
 }
 
@@ -333,7 +352,7 @@ template hipError_t launch_ingest<SingleSrc>(const SingleSrc&, const Plan&, hipS
 template hipError_t launch_ingest<BatchSrc>(const BatchSrc&, const Plan&, hipStream_t);
 template hipError_t launch_edge_sort<SingleSrc>(const SingleSrc&, const Plan&, hipStream_t);
 template hipError_t launch_edge_sort<BatchSrc>(const BatchSrc&, const Plan&, hipStream_t);
-template hipError_t launch_inside<SingleSrc>(const SingleSrc&, const Plan&, hipStream_t);
-template hipError_t launch_inside<BatchSrc>(const BatchSrc&, const Plan&, hipStream_t);
+template hipError_t launch_gorder<SingleSrc>(const SingleSrc&, const Plan&, hipStream_t);
+template hipError_t launch_gorder<BatchSrc>(const BatchSrc&, const Plan&, hipStream_t);
 
 }  // namespace spm

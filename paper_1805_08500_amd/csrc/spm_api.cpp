@@ -366,8 +366,8 @@ int check_tile(int tw, int th) {
   return SPM_OK;
 }
 
-const char* kStageNames[7] = {"ingest", "edge sort", "inside mask", "generator visibility", "relaxation",
-                              "generator sort", "pixel propagation"};
+const char* kStageNames[7] = {"ingest", "edge sort and inside mask", "generator order and chunk boxes",
+                              "generator visibility", "relaxation", "generator sort", "pixel propagation"};
 
 // queue the seven stages of a build for a scene source; marks timer events
 template <class S, class PixelFn>
@@ -385,7 +385,7 @@ int run_stages(const S& src, const Plan& p, hipStream_t st, spm_timer* tm, Pixel
     switch (k) {
       case 0: e = launch_ingest(src, p, st); break;
       case 1: e = launch_edge_sort(src, p, st); break;
-      case 2: e = launch_inside(src, p, st); break;
+      case 2: e = launch_gorder(src, p, st); break;
       case 3: e = launch_genvis(src, p, st); break;
       case 4: e = launch_relax(src, p, st); break;
       case 5: e = launch_gsort(src, p, st); break;

@@ -284,7 +284,7 @@ struct Plan {
 // host launchers (each queues kernels on the stream and returns hipError_t)
 template <class S> hipError_t launch_ingest(const S& src, const Plan& p, hipStream_t s);
 template <class S> hipError_t launch_edge_sort(const S& src, const Plan& p, hipStream_t s);
-template <class S> hipError_t launch_inside(const S& src, const Plan& p, hipStream_t s);
+template <class S> hipError_t launch_gorder(const S& src, const Plan& p, hipStream_t s);
 template <class S> hipError_t launch_genvis(const S& src, const Plan& p, hipStream_t s);
 template <class S> hipError_t launch_relax(const S& src, const Plan& p, hipStream_t s);
 template <class S> hipError_t launch_gsort(const S& src, const Plan& p, hipStream_t s);
