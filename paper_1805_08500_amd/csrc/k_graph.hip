@@ -6,16 +6,17 @@
 // Here the same costs come from three kernels (templates over the scene
 // source, like the ingest kernels):
 //   k_genvis   every (corner, generator) arc of the visibility graph, as a
-//              bit matrix (one wavefront per 64 arcs, exact predicates);
-//   k_genvis_seg  the columns of segment sources in that matrix;
-//   k_relax_wide, k_relax, k_relax_parents
+//              bit matrix (exact predicates; by pairs with lanes over edges,
+//              or lanes over generators), and the columns of segment sources;
+//   k_relax_wide, k_relax
 //              Bellman-Ford over that matrix in double precision, iterated to
 //              its fixed point (which Dijkstra also reaches): the first rounds
-//              chip-wide, the rest in one workgroup; then each corner's
-//              parent: the smallest id among the visible predecessors that
-//              attain its cost;
-//   k_gsort    the reached generators ordered by (float cost, id), the order
-//              the pixel stage walks them in.
+//              chip-wide, the rest in one workgroup;
+//   k_gsort_parents
+//              the reached generators ordered by (float cost, id), the order
+//              the pixel stage walks them in; and each corner's parent: the
+//              smallest id among the visible predecessors that attain its
+//              cost.
 #include <math.h>
 
 #include "spm_internal.hpp"
@@ -368,44 +369,49 @@ __global__ __launch_bounds__(256) void k_relax_wide(S src, int round) {
   }
 }
 
-// Parents over the whole chip, once the costs are final: one thread per
-// (corner row p, byte of word k); the smallest canonical id among the visible
-// predecessors attaining cost(p), merged by an atomic minimum (parcan was set
-// to INT_MAX by k_relax).
+// Parents, once the costs are final: one wavefront per spatial position p,
+// lanes over the 64 generators of each bit word of row p (four words per
+// step, all loads requested together): the smallest canonical id among the
+// visible predecessors attaining cost(p).  Sources are their own parents,
+// unreached generators have none (-1).
 template <class S>
-__global__ __launch_bounds__(256) void k_relax_parents(S src) {
-  int sc, it;
-  if (!src.locate(STG_RELAXW, blockIdx.x * blockDim.x + threadIdx.x, sc, it)) return;
+__device__ __forceinline__ void parent_wave(const S& src, int wid) {
+  int sc, p;
+  if (!src.locate(STG_GEN, wid, sc, p)) return;
   const Dev& d = src.scene(sc);
+  const int G = uni(d.misc[MISC_G]);
+  if (p >= G) return;
+  const int lane = lane_id();
   const int RW = d.RW, nsrc = d.np + d.ns;
-  const int pk = it >> 3, sh = (it & 7) * 8;
-  const int p = nsrc + pk / RW, k = pk - (pk / RW) * RW;
-  if (p >= d.misc[MISC_G]) return;
+  const int g = uni(d.gorder[p]);
   const double c = __longlong_as_double((long long)d.costpos[p]);
-  if (!(c < INFINITY)) return;
-  const u64 m = (d.vis[(size_t)p * RW + k] >> sh) & 0xffull;
-  if (!m) return;
-  // the candidates' costs and coordinates, all requested before any is used
-  const int u0 = k * 64 + sh;
-  double cu[8];
-  int4 pu[8];
-#pragma unroll
-  for (int j = 0; j < 8; ++j) {
-    cu[j] = INFINITY;
-    if ((m >> j) & 1ull) {
-      cu[j] = __longlong_as_double((long long)d.costpos[u0 + j]);
-      pu[j] = d.gxy[u0 + j];
-    }
-  }
-  const int4 pv = d.gxy[p];
   int best = 0x7fffffff;
+  if (p >= nsrc && c < INFINITY) {
+    const int4 pv = d.gxy[p];
+    for (int k0 = 0; k0 < RW; k0 += 4) {
+      double cu[4];
+      int4 pu[4];
+      int gu[4];
 #pragma unroll
-  for (int j = 0; j < 8; ++j) {
-    if (!(cu[j] < c)) continue;
-    if (cu[j] + arc_lower(pu[j], pv.x, pv.y) > c) continue;
-    if (cu[j] + arc_len4(pu[j], pv.x, pv.y) == c) best = min(best, d.gorder[u0 + j]);
+      for (int q = 0; q < 4; ++q) {
+        const int k = k0 + q, u = 64 * k + lane;
+        cu[q] = INFINITY;
+        if (k < RW && u < G && ((d.vis[(size_t)p * RW + k] >> lane) & 1ull)) {
+          cu[q] = __longlong_as_double((long long)d.costpos[u]);
+          pu[q] = d.gxy[u];
+          gu[q] = d.gorder[u];
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        if (!(cu[q] < c)) continue;
+        if (cu[q] + arc_lower(pu[q], pv.x, pv.y) > c) continue;
+        if (cu[q] + arc_len4(pu[q], pv.x, pv.y) == c) best = min(best, gu[q]);
+      }
+    }
+    best = wave_min_i(best);
   }
-  if (best != 0x7fffffff) atomicMin(&d.parcan[d.gorder[p]], best);
+  if (lane == 0) d.gen_parent[g] = p < nsrc ? g : ((c < INFINITY && best != 0x7fffffff) ? best : -1);
 }
 
 template <class S, bool LDS, bool VLDS>
@@ -532,7 +538,7 @@ __global__ __launch_bounds__(1024) void k_relax(S src, int Gcap, int RWcap) {
     for (int k = tid; k < RW; k += nt) nxt[k] = 0;
     __syncthreads();
   }
-  // outputs by canonical id; parents follow in k_relax_parents
+  // outputs by canonical id; parents follow in k_gsort_parents
   int mine = 0;
   for (int p = tid; p < G; p += nt) {
     const double c = __longlong_as_double((long long)cost[p]);
@@ -540,7 +546,6 @@ __global__ __launch_bounds__(1024) void k_relax(S src, int Gcap, int RWcap) {
     if (LDS) d.costpos[p] = cost[p];
     d.gen_cost[v] = c;
     d.cost64[v] = c;
-    d.parcan[v] = 0x7fffffff;
     if (c < INFINITY) ++mine;
   }
   atomicAdd(&reached, mine);
@@ -554,16 +559,15 @@ __global__ __launch_bounds__(1024) void k_relax(S src, int Gcap, int RWcap) {
 // One wavefront per generator: rank by (float cost, id) among all generators;
 // unreached ones (+inf) rank last and are not copied.
 template <class S>
-__global__ __launch_bounds__(256) void k_gsort(S src) {
+__device__ __forceinline__ void gsort_wave(const S& src, int wid) {
   int sc, g;
-  if (!src.locate(STG_GEN, blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6), sc, g)) return;
+  if (!src.locate(STG_GEN, wid, sc, g)) return;
   const Dev& d = src.scene(sc);
   const int G = uni(d.misc[MISC_G]);
   if (g >= G) return;
   const int lane = lane_id();
-  // requested up front: this generator's record and parent (written after the rank)
+  // requested up front: this generator's record (written after the rank)
   GenRec r = d.gens[g];
-  const int pc = d.parcan[g];
   const float cf = (float)d.cost64[g];
   const u64 key = ((u64)__float_as_uint(cf) << 32) | (u64)(unsigned)g;
   int rank = 0;
@@ -581,16 +585,20 @@ __global__ __launch_bounds__(256) void k_gsort(S src) {
       rank += __popcll(ballot(h < G && (((u64)__float_as_uint(ch[q]) << 32) | (u64)(unsigned)h) < key));
     }
   }
-  if (lane == 0) {
-    // the parent found by k_relax_parents; sources are their own parents
-    d.gen_parent[g] = g < d.np + d.ns ? g : ((cf < INFINITY && pc != 0x7fffffff) ? pc : -1);
-  }
   if (lane == 0 && cf < INFINITY) {
     r.costf = cf;
     d.sgen[rank] = r;
     d.sgcost[rank] = cf;
     d.sgbb[rank] = make_int4(min(r.x, r.x2), min(r.y, r.y2), max(r.x, r.x2), max(r.y, r.y2));
   }
+}
+
+// The generator sort and the parents in one launch: the first nsort
+// workgroups rank generators, the others find parents (four wavefronts each).
+template <class S>
+__global__ __launch_bounds__(256) void k_gsort_parents(S src, int nsort) {
+  if ((int)blockIdx.x < nsort) gsort_wave(src, blockIdx.x * 4 + (threadIdx.x >> 6));
+  else parent_wave(src, (blockIdx.x - nsort) * 4 + (threadIdx.x >> 6));
 }
 
 static int max_lds_per_block() {
@@ -646,14 +654,14 @@ hipError_t launch_relax(const S& src, const Plan& p, hipStream_t s) {
   } else {
     hipLaunchKernelGGL((k_relax<S, false, false>), grid, dim3(kRelaxThreads), chg, s, src, Gcap, RWcap);
   }
-  if (nw > 0) hipLaunchKernelGGL(k_relax_parents<S>, dim3(wblocks), dim3(256), 0, s, src);
   return hipGetLastError();
 }
 
 template <class S>
 hipError_t launch_gsort(const S& src, const Plan& p, hipStream_t s) {
   if (p.total[STG_GEN] <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_gsort<S>, dim3((unsigned)((p.total[STG_GEN] + 3) / 4)), dim3(256), 0, s, src);
+  const unsigned nb = (unsigned)((p.total[STG_GEN] + 3) / 4);
+  hipLaunchKernelGGL(k_gsort_parents<S>, dim3(2 * nb), dim3(256), 0, s, src, (int)nb);
   return hipGetLastError();
 }
 

@@ -321,7 +321,6 @@ void fill_dev(Dev& d, const spm_scene* s, const spm_out* out, char* ws, const La
   d.vtx2gid = (int*)(ws + L.off_vtx2gid);
   d.gorder = (int*)(ws + L.off_gorder);
   d.costpos = (u64*)(ws + L.off_costpos);
-  d.parcan = (int*)(ws + L.off_parpos);
   d.rmask = (u64*)(ws + L.off_rmask);
   d.qctr = (int*)(ws + L.off_qctr);
   d.obins = (int*)(ws + L.off_obins);

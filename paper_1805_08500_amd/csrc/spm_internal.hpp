@@ -81,7 +81,7 @@ struct Layout {
   int E, NC, Gmax, RW, W32;
   size_t off_edges_raw, off_ext_raw, off_keys, off_edges, off_ext, off_chunks, off_convex;
   size_t off_gens, off_vis, off_sgen, off_sgcost, off_sgbb, off_inside, off_cost64, off_gxy, off_misc;
-  size_t off_vsorted, off_vtx2gid, off_gorder, off_costpos, off_parpos, off_qctr, off_rmask;
+  size_t off_vsorted, off_vtx2gid, off_gorder, off_costpos, off_qctr, off_rmask;
   size_t off_obins, off_order;
   int ocap;   // capacity of each work class (the most tiles any tile shape gives)
   size_t total;
@@ -121,7 +121,6 @@ inline Layout make_layout(int W, int H, int n_polys, int nv, int np, int ns) {
   L.off_vtx2gid = take(E1 * sizeof(int));
   L.off_gorder = take(G1 * sizeof(int));
   L.off_costpos = take(G1 * sizeof(u64));
-  L.off_parpos = take(G1 * sizeof(int));
   L.off_qctr = take(kQueues * kQueueStride * sizeof(int));
   L.off_rmask = take(3 * (size_t)(L.RW > 0 ? L.RW : 1) * sizeof(u64));
   L.ocap = tiles_of(W, H, 4);
@@ -164,7 +163,6 @@ struct Dev {
   int* vtx2gid;   // generator id of each convex vertex
   int* gorder;    // generator id at each spatial position (sources first)
   u64* costpos;   // relaxation costs by spatial position (IEEE bits) when they do not fit in LDS
-  int* parcan;    // relaxation parents by canonical id (smallest id attaining the cost)
   u64* rmask;     // wide relaxation rounds: three rotating change masks of RW words
   int* qctr;      // pixel-stage queue counters, kQueues of them kQueueStride ints apart
   int* obins;     // pixel-stage work classes: item count of each (kOrderBins)
