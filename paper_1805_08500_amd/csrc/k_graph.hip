@@ -369,6 +369,51 @@ __global__ __launch_bounds__(256) void k_relax_wide(S src, int round) {
   }
 }
 
+// The first rounds without a barrier between them: one thread per (corner row
+// v, byte of word k) relaxes its (up to eight) arcs iters times, reading the
+// current costs each time (coherent loads) and merging by an atomic minimum;
+// every vertex it lowers is marked in change mask 1.  Costs only fall and every
+// arc is relaxed at least once from its source's value at the time, so
+// afterwards an arc (u, v) can still lower v only if u was lowered during the
+// launch, i.e. u is marked: a chip-wide round from mask 1 (round 1 of
+// k_relax_wide) restores the exact change mask the one-workgroup kernel starts
+// from.  The arc weights are computed once.
+template <class S>
+__global__ __launch_bounds__(256) void k_relax_chaos(S src, int iters) {
+  int sc, it;
+  if (!src.locate(STG_RELAXW, blockIdx.x * blockDim.x + threadIdx.x, sc, it)) return;
+  const Dev& d = src.scene(sc);
+  const int RW = d.RW, nsrc = d.np + d.ns;
+  const int vk = it >> 3, sh = (it & 7) * 8;
+  const int v = nsrc + vk / RW, k = vk - (vk / RW) * RW;
+  if (v >= d.misc[MISC_G]) return;
+  const u64 m = (d.vis[(size_t)v * RW + k] >> sh) & 0xffull;
+  if (!m) return;
+  u64* cost = d.costpos;
+  const int u0 = k * 64 + sh;
+  const int4 pv = d.gxy[v];
+  double w[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) w[j] = ((m >> j) & 1ull) ? arc_len4(d.gxy[u0 + j], pv.x, pv.y) : INFINITY;
+  for (int t = 0; t < iters; ++t) {
+    double cu[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j)
+      cu[j] = ((m >> j) & 1ull) ? __longlong_as_double((long long)__hip_atomic_load(
+                                      &cost[u0 + j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+                                : INFINITY;
+    const double old =
+        __longlong_as_double((long long)__hip_atomic_load(&cost[v], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+    double best = old;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) best = fmin(best, cu[j] + w[j]);
+    if (best < old) {
+      const u64 ob = atomicMin(&cost[v], (u64)__double_as_longlong(best));
+      if (__longlong_as_double((long long)ob) > best) atomicOr(&d.rmask[RW + (v >> 6)], 1ull << (v & 63));
+    }
+  }
+}
+
 // Parents, once the costs are final: one wavefront per spatial position p,
 // lanes over the 64 generators of each bit word of row p (four words per
 // step, all loads requested together): the smallest canonical id among the
@@ -415,7 +460,7 @@ __device__ __forceinline__ void parent_wave(const S& src, int wid) {
 }
 
 template <class S, bool LDS, bool VLDS>
-__global__ __launch_bounds__(1024) void k_relax(S src, int Gcap, int RWcap) {
+__global__ __launch_bounds__(1024) void k_relax(S src, int Gcap, int RWcap, int m0idx, int rounds0) {
   int sc, one;
   if (!src.locate(STG_SCENE, blockIdx.x, sc, one)) return;
   const Dev& d = src.scene(sc);
@@ -444,7 +489,7 @@ __global__ __launch_bounds__(1024) void k_relax(S src, int Gcap, int RWcap) {
     vis = s_vis;
   }
   // the change mask left by the wide rounds
-  const u64* m0 = d.rmask + (kRelaxWideRounds % 3) * RW;
+  const u64* m0 = d.rmask + m0idx * RW;
   for (int k = tid; k < RW; k += nt) { chg_a[k] = m0[k]; chg_b[k] = 0; }
   if (tid == 0) { reached = 0; nfront = -1; }
   __syncthreads();
@@ -552,7 +597,7 @@ __global__ __launch_bounds__(1024) void k_relax(S src, int Gcap, int RWcap) {
   __syncthreads();
   if (tid == 0) {
     d.misc[MISC_REACHED] = reached;
-    d.misc[MISC_ROUNDS] = kRelaxWideRounds + rounds;
+    d.misc[MISC_ROUNDS] = rounds0 + rounds;
   }
 }
 
@@ -629,9 +674,19 @@ template <class S>
 hipError_t launch_relax(const S& src, const Plan& p, hipStream_t s) {
   const long long nw = p.total[STG_RELAXW];
   const unsigned wblocks = (unsigned)((nw + 255) / 256);
-  if (nw > 0)
+  // the large early rounds chip-wide: without barriers then one exact round, or kRelaxWideRounds rounds
+  int m0idx = kRelaxWideRounds % 3, rounds0 = kRelaxWideRounds;
+  if (kRelaxChaos > 0) {
+    m0idx = 2;
+    rounds0 = kRelaxChaos + 1;
+    if (nw > 0) {
+      hipLaunchKernelGGL(k_relax_chaos<S>, dim3(wblocks), dim3(256), 0, s, src, kRelaxChaos);
+      hipLaunchKernelGGL(k_relax_wide<S>, dim3(wblocks), dim3(256), 0, s, src, 1);
+    }
+  } else if (nw > 0) {
     for (int r = 0; r < kRelaxWideRounds; ++r)
       hipLaunchKernelGGL(k_relax_wide<S>, dim3(wblocks), dim3(256), 0, s, src, r);
+  }
   const int RWcap = p.maxRW > 0 ? p.maxRW : 1;
   const int Gcap = p.maxGmax > 0 ? p.maxGmax : 1;
   const size_t chg = 2 * (size_t)RWcap * sizeof(u64);
@@ -647,12 +702,12 @@ hipError_t launch_relax(const S& src, const Plan& p, hipStream_t s) {
   hipError_t e = hipSuccess;
   if (shm_v + static_lds <= lim) {
     if ((e = big((const void*)k_relax<S, true, true>, shm_v)) != hipSuccess) return e;
-    hipLaunchKernelGGL((k_relax<S, true, true>), grid, dim3(kRelaxThreads), shm_v, s, src, Gcap, RWcap);
+    hipLaunchKernelGGL((k_relax<S, true, true>), grid, dim3(kRelaxThreads), shm_v, s, src, Gcap, RWcap, m0idx, rounds0);
   } else if (shm + static_lds <= lim) {
     if ((e = big((const void*)k_relax<S, true, false>, shm)) != hipSuccess) return e;
-    hipLaunchKernelGGL((k_relax<S, true, false>), grid, dim3(kRelaxThreads), shm, s, src, Gcap, RWcap);
+    hipLaunchKernelGGL((k_relax<S, true, false>), grid, dim3(kRelaxThreads), shm, s, src, Gcap, RWcap, m0idx, rounds0);
   } else {
-    hipLaunchKernelGGL((k_relax<S, false, false>), grid, dim3(kRelaxThreads), chg, s, src, Gcap, RWcap);
+    hipLaunchKernelGGL((k_relax<S, false, false>), grid, dim3(kRelaxThreads), chg, s, src, Gcap, RWcap, m0idx, rounds0);
   }
   return hipGetLastError();
 }

@@ -26,6 +26,10 @@ constexpr int kRelaxThreads = 1024;
 #define SPM_RELAX_WIDE 6
 #endif
 constexpr int kRelaxWideRounds = SPM_RELAX_WIDE;   // Bellman-Ford rounds run chip-wide before the one-workgroup rounds
+#ifndef SPM_RELAX_CHAOS
+#define SPM_RELAX_CHAOS 16
+#endif
+constexpr int kRelaxChaos = SPM_RELAX_CHAOS;   // > 0: instead, that many rounds in one launch without barriers
 constexpr int kDefaultStrip = 1;      // tiles per pixel-stage work item
 constexpr int kDefaultSamples = 3;    // seed searches per pixel tile
 constexpr int kMaxStrip = 64;
