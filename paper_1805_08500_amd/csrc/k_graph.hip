@@ -19,6 +19,8 @@
 //              cost.
 #include <math.h>
 
+#include <type_traits>
+
 #include "spm_internal.hpp"
 
 namespace spm {
@@ -639,11 +641,32 @@ __device__ __forceinline__ void gsort_wave(const S& src, int wid) {
 }
 
 // The generator sort and the parents in one launch: the first nsort
-// workgroups rank generators, the others find parents (four wavefronts each).
+// workgroups rank generators, the next nsort find parents (four wavefronts
+// each); for a single scene, norder more build the pixel stage's work order
+// (tile_order_group) from the canonical costs and coordinates, staged in LDS.
 template <class S>
-__global__ __launch_bounds__(256) void k_gsort_parents(S src, int nsort) {
-  if ((int)blockIdx.x < nsort) gsort_wave(src, blockIdx.x * 4 + (threadIdx.x >> 6));
-  else parent_wave(src, (blockIdx.x - nsort) * 4 + (threadIdx.x >> 6));
+__global__ __launch_bounds__(256) void k_gsort_parents(S src, int nsort, int norder) {
+  const int b = blockIdx.x;
+  if (b < nsort) {
+    gsort_wave(src, b * 4 + (threadIdx.x >> 6));
+  } else if (b < 2 * nsort) {
+    parent_wave(src, (b - nsort) * 4 + (threadIdx.x >> 6));
+  } else if (b < 2 * nsort + norder) {
+    extern __shared__ int4 gsm[];
+    __shared__ int lcount[kOrderBins], lbase[kOrderBins], icls[kOrderGroup], islot[kOrderGroup];
+    const Dev& d = src.scene(0);
+    const int G = d.misc[MISC_G];
+    int4* bb = gsm;
+    float* cost = (float*)(gsm + d.Gmax);
+    for (int g = threadIdx.x; g < G; g += blockDim.x) {
+      const GenRec& r = d.gens[g];
+      bb[g] = make_int4(min(r.x, r.x2), min(r.y, r.y2), max(r.x, r.x2), max(r.y, r.y2));
+      cost[g] = (float)d.cost64[g];
+    }
+    if (threadIdx.x < kOrderBins) lcount[threadIdx.x] = 0;
+    __syncthreads();
+    tile_order_group(d, b - 2 * nsort, G, bb, cost, lcount, lbase, icls, islot);
+  }
 }
 
 static int max_lds_per_block() {
@@ -716,7 +739,15 @@ template <class S>
 hipError_t launch_gsort(const S& src, const Plan& p, hipStream_t s) {
   if (p.total[STG_GEN] <= 0) return hipSuccess;
   const unsigned nb = (unsigned)((p.total[STG_GEN] + 3) / 4);
-  hipLaunchKernelGGL(k_gsort_parents<S>, dim3(2 * nb), dim3(256), 0, s, src, (int)nb);
+  unsigned norder = 0;
+  size_t shm = 0;
+  if constexpr (std::is_same<S, SingleSrc>::value) {
+    if (order_fused(src.d)) {
+      norder = (unsigned)((order_items(src.d) + kOrderGroup - 1) / kOrderGroup);
+      shm = (size_t)src.d.Gmax * (sizeof(int4) + sizeof(float));
+    }
+  }
+  hipLaunchKernelGGL(k_gsort_parents<S>, dim3(2 * nb + norder), dim3(256), shm, s, src, (int)nb, (int)norder);
   return hipGetLastError();
 }
 

@@ -782,7 +782,10 @@ size_t pixel_lds_bytes(int Gmax, int E, int NC) {
 // workgroup takes kOrderItems items and appends them to their classes with
 // one atomic per class.
 constexpr int kOrderThreads = 512;
-constexpr int kOrderItems = 64;
+#ifndef SPM_ORDER_ITEMS
+#define SPM_ORDER_ITEMS 64
+#endif
+constexpr int kOrderItems = SPM_ORDER_ITEMS;   // work items per workgroup of k_tile_order
 constexpr size_t kOrderLdsMax = 48 * 1024;
 
 template <int TW, bool LDS>
@@ -973,7 +976,9 @@ static hipError_t launch_variant(const Dev& d, hipStream_t s, size_t shm) {
   if (blocks < 1) blocks = 1;
   // the work order matters only when some items wait for a free wavefront
   const int* order = nullptr;
-  if (SPM_TILE_ORDER && waves_needed > blocks * (kPixelThreads / 64)) {
+  if (SPM_TILE_ORDER && waves_needed > blocks * (kPixelThreads / 64) && order_fused(d)) {
+    order = d.order;   // built in the generator sort's launch
+  } else if (SPM_TILE_ORDER && waves_needed > blocks * (kPixelThreads / 64)) {
     const dim3 og((unsigned)((waves_needed + kOrderItems - 1) / kOrderItems));
     const size_t osh = (size_t)d.Gmax * (sizeof(int4) + sizeof(float));
     if (osh <= kOrderLdsMax)

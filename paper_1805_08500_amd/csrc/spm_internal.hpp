@@ -286,6 +286,7 @@ struct Plan {
 // host launchers (each queues kernels on the stream and returns hipError_t)
 template <class S> hipError_t launch_ingest(const S& src, const Plan& p, hipStream_t s);
 template <class S> hipError_t launch_edge_sort(const S& src, const Plan& p, hipStream_t s);
+
 template <class S> hipError_t launch_gorder(const S& src, const Plan& p, hipStream_t s);
 template <class S> hipError_t launch_genvis(const S& src, const Plan& p, hipStream_t s);
 template <class S> hipError_t launch_relax(const S& src, const Plan& p, hipStream_t s);
@@ -785,5 +786,67 @@ __device__ __forceinline__ u64 wave_blocked_perp(const Geo& d, int px, int py, u
   return blocked;
 }
 #endif  // __HIPCC__
+
+// Work order of the pixel stage (the order itself is described with k_pixel):
+// item classes by lb = min_g cost(g) + |c - box(g)| at the item centre c.
+// One call handles kOrderGroup items with a 256-thread workgroup (eight per
+// wavefront): bb and cost hold the G generators' boxes and float costs (any
+// order; +inf for unreached ones).  Each class count is raised with one
+// atomic per workgroup and the items go to order[class * ocap + slot].
+constexpr int kOrderGroup = 32;
+constexpr size_t kOrderFuseLds = 48 * 1024;
+inline int order_items(const Dev& d) {
+  const int tw = d.tile_w, th = 64 / tw;
+  const int ntx = (d.W + tw - 1) / tw, nty = (d.H + th - 1) / th;
+  return (ntx + d.strip - 1) / d.strip * nty;
+}
+// The order comes from the generator sort's launch when its tables fit in LDS
+// there and the scene has more items than a launch of the pixel stage keeps
+// resident at 4 waves per SIMD (below that every item starts at once); the
+// pixel launch asks the same question, so the two always agree.
+constexpr int kOrderMinItems = 256 * 16;
+inline bool order_fused(const Dev& d) {
+  return (size_t)d.Gmax * (sizeof(int4) + sizeof(float)) <= kOrderFuseLds && order_items(d) > kOrderMinItems;
+}
+__device__ __forceinline__ void tile_order_group(const Dev& d, int grp, int G, const int4* bb, const float* cost,
+                                                 int* lcount, int* lbase, int* icls, int* islot) {
+  const int tid = threadIdx.x, lane = lane_id(), wv = tid / 64;
+  const int TW = d.tile_w, TH = 64 / TW;
+  const int ntx = (d.W + TW - 1) / TW, nty = (d.H + TH - 1) / TH;
+  const int spr = (ntx + d.strip - 1) / d.strip;
+  const int nitems = spr * nty;
+  const float scale = (float)(2 * kOrderBins) / (float)(d.W + d.H);
+  constexpr int kPer = kOrderGroup / 4;
+  for (int k = 0; k < kPer; ++k) {
+    const int li = wv * kPer + k;
+    const int item = grp * kOrderGroup + li;
+    if (item >= nitems) break;
+    const int ty = item / spr, sx = item - ty * spr;
+    const int t0 = sx * d.strip, t1 = min(t0 + d.strip, ntx);
+    const int cx = (t0 + t1) * TW, cy = (2 * ty + 1) * TH;   // item centre, doubled coordinates
+    float lb = INFINITY;
+    for (int h = lane; h < G; h += 64) {
+      const int4 b = bb[h];
+      const float dx = (float)max(max(b.x - cx, cx - b.z), 0), dy = (float)max(max(b.y - cy, cy - b.w), 0);
+      lb = fminf(lb, cost[h] + 0.5f * __builtin_amdgcn_sqrtf(dx * dx + dy * dy));
+    }
+    // lb >= 0, so its bits order as unsigned
+    const float f = __uint_as_float(wave_min_u32(__float_as_uint(lb))) * scale;
+    const int c = f < (float)(kOrderBins - 1) ? (int)f : kOrderBins - 1;
+    if (lane == 0) {
+      const int cls = kOrderBins - 1 - c;
+      icls[li] = cls;
+      islot[li] = atomicAdd(&lcount[cls], 1);
+    }
+  }
+  __syncthreads();
+  if (tid < kOrderBins) lbase[tid] = lcount[tid] ? atomicAdd(&d.obins[tid], lcount[tid]) : 0;
+  __syncthreads();
+  if (tid < kOrderGroup) {
+    const int item = grp * kOrderGroup + tid;
+    if (item < nitems) d.order[(size_t)icls[tid] * d.ocap + lbase[icls[tid]] + islot[tid]] = item;
+  }
+}
+
 
 }  // namespace spm
