@@ -129,7 +129,13 @@ int spm_timer_elapsed(spm_timer* t, float* ms /* [SPM_N_STAGES] */, int32_t* n_b
  * samples is the number of seed searches a tile runs, each from one of its
  * pixels that still has no value: candidates in order of cost + distance,
  * checked with a cheap visibility test, until one is seen (0 = the default,
- * -1 = none).  strip and samples change speed only, never an output bit.
+ * -1 = none).  walk selects how a tile goes through the generators: 0 = by
+ * the scene's largest possible generator count G (np + ns + nv); 1 = in order
+ * of a lower bound over the tile, every estimate in registers (G <= 512);
+ * 2 = the same with the least estimates cached and refilled (G <= 4096);
+ * 3 = seed searches, then (cost, id) order.  A forced walk that does not fit
+ * G fails with SPM_ERR_INVALID_ARG.  strip, samples and walk change speed
+ * only, never an output bit.
  * d_stats, when not NULL, selects the instrumented pixel kernel, which adds
  * its work counters (unsigned 64-bit: [0] tiles, [1] batches of 64
  * lane-parallel generator bound or seed-search tests, [2] lane bound tests,
@@ -142,6 +148,7 @@ typedef struct {
   uint64_t* d_stats;
   int32_t strip;
   int32_t samples;
+  int32_t walk;
 } spm_build_opts;
 int spm_build_ex(const spm_scene* dev_scene, const spm_out* out, void* d_ws, size_t ws_bytes, void* stream,
                  const spm_build_opts* opts);

@@ -41,7 +41,7 @@ class SpmOut(ctypes.Structure):
 
 class SpmBuildOpts(ctypes.Structure):
     _fields_ = [("tile_w", c_i32), ("tile_h", c_i32), ("timer", c_vp), ("d_stats", c_vp), ("strip", c_i32),
-                ("samples", c_i32)]
+                ("samples", c_i32), ("walk", c_i32)]
 
 
 class SpmBatch(ctypes.Structure):

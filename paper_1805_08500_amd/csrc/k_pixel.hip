@@ -1006,7 +1006,7 @@ static hipError_t launch_tw_walk(const Dev& d, hipStream_t s) {
 
 template <int TW>
 static hipError_t launch_tw(const Dev& d, hipStream_t s) {
-  switch (walk_mode(d.Gmax)) {
+  switch (d.walk > 0 ? d.walk - 1 : walk_mode(d.Gmax)) {
     case kWalkCached: return launch_tw_walk<TW, kWalkCached>(d, s);
     case kWalkRefill: return launch_tw_walk<TW, kWalkRefill>(d, s);
     default: return launch_tw_walk<TW, kWalkCost>(d, s);

@@ -331,6 +331,7 @@ void fill_dev(Dev& d, const spm_scene* s, const spm_out* out, char* ws, const La
   d.tile_w = tw; d.tile_h = 64 / tw;
   d.strip = kDefaultStrip;
   d.samples = kDefaultSamples;
+  d.walk = 0;
   // generator visibility: the narrowest wavefronts (smallest culling boxes) that keep the launch
   // within about two rounds of resident wavefronts
   d.gv_sub = 64;
@@ -467,10 +468,16 @@ int spm_build_ex(const spm_scene* s, const spm_out* out, void* d_ws, size_t ws_b
     return fail(SPM_ERR_INVALID_ARG, "strip %d outside 0..%d", opts->strip, kMaxStrip);
   if (opts && opts->samples < -1)
     return fail(SPM_ERR_INVALID_ARG, "samples %d below -1", opts->samples);
+  if (opts && (opts->walk < 0 || opts->walk > 3))
+    return fail(SPM_ERR_INVALID_ARG, "walk %d outside 0..3", opts->walk);
+  if (opts && ((opts->walk == 1 && L.Gmax > 512) || (opts->walk == 2 && L.Gmax > 4096)))
+    return fail(SPM_ERR_INVALID_ARG, "walk %d needs at most %d generators (scene has up to %d)", opts->walk,
+                opts->walk == 1 ? 512 : 4096, L.Gmax);
   SingleSrc src;
   fill_dev(src.d, s, out, (char*)d_ws, L, tw, opts ? (u64*)opts->d_stats : nullptr);
   if (opts && opts->strip) src.d.strip = opts->strip;
   if (opts && opts->samples) src.d.samples = opts->samples < 0 ? 0 : opts->samples;
+  if (opts) src.d.walk = opts->walk;
   Plan p{};
   plan_add(p, src.d);
   hipStream_t st = (hipStream_t)stream;

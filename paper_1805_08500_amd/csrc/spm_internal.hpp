@@ -184,6 +184,7 @@ struct Dev {
   int tile_w, tile_h;
   int strip;       // pixel stage: tiles per wavefront work item (>= 1)
   int samples;     // pixel stage: seed searches per tile (>= 0)
+  int walk;        // pixel stage: 0 by generator count, else 1 + the walk (cached, refilled, cost order)
   int gv_sub;      // generator visibility: columns per wavefront (64, 32 or 16); 0: one pair at a time,
                    // lanes over edges (kGvPairRows x kGvPairRows blocks of the lower triangle)
   u64* stats;

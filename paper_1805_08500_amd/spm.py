@@ -117,10 +117,12 @@ class Builder:
     """Owns the outputs and workspace of one scene's builds.
 
     tile: pixel tile of one wavefront; strip: tiles per work item (0 = library
-    default); samples: seed searches per tile (0 = default, -1 = none).
-    strip and samples change speed only."""
+    default); samples: seed searches per tile (0 = default, -1 = none); walk:
+    how tiles go through the generators (0 = by generator count, 1 = register
+    cache, 2 = refilled cache, 3 = seed searches and cost order).  strip,
+    samples and walk change speed only."""
 
-    def __init__(self, dscene: DeviceScene, tile=(8, 8), strip: int = 0, samples: int = 0):
+    def __init__(self, dscene: DeviceScene, tile=(8, 8), strip: int = 0, samples: int = 0, walk: int = 0):
         self.ds = dscene
         dev = dscene.t["vx"].device
         self.max_gen, self.ws_bytes = dscene.sizes
@@ -142,13 +144,15 @@ class Builder:
         self.tile = tuple(tile)
         self.strip = int(strip)
         self.samples = int(samples)
+        self.walk = int(walk)
 
     def build(self, stream=None, timer: Timer = None, stats: torch.Tensor = None) -> Map:
         """Queue one build on `stream` (default: torch's current stream)."""
         if stream is None:
             stream = torch.cuda.current_stream(self.ws.device)
         opts = C.SpmBuildOpts(self.tile[0], self.tile[1], timer.h if timer is not None else None,
-                              stats.data_ptr() if stats is not None else None, self.strip, self.samples)
+                              stats.data_ptr() if stats is not None else None, self.strip, self.samples,
+                              self.walk)
         C.check(C.lib().spm_build_ex(ctypes.byref(self.ds.c), ctypes.byref(self.out), self.ws.data_ptr(),
                                      self.ws_bytes, ctypes.c_void_p(stream.cuda_stream), ctypes.byref(opts)))
         return self.map

@@ -120,6 +120,23 @@ def test_build_rejects_null_arguments_before_device_work(C):
     assert rc == C.SPM_ERR_INVALID_ARG
 
 
+def test_build_rejects_bad_walk_before_device_work(C):
+    """The walk option is checked on the host, before any device pointer is touched."""
+    L = C.lib()
+    n = 600   # point sources: up to 600 generators
+    pts = (ctypes.c_int32 * (2 * n))(*([1, 1] * n))
+    s = C.SpmScene(10, 10, 0, 0, n, 0, None, None, None, None, None)
+    s.pts = ctypes.cast(pts, ctypes.c_void_p)
+    fake = 4096   # never dereferenced: every check below fails first
+    out = C.SpmOut(fake, fake, fake, fake, fake, fake, fake)
+    for walk, what in [(7, b"outside"), (-1, b"outside"), (1, b"at most 512")]:
+        opts = C.SpmBuildOpts(0, 0, None, None, 0, 0, walk)
+        rc = L.spm_build_ex(ctypes.byref(s), ctypes.byref(out), ctypes.c_void_p(fake), ctypes.c_size_t(1 << 40), None,
+                            ctypes.byref(opts))
+        assert rc == C.SPM_ERR_INVALID_ARG, walk
+        assert what in L.spm_last_error(), L.spm_last_error()
+
+
 def _oracle_host_map(O, scene):
     m = O.full_map(scene)
     kind, ref, xy = O.generators(scene)

@@ -111,6 +111,26 @@ def test_tile_shapes_bitwise(spm, tile):
     assert np.array_equal(a["dist"], b["dist"]) and np.array_equal(a["parent"], b["parent"])
 
 
+@pytest.mark.parametrize("make,walks", [(lambda: config2(1), (1, 2, 3)), (lambda: profiling_grid(20, seed=2), (2, 3)),
+                                        (lambda: random_small(5), (1, 2, 3))])
+def test_walk_modes_bitwise(spm, make, walks):
+    """Every walk of the pixel stage gives the same map bit for bit (the (value, position) order decides)."""
+    import torch
+    scene = make()
+    ds = spm.DeviceScene(scene)
+    ref = None
+    for w in (0,) + tuple(walks):
+        b = spm.Builder(ds, walk=w)
+        b.build()
+        torch.cuda.synchronize()
+        h = b.map.host()
+        _say(f"[parity] walk {w} {scene.width}x{scene.height} G={h['n_gen']}")
+        if ref is None:
+            ref = h
+        else:
+            assert np.array_equal(ref["dist"], h["dist"]) and np.array_equal(ref["parent"], h["parent"]), f"walk {w}"
+
+
 def test_deterministic(spm):
     scene = config2(2)
     a = _gpu(spm, scene)
