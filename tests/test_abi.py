@@ -22,8 +22,8 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 def C():
     from paper_1805_08500_amd import _lib
     if not os.path.exists(_lib.LIB_PATH):
-        from paper_1805_08500_amd import build
-        build.build()
+        import importlib
+        importlib.import_module("paper_1805_08500_amd.build").build()
     _lib.lib()
     return _lib
 
