@@ -66,10 +66,12 @@ __device__ __forceinline__ double arc_len(const GenRec& u, int vx, int vy) {
 // whole workgroups).
 // The relaxation's starting state, by spatial position (entry wid * 64 + lane
 // of it; the point-column wavefronts cover all of it): sources at cost 0 and
-// marked changed, everything else at +inf; generator coordinates.
+// marked changed, everything else at +inf; generator coordinates; the
+// barrier-free rounds' progress mark at 0.
 __device__ __forceinline__ void relax_init(const Dev& d, int wid, int G, int nsrc) {
   const int RW = d.RW;
   const int t = wid * 64 + lane_id();
+  if (t < kChaosSlots) d.cmark[t * kQueueStride] = 0;
   if (t < G) {
     const GenRec gt = d.gens[d.gorder[t]];
     d.costpos[t] = (u64)__double_as_longlong(t < nsrc ? 0.0 : INFINITY);
@@ -372,15 +374,21 @@ __global__ __launch_bounds__(256) void k_relax_wide(S src, int round) {
 }
 
 // The first rounds without a barrier between them: one thread per (corner row
-// v, byte of word k) relaxes its (up to eight) arcs iters times, reading the
-// current costs each time (coherent loads) and merging by an atomic minimum;
-// every vertex it lowers is marked in change mask 1.  Costs only fall and every
-// arc is relaxed at least once from its source's value at the time, so
-// afterwards an arc (u, v) can still lower v only if u was lowered during the
-// launch, i.e. u is marked: a chip-wide round from mask 1 (round 1 of
+// v, byte of word k) relaxes its (up to eight) arcs up to iters times, reading
+// the current costs each time (coherent loads) and merging by an atomic
+// minimum; every vertex it lowers is marked in change mask 1.  Costs only fall
+// and every arc is relaxed at least once from its source's value at the time,
+// so afterwards an arc (u, v) can still lower v only if u was lowered during
+// the launch, i.e. u is marked: a chip-wide round from mask 1 (round 1 of
 // k_relax_wide) restores the exact change mask the one-workgroup kernel starts
-// from.  The arc weights are computed once.
-template <class S>
+// from.  That holds whenever a thread stops, so stopping is a matter of speed
+// alone.  ADAPT (large graphs, whose shortest paths take many arcs): a
+// wavefront that lowers a cost in its pass t raises its workgroup's progress
+// mark (one of kChaosSlots, spread over cache lines) to t + 1, and every
+// wavefront stops once the largest mark shows kChaosQuiet passes in a row
+// without a lowering; otherwise all iters passes run, with no mark traffic.
+// The arc weights are computed once.
+template <class S, bool ADAPT>
 __global__ __launch_bounds__(256) void k_relax_chaos(S src, int iters) {
   int sc, it;
   if (!src.locate(STG_RELAXW, blockIdx.x * blockDim.x + threadIdx.x, sc, it)) return;
@@ -398,6 +406,12 @@ __global__ __launch_bounds__(256) void k_relax_chaos(S src, int iters) {
 #pragma unroll
   for (int j = 0; j < 8; ++j) w[j] = ((m >> j) & 1ull) ? arc_len4(d.gxy[u0 + j], pv.x, pv.y) : INFINITY;
   for (int t = 0; t < iters; ++t) {
+    int seen = 0;
+    if (ADAPT) {
+#pragma unroll
+      for (int q = 0; q < kChaosSlots; ++q)
+        seen = max(seen, __hip_atomic_load(d.cmark + q * kQueueStride, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+    }
     double cu[8];
 #pragma unroll
     for (int j = 0; j < 8; ++j)
@@ -406,12 +420,23 @@ __global__ __launch_bounds__(256) void k_relax_chaos(S src, int iters) {
                                 : INFINITY;
     const double old =
         __longlong_as_double((long long)__hip_atomic_load(&cost[v], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+    // no lowering seen in the last kChaosQuiet passes (the mark is wave-uniform once read by lane 0)
+    if (ADAPT && t >= kChaosQuiet && __builtin_amdgcn_readfirstlane(seen) <= t - kChaosQuiet) break;
     double best = old;
 #pragma unroll
     for (int j = 0; j < 8; ++j) best = fmin(best, cu[j] + w[j]);
+    bool lowered = false;
     if (best < old) {
       const u64 ob = atomicMin(&cost[v], (u64)__double_as_longlong(best));
-      if (__longlong_as_double((long long)ob) > best) atomicOr(&d.rmask[RW + (v >> 6)], 1ull << (v & 63));
+      if (__longlong_as_double((long long)ob) > best) {
+        atomicOr(&d.rmask[RW + (v >> 6)], 1ull << (v & 63));
+        lowered = true;
+      }
+    }
+    if (ADAPT) {
+      const u64 any = ballot(lowered);
+      if (any && lane_id() == (int)__builtin_ctzll(any) && __builtin_amdgcn_readfirstlane(seen) <= t)
+        atomicMax(d.cmark + (blockIdx.x % kChaosSlots) * kQueueStride, t + 1);
     }
   }
 }
@@ -700,10 +725,14 @@ hipError_t launch_relax(const S& src, const Plan& p, hipStream_t s) {
   // the large early rounds chip-wide: without barriers then one exact round, or kRelaxWideRounds rounds
   int m0idx = kRelaxWideRounds % 3, rounds0 = kRelaxWideRounds;
   if (kRelaxChaos > 0) {
+    const bool adapt = p.maxGmax > kChaosAdaptMinGen;
     m0idx = 2;
-    rounds0 = kRelaxChaos + 1;
+    rounds0 = (adapt ? kRelaxChaosMax : kRelaxChaos) + 1;
     if (nw > 0) {
-      hipLaunchKernelGGL(k_relax_chaos<S>, dim3(wblocks), dim3(256), 0, s, src, kRelaxChaos);
+      if (adapt)
+        hipLaunchKernelGGL((k_relax_chaos<S, true>), dim3(wblocks), dim3(256), 0, s, src, kRelaxChaosMax);
+      else
+        hipLaunchKernelGGL((k_relax_chaos<S, false>), dim3(wblocks), dim3(256), 0, s, src, kRelaxChaos);
       hipLaunchKernelGGL(k_relax_wide<S>, dim3(wblocks), dim3(256), 0, s, src, 1);
     }
   } else if (nw > 0) {

@@ -323,6 +323,7 @@ void fill_dev(Dev& d, const spm_scene* s, const spm_out* out, char* ws, const La
   d.costpos = (u64*)(ws + L.off_costpos);
   d.rmask = (u64*)(ws + L.off_rmask);
   d.qctr = (int*)(ws + L.off_qctr);
+  d.cmark = (int*)(ws + L.off_cmark);
   d.obins = (int*)(ws + L.off_obins);
   d.order = (int*)(ws + L.off_order);
   d.ocap = L.ocap;

@@ -29,7 +29,20 @@ constexpr int kRelaxWideRounds = SPM_RELAX_WIDE;   // Bellman-Ford rounds run ch
 #ifndef SPM_RELAX_CHAOS
 #define SPM_RELAX_CHAOS 16
 #endif
-constexpr int kRelaxChaos = SPM_RELAX_CHAOS;   // > 0: instead, that many rounds in one launch without barriers
+constexpr int kRelaxChaos = SPM_RELAX_CHAOS;   // > 0: instead, that many rounds in one launch without barriers (small graphs)
+#ifndef SPM_CHAOS_QUIET
+#define SPM_CHAOS_QUIET 3
+#endif
+constexpr int kChaosQuiet = SPM_CHAOS_QUIET;   // the barrier-free rounds stop after that many passes without a lowering
+#ifndef SPM_RELAX_CHAOS_MAX
+#define SPM_RELAX_CHAOS_MAX 64
+#endif
+constexpr int kRelaxChaosMax = SPM_RELAX_CHAOS_MAX;   // their cap when they stop by themselves
+#ifndef SPM_CHAOS_ADAPT_MIN_GEN
+#define SPM_CHAOS_ADAPT_MIN_GEN 1024
+#endif
+constexpr int kChaosAdaptMinGen = SPM_CHAOS_ADAPT_MIN_GEN;   // above that many generators they do
+constexpr int kChaosSlots = 8;     // progress marks, spread over cache lines to keep atomics apart
 constexpr int kDefaultStrip = 1;      // tiles per pixel-stage work item
 constexpr int kDefaultSamples = 3;    // seed searches per pixel tile
 constexpr int kMaxStrip = 64;
@@ -85,7 +98,7 @@ struct Layout {
   int E, NC, Gmax, RW, W32;
   size_t off_edges_raw, off_ext_raw, off_keys, off_edges, off_ext, off_chunks, off_convex;
   size_t off_gens, off_vis, off_sgen, off_sgcost, off_sgbb, off_inside, off_cost64, off_gxy, off_misc;
-  size_t off_vsorted, off_vtx2gid, off_gorder, off_costpos, off_qctr, off_rmask;
+  size_t off_vsorted, off_vtx2gid, off_gorder, off_costpos, off_qctr, off_rmask, off_cmark;
   size_t off_obins, off_order;
   int ocap;   // capacity of each work class (the most tiles any tile shape gives)
   size_t total;
@@ -126,6 +139,7 @@ inline Layout make_layout(int W, int H, int n_polys, int nv, int np, int ns) {
   L.off_gorder = take(G1 * sizeof(int));
   L.off_costpos = take(G1 * sizeof(u64));
   L.off_qctr = take(kQueues * kQueueStride * sizeof(int));
+  L.off_cmark = take(kChaosSlots * kQueueStride * sizeof(int));
   L.off_rmask = take(3 * (size_t)(L.RW > 0 ? L.RW : 1) * sizeof(u64));
   L.ocap = tiles_of(W, H, 4);
   if (tiles_of(W, H, 8) > L.ocap) L.ocap = tiles_of(W, H, 8);
@@ -169,6 +183,7 @@ struct Dev {
   u64* costpos;   // relaxation costs by spatial position (IEEE bits) when they do not fit in LDS
   u64* rmask;     // wide relaxation rounds: three rotating change masks of RW words
   int* qctr;      // pixel-stage queue counters, kQueues of them kQueueStride ints apart
+  int* cmark;     // the barrier-free rounds' progress marks, kChaosSlots of them kQueueStride ints apart
   int* obins;     // pixel-stage work classes: item count of each (kOrderBins)
   int* order;     // work items of class c at order[c * ocap ...], in no particular order within it
   int ocap;
