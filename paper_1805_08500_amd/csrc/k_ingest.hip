@@ -225,25 +225,34 @@ __device__ __forceinline__ int floor_div(int a, int b) {  // b > 0
   return q;
 }
 
-// One workgroup per pixel row: the closed inside-obstacle mask.  The row's
+// One wavefront per pixel row: the closed inside-obstacle mask.  The row's
 // centre line y = 2j + 1 is odd and every vertex y is even, so the line never
 // passes through a vertex; each edge crossing it toggles the parity of the
 // pixels to its left, and a centre exactly on an edge counts as inside.
+// Toggles and on-edge centres are bits in the wavefront's own LDS words
+// (lds: 2 * TW of them, TW = (W + 32) / 32), merged by LDS atomics; pixel i is
+// inside iff the toggles at positions above i have odd parity, found per word
+// by a shift-xor suffix scan plus the parity of the later words (a ballot over
+// the lanes, each owning a run of words).
+__device__ __forceinline__ void lds_wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
 template <class S>
-__device__ __forceinline__ void inside_row(const S& src, int item, int* sh, int* wave_tot) {
+__device__ __forceinline__ void inside_row_wave(const S& src, int wid, unsigned* lds) {
   int sc, j;
-  if (!src.locate(STG_ROW, item, sc, j)) return;
+  if (!src.locate(STG_ROW, wid, sc, j)) return;
   const Dev& d = src.scene(sc);
   const int W = d.W, E = d.E, W32 = d.W32;
-  int* tog = sh;                                      // [W + 1]
-  unsigned char* on = (unsigned char*)(sh + W + 1);   // [W]
-  const int tid = threadIdx.x;
+  const int TW = (W + 32) >> 5;   // words of toggle positions 0..W
+  unsigned* tog = lds;
+  unsigned* on = lds + TW;
+  const int lane = lane_id();
+  for (int k = lane; k < TW; k += 64) { tog[k] = 0u; on[k] = 0u; }
+  lds_wave_sync();
   const int y = 2 * j + 1;
-  const int lane = tid & 63, wv = tid >> 6, nw = blockDim.x >> 6;
-  for (int k = tid; k <= W; k += blockDim.x) tog[k] = 0;
-  for (int k = tid; k < W; k += blockDim.x) on[k] = 0;
-  __syncthreads();
-  for (int e = tid; e < E; e += blockDim.x) {
+  for (int e = lane; e < E; e += 64) {
     const EdgeRec r = d.edges_raw[e];
     if ((r.wy > y) == (r.vy > y)) continue;
     // crossing x = N / Dn; |N| < 2^30 in doubled coordinates
@@ -253,46 +262,34 @@ __device__ __forceinline__ void inside_row(const S& src, int item, int* sh, int*
     const int f = floor_div(N - 1, Dn);       // largest integer strictly left of the crossing
     int cnt = floor_div(f + 1, 2);            // pixels i with 2i + 1 < crossing
     cnt = cnt < 0 ? 0 : (cnt > W ? W : cnt);
-    atomicXor(&tog[cnt], 1);
+    atomicXor(&tog[cnt >> 5], 1u << (cnt & 31));
     if (N >= 0 && N % Dn == 0) {
       const int xc = N / Dn;
       if (xc & 1) {
         const int i = (xc - 1) / 2;
-        if (i >= 0 && i < W) on[i] = 1;
+        if (i >= 0 && i < W) atomicOr(&on[i >> 5], 1u << (i & 31));
       }
     }
   }
-  __syncthreads();
-  // suffix xor: inside(i) = xor of tog[k] for k > i
-  const int per = (W + 1 + blockDim.x - 1) / blockDim.x;
-  const int k0 = tid * per, k1 = min(k0 + per, W + 1);
-  int x = 0;
-  for (int k = k0; k < k1; ++k) x ^= tog[k];
-  // xor of x over the threads after this one: within the wavefront by log steps, then the
-  // totals of the later wavefronts
-  int incl = x;   // xor over lanes >= lane
-#pragma unroll
-  for (int off = 1; off < 64; off <<= 1) {
-    const int o = __shfl_down(incl, off, 64);
-    if (lane + off < 64) incl ^= o;
-  }
-  if (lane == 0) wave_tot[wv] = incl;
-  __syncthreads();
-  int acc = incl ^ x;
-  for (int w = wv + 1; w < nw; ++w) acc ^= wave_tot[w];
+  lds_wave_sync();
+  const int per = (TW + 63) >> 6;
+  const int k0 = min(lane * per, TW), k1 = min(k0 + per, TW);
+  unsigned par = 0u;
+  for (int k = k0; k < k1; ++k) par ^= (unsigned)__popc(tog[k]) & 1u;
+  const u64 pm = ballot(par != 0u);
+  unsigned c = lane < 63 ? ((unsigned)__popcll(pm >> (lane + 1)) & 1u) : 0u;   // parity of later lanes' words
   for (int k = k1 - 1; k >= k0; --k) {
-    const int nxt = acc;     // xor of tog[m] for m > k
-    acc ^= tog[k];
-    tog[k] = nxt;            // now tog[k] = xor over m > k
-  }
-  __syncthreads();
-  for (int wd = tid; wd < W32; wd += blockDim.x) {
-    unsigned bits = 0;
-    for (int b = 0; b < 32; ++b) {
-      const int i = wd * 32 + b;
-      if (i < W && ((tog[i] & 1) || on[i])) bits |= 1u << b;
+    const unsigned t = tog[k];
+    unsigned x = t >> 1;   // bit b: xor of toggles b + 1 .. 31 of this word, after the scan
+    x ^= x >> 1; x ^= x >> 2; x ^= x >> 4; x ^= x >> 8; x ^= x >> 16;
+    if (c) x = ~x;
+    if (k < W32) {
+      unsigned bits = x | on[k];
+      const int rem = W - k * 32;
+      if (rem < 32) bits &= (1u << rem) - 1u;
+      d.inside[(size_t)j * W32 + k] = bits;
     }
-    d.inside[(size_t)j * W32 + wd] = bits;
+    c ^= (unsigned)__popc(t) & 1u;
   }
 }
 
@@ -302,13 +299,13 @@ static inline unsigned blocks_for(long long items, int per_block) {
 
 // Two independent steps in one launch: the first nrank workgroups rank the
 // edges (one wavefront per edge), the others build the inside mask (one
-// workgroup per pixel row, from the raw edges).
+// wavefront per pixel row, from the raw edges; lds_words LDS words each).
 template <class S>
-__global__ __launch_bounds__(256) void k_rank_inside(S src, int nrank) {
-  extern __shared__ int sh[];
-  __shared__ int wave_tot[4];
-  if ((int)blockIdx.x < nrank) edge_rank_wave(src, blockIdx.x * 4 + (threadIdx.x >> 6));
-  else inside_row(src, blockIdx.x - nrank, sh, wave_tot);
+__global__ __launch_bounds__(256) void k_rank_inside(S src, int nrank, int lds_words) {
+  extern __shared__ unsigned shw[];
+  const int wv = threadIdx.x >> 6;
+  if ((int)blockIdx.x < nrank) edge_rank_wave(src, blockIdx.x * 4 + wv);
+  else inside_row_wave(src, ((int)blockIdx.x - nrank) * 4 + wv, shw + wv * lds_words);
 }
 
 // Two independent steps on the sorted edges in one launch: the first
@@ -334,8 +331,10 @@ hipError_t launch_ingest(const S& src, const Plan& p, hipStream_t s) {
 template <class S>
 hipError_t launch_edge_sort(const S& src, const Plan& p, hipStream_t s) {
   const unsigned nrank = p.total[STG_EDGE] > 0 ? blocks_for(p.total[STG_EDGE], 4) : 0u;
-  const size_t shm = (size_t)(p.maxW + 1) * sizeof(int) + (size_t)p.maxW + 16;
-  hipLaunchKernelGGL(k_rank_inside<S>, dim3(nrank + (unsigned)p.total[STG_ROW]), dim3(256), shm, s, src, (int)nrank);
+  const int lds_words = 2 * ((p.maxW + 32) >> 5);
+  const size_t shm = 4 * (size_t)lds_words * sizeof(unsigned);
+  hipLaunchKernelGGL(k_rank_inside<S>, dim3(nrank + blocks_for(p.total[STG_ROW], 4)), dim3(256), shm, s, src,
+                     (int)nrank, lds_words);
   return hipGetLastError();
 }
 

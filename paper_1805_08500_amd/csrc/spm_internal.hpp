@@ -225,7 +225,7 @@ enum StageKind {
   STG_SCENE,     // one workgroup per scene
   STG_EDGE,      // one wavefront per edge
   STG_CHUNK,     // one thread per edge chunk
-  STG_ROW,       // one workgroup per pixel row
+  STG_ROW,       // one wavefront per pixel row
   STG_GVBLK,     // one 4-wavefront workgroup per 4 (row, gv_sub columns) generator-visibility items
   STG_GEN,       // one wavefront per generator slot
   STG_SLICE,     // one pixel-tile slice (batched pixel stage)
