@@ -14,13 +14,9 @@
 
 namespace spm {
 
-// One thread per obstacle vertex i: the edge i -> next(i), its neighbours,
-// the corner's convexity and a Morton key of the edge midpoint.
-template <class S>
-__global__ __launch_bounds__(256) void k_ingest_edges(S src) {
-  int sc, i;
-  if (!src.locate(STG_VTX, blockIdx.x * blockDim.x + threadIdx.x, sc, i)) return;
-  const Dev& d = src.scene(sc);
+// Obstacle vertex i: the edge i -> next(i), its neighbours, the corner's
+// convexity and a Morton key of the edge midpoint.
+__device__ __forceinline__ void ingest_vertex(const Dev& d, int i) {
   int lo = 0, hi = d.n_polys - 1;
   while (lo < hi) {
     int mid = (lo + hi + 1) >> 1;
@@ -52,14 +48,28 @@ __global__ __launch_bounds__(256) void k_ingest_edges(S src) {
   d.keys[i] = ((u64)code << 32) | (u64)(unsigned)i;
 }
 
+// One thread per obstacle vertex, chip-wide (scenes with many vertices).
+template <class S>
+__global__ __launch_bounds__(256) void k_ingest_edges(S src) {
+  int sc, i;
+  if (!src.locate(STG_VTX, blockIdx.x * blockDim.x + threadIdx.x, sc, i)) return;
+  ingest_vertex(src.scene(sc), i);
+}
+
 // One workgroup per scene: the canonical generator table.  Points, then
 // segments, then every convex corner (left turn) in vertex order; ids by a
-// block scan.  Also resets the scene's pixel tile queue.
-template <class S>
+// block scan.  Also resets the scene's pixel tile queue.  EDGES: the
+// workgroup first ingests the scene's vertices itself (scenes of at most
+// kIngestFuseMax vertices), saving the chip-wide launch.
+template <class S, bool EDGES>
 __global__ __launch_bounds__(1024) void k_gen_table(S src) {
   int sc, one;
   if (!src.locate(STG_SCENE, blockIdx.x, sc, one)) return;
   const Dev& d = src.scene(sc);
+  if (EDGES) {
+    for (int i = threadIdx.x; i < d.nv; i += blockDim.x) ingest_vertex(d, i);
+    __syncthreads();
+  }
   __shared__ int wave_tot[16];
   __shared__ int running;
   const int tid = threadIdx.x;
@@ -321,9 +331,13 @@ __global__ __launch_bounds__(1024) void k_gorder_boxes(S src, int ngorder) {
 
 template <class S>
 hipError_t launch_ingest(const S& src, const Plan& p, hipStream_t s) {
+  if (p.maxE <= kIngestFuseMax) {
+    hipLaunchKernelGGL((k_gen_table<S, true>), dim3((unsigned)p.total[STG_SCENE]), dim3(1024), 0, s, src);
+    return hipGetLastError();
+  }
   if (p.total[STG_VTX] > 0)
     hipLaunchKernelGGL(k_ingest_edges<S>, dim3(blocks_for(p.total[STG_VTX], 256)), dim3(256), 0, s, src);
-  hipLaunchKernelGGL(k_gen_table<S>, dim3((unsigned)p.total[STG_SCENE]), dim3(1024), 0, s, src);
+  hipLaunchKernelGGL((k_gen_table<S, false>), dim3((unsigned)p.total[STG_SCENE]), dim3(1024), 0, s, src);
   return hipGetLastError();
 }
 

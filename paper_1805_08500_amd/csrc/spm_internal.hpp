@@ -43,6 +43,7 @@ constexpr int kRelaxChaosMax = SPM_RELAX_CHAOS_MAX;   // their cap when they sto
 #endif
 constexpr int kChaosAdaptMinGen = SPM_CHAOS_ADAPT_MIN_GEN;   // above that many generators they do
 constexpr int kChaosSlots = 8;     // progress marks, spread over cache lines to keep atomics apart
+constexpr int kIngestFuseMax = 1024;   // scenes up to that many vertices ingest in the generator-table launch
 constexpr int kDefaultStrip = 1;      // tiles per pixel-stage work item
 constexpr int kDefaultSamples = 3;    // seed searches per pixel tile
 constexpr int kMaxStrip = 64;
