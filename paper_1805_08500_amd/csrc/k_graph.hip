@@ -504,26 +504,33 @@ __global__ __launch_bounds__(1024) void k_relax(S src, int Gcap, int RWcap, int 
   const int G = d.misc[MISC_G];
   const int nsrc = d.np + d.ns;
   const int ncr = G - nsrc;   // corner rows
-  if (LDS) {
+  // nothing changed in the last chip-wide round: the costs are final, skip the staging
+  const u64* m0 = d.rmask + m0idx * RW;
+  if (tid == 0) any = 0;
+  __syncthreads();
+  for (int k = tid; k < RW; k += nt)
+    if (m0[k]) any = 1;
+  __syncthreads();
+  const bool idle = !any;
+  if (LDS && !idle) {
     int4* s_gxy = (int4*)(shm + 2 * RWcap + Gcap);
     for (int g = tid; g < G; g += nt) { cost[g] = d.costpos[g]; s_gxy[g] = d.gxy[g]; }
     gxy = s_gxy;
   }
-  if (VLDS) {
+  if (VLDS && !idle) {
     // the arc matrix itself in LDS (G rows of RW words)
     u64* s_vis = shm + 2 * RWcap + 3 * (size_t)Gcap;
     for (int k = tid; k < G * RW; k += nt) s_vis[k] = d.vis[k];
     vis = s_vis;
   }
   // the change mask left by the wide rounds
-  const u64* m0 = d.rmask + m0idx * RW;
   for (int k = tid; k < RW; k += nt) { chg_a[k] = m0[k]; chg_b[k] = 0; }
   if (tid == 0) { reached = 0; nfront = -1; }
   __syncthreads();
   u64* cur = chg_a;
   u64* nxt = chg_b;
   int rounds = 0;
-  for (; rounds <= G; ++rounds) {
+  for (; !idle && rounds <= G; ++rounds) {
     if (tid == 0) any = 0;
     const int nf = nfront;  // frontier list size, or -1 when only the mask is valid
     __syncthreads();
@@ -612,10 +619,11 @@ __global__ __launch_bounds__(1024) void k_relax(S src, int Gcap, int RWcap, int 
   }
   // outputs by canonical id; parents follow in k_gsort_parents
   int mine = 0;
+  const u64* fin = (LDS && !idle) ? cost : d.costpos;
   for (int p = tid; p < G; p += nt) {
-    const double c = __longlong_as_double((long long)cost[p]);
+    const double c = __longlong_as_double((long long)fin[p]);
     const int v = d.gorder[p];
-    if (LDS) d.costpos[p] = cost[p];
+    if (LDS && !idle) d.costpos[p] = cost[p];
     d.gen_cost[v] = c;
     d.cost64[v] = c;
     if (c < INFINITY) ++mine;
