@@ -184,16 +184,58 @@ __device__ __forceinline__ bool pair_visible(const Geo& geo, int px, int py, boo
 // Point columns by pairs (few edges): one wavefront per row of a
 // kGvPairRows x kGvPairRows block of the lower triangle of the matrix (blocks
 // numbered row by row), testing its pairs (row corner v, column u < v) one at
-// a time.  Corner-corner visibility is symmetric, so a visible pair sets both
+// a time; spread: the same pairs dealt round-robin instead (smaller graphs).  Corner-corner visibility is symmetric, so a visible pair sets both
 // v's bit u and u's bit v; point-source columns set v's bit only (source rows
 // are never read) and segment columns are left to the segment wavefronts.
 template <class S>
-__device__ __forceinline__ void genvis_pairs(const Dev& d, const Geo& geo, int wid) {
+__device__ __forceinline__ void genvis_pairs(const Dev& d, const Geo& geo, int wid, bool spread) {
   const int RW = d.RW;
   const int G = uni(d.misc[MISC_G]);
   const int nsrc = d.np + d.ns;
   const int lane = lane_id();
   relax_init(d, wid, G, nsrc);
+  if (spread) {
+  // The pairs of the block enumeration (block b, row i, column c), dealt
+  // round-robin: lane j < kGvPairRows holds pair q = wid + j * NW, so every
+  // wavefront mixes pairs from all over the triangle (pairs far apart cross
+  // more chunks, and whole blocks off the diagonal are far apart).
+  const int Bn = (d.Gmax + kGvPairRows - 1) / kGvPairRows;
+  const int NW = kGvPairRows * (Bn * (Bn + 1) / 2);
+  if (wid >= NW) return;
+  int r = G, u = G;
+  if (lane < kGvPairRows) {
+    const int q = wid + lane * NW;
+    const int rowid = q / kGvPairRows, c = q - rowid * kGvPairRows;
+    const int b = rowid / kGvPairRows, i = rowid - b * kGvPairRows;
+    int R = (int)((sqrtf(8.0f * (float)b + 1.0f) - 1.0f) * 0.5f);
+    while (R > 0 && R * (R + 1) / 2 > b) --R;
+    while ((R + 1) * (R + 2) / 2 <= b) ++R;
+    r = R * kGvPairRows + i;
+    u = (b - R * (R + 1) / 2) * kGvPairRows + c;
+  }
+  const bool ok = r < G && r >= nsrc && u < r;
+  GenRec gr = {}, gu = {};
+  if (ok) {
+    gr = d.gens[d.gorder[r]];
+    gu = d.gens[d.gorder[u]];
+  }
+  u64 todo = ballot(ok && gu.kind != SPM_GEN_SEGMENT);
+  bool seen = false;
+  while (todo) {
+    const int j = (int)__builtin_ctzll(todo);
+    todo &= todo - 1;
+    const bool pv = readlane(gu.kind, j) == SPM_GEN_VERTEX;
+    const bool vj = pair_visible(geo, readlane(gu.x, j), readlane(gu.y, j), pv, readlane(gu.ux, j), readlane(gu.uy, j),
+                                 readlane(gu.nx, j), readlane(gu.ny, j), readlane(gr.x, j), readlane(gr.y, j),
+                                 readlane(gr.ux, j), readlane(gr.uy, j), readlane(gr.nx, j), readlane(gr.ny, j));
+    if (lane == j) seen = vj;
+  }
+  if (seen) {
+    atomicOr(&d.vis[(size_t)r * RW + (u >> 6)], 1ull << (u & 63));
+    if (u >= nsrc) atomicOr(&d.vis[(size_t)u * RW + (r >> 6)], 1ull << (r & 63));
+  }
+  return;
+  }
   const int b = wid / kGvPairRows, i = wid - b * kGvPairRows;
   // block row R of block b: R (R + 1) / 2 <= b < (R + 1) (R + 2) / 2
   int R = (int)((sqrtf(8.0f * (float)b + 1.0f) - 1.0f) * 0.5f);
@@ -279,7 +321,7 @@ __global__ __launch_bounds__(256) void k_genvis(S src, int nblk_points) {
     geo.chunks = s_chunks;
   }
   if (pts) {
-    if (d.gv_sub == 0) genvis_pairs<S>(d, geo, item * 4 + (threadIdx.x >> 6));
+    if (d.gv_sub <= 0) genvis_pairs<S>(d, geo, item * 4 + (threadIdx.x >> 6), d.gv_sub < 0);
     else genvis_points<S>(d, geo, item * 4 + (threadIdx.x >> 6));
   } else {
     genvis_segments(d, geo, item);

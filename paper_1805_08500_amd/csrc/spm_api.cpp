@@ -339,6 +339,8 @@ void fill_dev(Dev& d, const spm_scene* s, const spm_out* out, char* ws, const La
   while (d.gv_sub > 16 && (long long)L.Gmax * L.RW * (64 / (d.gv_sub / 2)) <= 16384) d.gv_sub /= 2;
   // beyond a few wavefronts' worth of generators: every arc by itself, 64 edges per step
   if (L.Gmax >= SPM_GV_PAIR_MIN_GEN) d.gv_sub = 0;
+  // up to kGvSpreadMaxGen generators each wavefront takes pairs from all over the triangle
+  if (d.gv_sub == 0 && L.Gmax <= kGvSpreadMaxGen) d.gv_sub = -1;
   d.stats = stats;
 }
 

@@ -61,6 +61,10 @@ constexpr int kGvPairRows = SPM_GV_PAIR_ROWS;   // generator visibility by pairs
 #ifndef SPM_GV_PAIR_MIN_GEN
 #define SPM_GV_PAIR_MIN_GEN 128    // generator visibility by pairs from this many generators on
 #endif
+#ifndef SPM_GV_SPREAD_MAX_GEN
+#define SPM_GV_SPREAD_MAX_GEN 1024
+#endif
+constexpr int kGvSpreadMaxGen = SPM_GV_SPREAD_MAX_GEN;   // pairs dealt round-robin over the triangle up to this many generators
 
 // One obstacle edge w -> v (obstacle on the left), with its line function
 // E(x, y) = a x + b y + c, positive on the obstacle side.
@@ -202,7 +206,8 @@ struct Dev {
   int samples;     // pixel stage: seed searches per tile (>= 0)
   int walk;        // pixel stage: 0 by generator count, else 1 + the walk (cached, refilled, cost order)
   int gv_sub;      // generator visibility: columns per wavefront (64, 32 or 16); 0: one pair at a time,
-                   // lanes over edges (kGvPairRows x kGvPairRows blocks of the lower triangle)
+                   // lanes over edges (kGvPairRows x kGvPairRows blocks of the lower triangle);
+                   // -1: the same pairs dealt round-robin over the triangle
   u64* stats;
 };
 
@@ -244,7 +249,7 @@ __host__ __device__ inline int stage_count(const Dev& d, int stage) {
     case STG_CHUNK: return d.NC;
     case STG_ROW: return d.H;
     case STG_GVBLK: {
-      if (d.gv_sub == 0) {
+      if (d.gv_sub <= 0) {
         const long long B = (d.Gmax + kGvPairRows - 1) / kGvPairRows;
         return (int)((kGvPairRows * (B * (B + 1) / 2) + 3) / 4);
       }
