@@ -208,3 +208,29 @@ def test_batch_argument_errors(C):
     assert L.spm_build_batch(ctypes.byref(b), fake, 1, None, None) == C.SPM_ERR_CAPACITY
     g = ctypes.c_void_p()
     assert L.spm_graph_capture_batch(ctypes.byref(b), fake, 1, None, ctypes.byref(g)) == C.SPM_ERR_INVALID_ARG
+
+
+
+def test_build_entry_reaches_the_build_module():
+    """__graft_entry__.build() must call the compiler module, not the package's build() function of
+    the same name.  Runs in a fresh interpreter (where the package attribute is still the function)
+    with both compilers replaced by stub modules: nothing is compiled."""
+    import subprocess
+    import sys
+    script = (
+        "import sys, types\n"
+        "calls = []\n"
+        "b = types.ModuleType('paper_1805_08500_amd.build')\n"
+        "b.build = lambda verbose=False: calls.append(('lib', verbose))\n"
+        "o = types.ModuleType('oracle.oracle')\n"
+        "o.build = lambda force=False: calls.append(('oracle', force))\n"
+        "sys.modules['paper_1805_08500_amd.build'] = b\n"
+        "sys.modules['oracle.oracle'] = o\n"
+        f"sys.path.insert(0, {ROOT!r})\n"
+        "import __graft_entry__\n"
+        "__graft_entry__.build()\n"
+        "assert calls == [('lib', True), ('oracle', True)], calls\n"
+        "print('ok')\n"
+    )
+    r = subprocess.run([sys.executable, "-c", script], capture_output=True, text=True, timeout=240, cwd=ROOT)
+    assert r.returncode == 0 and r.stdout.strip().endswith("ok"), r.stderr[-2000:]
