@@ -733,10 +733,11 @@ __global__ __launch_bounds__(256) void k_gsort_parents(S src, int nsort, int nor
     const int G = d.misc[MISC_G];
     int4* bb = gsm;
     float* cost = (float*)(gsm + d.Gmax);
+    // the minimum runs over all generators, so the compact arrays by spatial position serve
     for (int g = threadIdx.x; g < G; g += blockDim.x) {
-      const GenRec& r = d.gens[g];
-      bb[g] = make_int4(min(r.x, r.x2), min(r.y, r.y2), max(r.x, r.x2), max(r.y, r.y2));
-      cost[g] = (float)d.cost64[g];
+      const int4 r = d.gxy[g];
+      bb[g] = make_int4(min(r.x, r.z), min(r.y, r.w), max(r.x, r.z), max(r.y, r.w));
+      cost[g] = (float)__longlong_as_double((long long)d.costpos[g]);
     }
     if (threadIdx.x < kOrderBins) lcount[threadIdx.x] = 0;
     __syncthreads();
