@@ -247,6 +247,31 @@ class Mini:
                     best = (d, "vertex", k)
         return best
 
+    def generator_value(self, i, j, kind, ref):
+        """What one generator offers pixel (i, j) when it is a candidate on its own: cost + distance
+        when the pixel centre sees the generator's nearest point, +inf otherwise.  kind is
+        'point' / 'segment' / 'vertex' and ref its index among the points, segments or all obstacle
+        vertices.  A segment's nearest point is the clamped projection of the centre onto the
+        whole segment (one candidate per segment source), computed here in Fraction arithmetic."""
+        p = (F(2 * i + 1, 2), F(2 * j + 1, 2))
+        if closed_inside(self.polys, p):
+            return math.inf
+        if kind == "point":
+            q, c = self.points[ref], 0.0
+        elif kind == "segment":
+            ax, ay, bx, by = (F(v) for v in self.segs[ref])
+            e = (bx - ax, by - ay)
+            t = ((p[0] - ax) * e[0] + (p[1] - ay) * e[1]) / (e[0] * e[0] + e[1] * e[1])
+            t = min(max(t, F(0)), F(1))
+            q, c = (ax + t * e[0], ay + t * e[1]), 0.0
+        else:
+            q, c = self.V[ref], self.cost[ref]
+            if not math.isfinite(c):
+                return math.inf
+        if not visible(self.polys, p, q, self.E):
+            return math.inf
+        return c + _dist(p, q)
+
     def grid(self):
         W, H = self.scene.width, self.scene.height
         D = np.full((H, W), np.inf)

@@ -63,6 +63,7 @@ def _load():
         L.orc_costs.argtypes = [sp, dp, ip, dp, ctypes.c_int]
         L.orc_pixels.argtypes = [sp, dp, ctypes.c_int, i64p, fp, ip, dp, dp, ctypes.c_int]
         L.orc_inside.argtypes = [sp, ctypes.c_int, i64p, ctypes.POINTER(ctypes.c_ubyte)]
+        L.orc_candidates.argtypes = [sp, dp, ctypes.c_int, i64p, ip, dp, ctypes.c_int]
         L.orc_points.argtypes = [sp, dp, ctypes.c_int, i64p, ctypes.c_int64, dp, ip, dp, ctypes.c_int]
         L.orc_max_threads.argtypes = []
         _lib = L
@@ -169,6 +170,24 @@ def points(scene, cost, qxy, qw: int, nthreads: int = 0) -> dict:
                      _ptr(d64, ctypes.c_double), _ptr(par, ctypes.c_int), _ptr(sec, ctypes.c_double),
                      int(nthreads))
     return {"dist64": d64[:n], "parent": par[:n], "second": sec[:n]}
+
+
+def candidates(scene, cost, pix, gen, nthreads: int = 0) -> np.ndarray:
+    """cost(g) + |p - x_g(p)| for each (pixel pix[k], generator gen[k]) pair when the pixel
+    centre sees x_g(p), +inf otherwise (float64)."""
+    L = _load()
+    b = _Bound(scene)
+    pix = np.ascontiguousarray(np.asarray(pix, np.int64).reshape(-1))
+    gen = np.ascontiguousarray(np.asarray(gen, np.int32).reshape(-1))
+    assert pix.size == gen.size
+    cost = np.ascontiguousarray(np.asarray(cost, np.float64))
+    if cost.size == 0:
+        cost = np.zeros(1, np.float64)
+    out = np.zeros(max(pix.size, 1), np.float64)
+    if pix.size:
+        L.orc_candidates(b.ref, _ptr(cost, ctypes.c_double), pix.size, _ptr(pix, ctypes.c_int64),
+                         _ptr(gen, ctypes.c_int), _ptr(out, ctypes.c_double), int(nthreads))
+    return out[:pix.size]
 
 
 def inside(scene, pix) -> np.ndarray:

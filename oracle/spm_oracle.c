@@ -466,6 +466,35 @@ int orc_pixels(const orc_scene *in, const double *cost, int n, const int64_t *pi
   return ORC_OK;
 }
 
+/* The value one generator offers one pixel (Procedure 3's cone, Section 4's
+ * segment distance): cost(g) + |p - x_g(p)| when g has a finite cost and the
+ * pixel centre sees x_g(p), +inf otherwise (also for a centre in or on an
+ * obstacle).  Pair k is (pix[k], gen[k]).  Used to check that a map's parent
+ * at a near-tie pixel is one of the valid choices. */
+int orc_candidates(const orc_scene *in, const double *cost, int n, const int64_t *pix, const int *gen,
+                   double *value, int nthreads) {
+  oscene s;
+  load_oscene(in, &s);
+#ifdef _OPENMP
+  if (nthreads > 0) omp_set_num_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 16)
+#endif
+  for (int k = 0; k < n; ++k) {
+    int64_t i = pix[k] % s.W, j = pix[k] / s.W;
+    int64_t px = 2 * i + 1, py = 2 * j + 1;
+    int g = gen[k];
+    double v = INFINITY;
+    if (g >= 0 && g < s.G && isfinite(cost[g]) && !in_closed_obstacle(&s, px, py)) {
+      double d;
+      hpt q = gen_point(&s, g, px, py, &d);
+      if (visible(&s, hp(px, py), q)) v = cost[g] + d;
+    }
+    value[k] = v;
+  }
+  free_oscene(&s);
+  return ORC_OK;
+}
+
 /* closed inside-obstacle mask for the listed pixels */
 int orc_inside(const orc_scene *in, int n, const int64_t *pix, unsigned char *inside) {
   oscene s;
@@ -486,7 +515,7 @@ int orc_max_threads(void) {
 #endif
 }
 
-/* Map value at rational points (Section 6: the exact first turn of a query
+/* Map value at rational points (Section 5.1, Discussion: the exact first turn of a query
  * point, not its pixel's).  Query k is (qxy[2k] / qw, qxy[2k+1] / qw) in
  * doubled coordinates.  Same rule as orc_pixels, over every generator:
  * dist64 / parent / second; a point in or on an obstacle, or outside the

@@ -35,8 +35,10 @@ def test_batch_matches_oracle_and_single_builds(oracle_mod, spm):
     for k, (sc, m) in enumerate(zip(scenes, maps)):
         h = m.host()
         ref = oracle_mod.full_map(sc)
-        compare(h["dist"], h["parent"], ref, f"batch[{k}]")
-        compare_generators(h, ref["cost"], ref["gparent"], f"batch[{k}]")
+        cost, gpar, wts = oracle_mod.costs(sc, weights=True)
+        compare(h["dist"], h["parent"], ref, f"batch[{k}]", O=oracle_mod, scene=sc, cost=cost,
+                pix=np.arange(sc.width * sc.height), max_ambiguous=0.05)
+        compare_generators(h, cost, gpar, wts, f"batch[{k}]")
         one = _single(spm, sc, tiles[k])
         assert np.array_equal(one["dist"], h["dist"]) and np.array_equal(one["parent"], h["parent"]), k
 
@@ -79,10 +81,11 @@ def test_config4_batch_sampled(oracle_mod, spm):
     for k in rng.choice(len(scenes), 6, replace=False):
         sc = scenes[k]
         h = bb.maps[k].host()
-        cost, gpar = oracle_mod.costs(sc)
-        compare_generators(h, cost, gpar, f"c4[{k}]")
+        cost, gpar, wts = oracle_mod.costs(sc, weights=True)
+        compare_generators(h, cost, gpar, wts, f"c4[{k}]")
         pix = np.unique(rng.integers(0, sc.width * sc.height, 4000))
         r = oracle_mod.pixels(sc, cost, pix)
-        compare(h["dist"].reshape(-1)[pix], h["parent"].reshape(-1)[pix], r, f"c4[{k}]")
+        compare(h["dist"].reshape(-1)[pix], h["parent"].reshape(-1)[pix], r, f"c4[{k}]", O=oracle_mod, scene=sc,
+                cost=cost, pix=pix, max_ambiguous=0.05)
         one = _single(spm, sc, 8)
         assert np.array_equal(one["dist"], h["dist"]) and np.array_equal(one["parent"], h["parent"]), k

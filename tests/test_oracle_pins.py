@@ -236,6 +236,98 @@ def test_enumeration_matches_oracle(oracle_mod, k):
                 assert kind[p] == exp_kind and ref[p] == where, (i, j)
 
 
+# ------------------------------------------------ runner-up D2 and single-generator values
+def test_free_space_runner_up(oracle_mod):
+    """Without obstacles every source is visible: D2 is the second smallest of the closed-form
+    distances to the point sources and to the segment (rotated frame)."""
+    pts = np.asarray([[3, 3], [30, 7], [12, 25], [25, 26]])
+    seg = np.asarray([[4, 5, 27, 19]])
+    s = Scene(34, 31, [], pts, seg)
+    m = oracle_mod.full_map(s)
+    i, j = _pix_centres(34, 31)
+    dp = [np.hypot(i - x, j - y) for x, y in pts]
+    e = complex(23, 14)
+    L = abs(e)
+    z = ((i + 1j * j) - complex(4, 5)) * np.conj(e) / L
+    ds = np.where((z.real >= 0) & (z.real <= L), np.abs(z.imag), np.minimum(np.abs(z), np.abs(z - L)))
+    srt = np.sort(np.stack(dp + [ds]), 0)
+    np.testing.assert_allclose(m["dist64"], srt[0], atol=1e-9)
+    np.testing.assert_allclose(m["second"], srt[1], atol=1e-9)
+
+
+_KIND_NAME = {0: "point", 1: "segment", 2: "vertex"}
+_mini_cache = {}
+
+
+def _mini_values(O, k):
+    """(scene, oracle map, oracle costs, generator table, mini's value matrix [pixels, G])."""
+    if k not in _mini_cache:
+        scene = _tiny_scenes()[k]
+        M = mini.Mini(scene, max_vertices=9)
+        cost, _ = O.costs(scene)
+        kind, ref, xy = O.generators(scene)
+        W, H, G = scene.width, scene.height, len(cost)
+        vals = np.array([[M.generator_value(i, j, _KIND_NAME[int(kind[g])], int(ref[g])) for g in range(G)]
+                         for j in range(H) for i in range(W)], np.float64).reshape(W * H, G)
+        _mini_cache[k] = (scene, O.full_map(scene), cost, (kind, ref, xy), vals)
+    return _mini_cache[k]
+
+
+@pytest.mark.parametrize("k", range(5))
+def test_runner_up_and_candidates_match_mini(oracle_mod, k):
+    """Every (pixel, generator) value of the oracle, and its runner-up D2, against mini.py's
+    brute force: its own visibility (event midpoints in Fraction arithmetic), its enumerated corner
+    costs and its own clamped projection onto a segment source.  D2 is the second smallest value
+    over the visible generators (Procedure 3 keeps the smallest; the next one decides which pixels
+    are near-ties)."""
+    scene, m, cost, (kind, ref, xy), vals = _mini_values(oracle_mod, k)
+    W, H, G = scene.width, scene.height, len(cost)
+    pix = np.repeat(np.arange(W * H, dtype=np.int64), G)
+    gen = np.tile(np.arange(G, dtype=np.int32), W * H)
+    got = oracle_mod.candidates(scene, cost, pix, gen).reshape(W * H, G)
+    assert np.array_equal(np.isinf(got), np.isinf(vals)), np.argwhere(np.isinf(got) != np.isinf(vals))[:5]
+    fin = np.isfinite(vals)
+    np.testing.assert_allclose(got[fin], vals[fin], rtol=1e-12, atol=1e-12)
+    srt = np.sort(vals, 1)
+    d1 = srt[:, 0]
+    d2 = srt[:, 1] if G > 1 else np.full(W * H, np.inf)
+    for name, mine, ref_v in (("D", d1, m["dist64"].ravel()), ("D2", d2, m["second"].ravel())):
+        assert np.array_equal(np.isinf(mine), np.isinf(ref_v)), name
+        f = np.isfinite(mine)
+        np.testing.assert_allclose(ref_v[f], mine[f], rtol=1e-12, atol=1e-12, err_msg=name)
+
+
+def test_runner_up_pin_catches_plausible_mistakes(oracle_mod):
+    """The pin above would fail for the mistakes a runner-up is prone to: taken over every other
+    candidate whether visible or not, or counting the winner twice (D2 = D)."""
+    over_invisible = 0
+    winner_twice = 0
+    for k in range(5):
+        scene, m, cost, (kind, ref, xy), vals = _mini_values(oracle_mod, k)
+        W, H, G = scene.width, scene.height, len(cost)
+        if G < 2:
+            continue
+        i, j = _pix_centres(W, H)
+        i, j = i.ravel(), j.ravel()
+        blind = np.empty((W * H, G))
+        for g in range(G):
+            x0, y0, x1, y1 = (float(v) for v in xy[g])
+            if kind[g] == oracle_mod.SEGMENT:
+                ex, ey = x1 - x0, y1 - y0
+                t = np.clip(((i - x0) * ex + (j - y0) * ey) / (ex * ex + ey * ey), 0, 1)
+                blind[:, g] = np.hypot(i - x0 - t * ex, j - y0 - t * ey)
+            else:
+                blind[:, g] = cost[g] + np.hypot(i - x0, j - y0)
+        free = np.isfinite(vals).sum(1) >= 2
+        win = np.argmin(vals, 1)
+        blind[np.arange(W * H), win] = np.inf
+        wrong = blind.min(1)
+        d2 = np.sort(vals, 1)[:, 1]
+        over_invisible += int(np.sum(free & (wrong < d2 - 1e-6)))
+        winner_twice += int(np.sum(free & (d2 > np.sort(vals, 1)[:, 0] + 1e-6)))
+    assert over_invisible > 50 and winner_twice > 500, (over_invisible, winner_twice)
+
+
 # ------------------------------------------------ invariants on larger scenes
 def _check_invariants(O, scene):
     cost, gpar, Wm = O.costs(scene, weights=True)
