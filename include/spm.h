@@ -59,10 +59,10 @@ typedef enum {
 
 enum { SPM_GEN_POINT = 0, SPM_GEN_SEGMENT = 1, SPM_GEN_VERTEX = 2 };
 
-/* A scene.  For spm_validate the arrays are host memory; for spm_build and
- * spm_backward they are device memory.  The counts are always host values.
- * Borrowed for the duration of the call only (device reads are complete when
- * the queued work completes). */
+/* A scene.  For spm_validate and spm_build the arrays are host memory, read
+ * before the call returns; for spm_build_ex, the batched builds and
+ * spm_query_points they are device memory, read by the queued work (keep
+ * them until it completes).  The counts are always host values. */
 typedef struct {
   int32_t width, height;     /* W, H */
   int32_t n_polys;           /* number of obstacle polygons */
@@ -93,7 +93,8 @@ const char* spm_last_error(void);
 
 /* Exact host-side check of a host-memory scene against the conventions above
  * (O(n^2) in the vertex count).  Returns SPM_OK, SPM_ERR_INVALID_ARG,
- * SPM_ERR_RANGE or SPM_ERR_GEOMETRY.  spm_build does not repeat this check. */
+ * SPM_ERR_RANGE or SPM_ERR_GEOMETRY.  spm_build runs it on every call;
+ * spm_build_ex and the batched builds take its result as a prerequisite. */
 int spm_validate(const spm_scene* host_scene);
 
 /* Capacities for a scene's counts (only the scalar fields are read):
@@ -101,13 +102,28 @@ int spm_validate(const spm_scene* host_scene);
  * build needs.  Returns SPM_ERR_INVALID_ARG / SPM_ERR_RANGE for bad counts. */
 int spm_query_sizes(const spm_scene* scene, int32_t* max_gen, size_t* workspace_bytes);
 
-/* Build the map (all steps on the device, queued on `stream`, a hipStream_t;
- * NULL = the null stream).  Returns after queueing; no host synchronisation
- * and no device allocation happen inside, so the call can be captured in a
- * HIP graph.  d_ws must hold workspace_bytes from spm_query_sizes and stays
- * owned by the caller; it must not be shared by builds that can run
- * concurrently.  The scene must satisfy spm_validate (unchecked here). */
-int spm_build(const spm_scene* dev_scene, const spm_out* out, void* d_ws, size_t ws_bytes, void* stream);
+/* Build the map of a host-memory scene: the problem statement of Sections 3
+ * and 4 (obstacles, point and segment sources) in, the grid of distance and
+ * parent (Section 3: the map's per-pixel distance and ParentId) plus the
+ * generator table out.
+ *   1. On the host, before any device work: argument checks, then spm_validate
+ *      (any failure returns its code: SPM_ERR_INVALID_ARG, SPM_ERR_RANGE,
+ *      SPM_ERR_GEOMETRY; SPM_ERR_CAPACITY when ws_bytes is below
+ *      spm_query_sizes' figure).
+ *   2. The scene is copied into the library's pinned staging (a ring of four
+ *      slots, each grown once to the largest scene it has held and kept until
+ *      the process ends), so the caller may free or change it as soon as the
+ *      call returns, and from there into d_ws by an asynchronous copy on
+ *      `stream` (a hipStream_t; NULL = the null stream).  Reusing a slot waits
+ *      for the copy queued from it four calls earlier.
+ *   3. Every step of the build is queued on `stream`; the call returns without
+ *      waiting for it.
+ * d_ws (device memory, workspace_bytes from spm_query_sizes) stays owned by
+ * the caller and must not be shared by builds that can run concurrently.
+ * Because of the host staging the call cannot be captured in a HIP graph
+ * (SPM_ERR_INVALID_ARG while `stream` is capturing): capture spm_build_ex.
+ * SPM_ERR_HIP if a HIP call fails. */
+int spm_build(const spm_scene* host_scene, const spm_out* out, void* d_ws, size_t ws_bytes, void* stream);
 
 /* Optional per-stage timing: a timer records HIP events around each build
  * stage on the build's stream.  spm_timer_elapsed synchronises on the last
@@ -150,6 +166,14 @@ typedef struct {
   int32_t samples;
   int32_t walk;
 } spm_build_opts;
+/* The same build from a scene already in device memory (dev_scene's arrays;
+ * its counts are host values), with options (opts may be NULL: defaults).
+ * Nothing is copied or allocated and the host never waits, so the call can be
+ * captured in a HIP graph and replayed.  Prerequisite: the scene passed
+ * spm_validate (as host arrays with the same contents); it is not checked
+ * again here, and a scene that breaks the conventions gives unspecified
+ * outputs.  Argument errors (SPM_ERR_INVALID_ARG, SPM_ERR_CAPACITY) are found
+ * before any launch; SPM_ERR_HIP if a launch fails. */
 int spm_build_ex(const spm_scene* dev_scene, const spm_out* out, void* d_ws, size_t ws_bytes, void* stream,
                  const spm_build_opts* opts);
 
@@ -209,7 +233,7 @@ int spm_agent_query_ws(const spm_scene* scene, int32_t n_agents, size_t* workspa
 int spm_agent_distance(const spm_scene* scene, const spm_out* map, int32_t n_agents, const float* d_agents_xy,
                        float* d_dist, void* stream);
 
-/* Refined map values and paths at arbitrary points (Section 6: a point near
+/* Refined map values and paths at arbitrary points (Section 5.1, Discussion: a point near
  * the border of two regions may take the wrong first turn from its own
  * pixel; comparing the parents of the neighbouring pixels at the point itself
  * removes that error).  For query point i (domain units, d_pts[2i], d_pts[2i+1]),

@@ -5,7 +5,7 @@
 // around it and keeps the one of least cost(g) + |q - x_g(q)| among those that
 // q actually sees.  A point near the border of two regions can belong to the
 // region of a neighbouring pixel; comparing the neighbours' parents at q
-// itself removes the first-turn error a pixel lookup would make (Section 6).
+// itself removes the first-turn error a pixel lookup would make (Section 5.1, Discussion).
 // If q sees none of them, every generator is compared.  Then the path is the
 // chain of parents down to a source (Section 1: one lookup, then a walk).
 //

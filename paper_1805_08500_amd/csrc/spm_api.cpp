@@ -11,6 +11,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -490,8 +491,102 @@ int spm_build_ex(const spm_scene* s, const spm_out* out, void* d_ws, size_t ws_b
   return ok();
 }
 
+}  // extern "C"
+
+namespace {
+
+// Pinned host staging for spm_build: a ring of slots, each holding one scene until the
+// copy queued from it has completed (its event), so a caller may free its host scene as
+// soon as spm_build returns and consecutive builds need not wait for each other.
+constexpr int kStageSlots = 4;
+struct StageSlot {
+  void* host = nullptr;
+  size_t cap = 0;
+  hipEvent_t ev = nullptr;
+  int dev = -1;
+  bool pending = false;
+};
+std::mutex g_stage_mu;
+StageSlot g_stage[kStageSlots];
+unsigned g_stage_next = 0;
+
+// pack the host scene into `dst` in the workspace's scene-block layout
+void pack_scene(const spm_scene* s, const Layout& L, int* dst) {
+  std::memset(dst, 0, L.scene_ints * sizeof(int));
+  if (s->n_polys > 0) std::memcpy(dst + L.sc_poly, s->poly_start, ((size_t)s->n_polys + 1) * sizeof(int));
+  if (s->n_vertices > 0) {
+    std::memcpy(dst + L.sc_vx, s->vx, (size_t)s->n_vertices * sizeof(int));
+    std::memcpy(dst + L.sc_vy, s->vy, (size_t)s->n_vertices * sizeof(int));
+  }
+  if (s->n_points > 0) std::memcpy(dst + L.sc_pts, s->pts, 2 * (size_t)s->n_points * sizeof(int));
+  if (s->n_segs > 0) std::memcpy(dst + L.sc_segs, s->segs, 4 * (size_t)s->n_segs * sizeof(int));
+}
+
+// copy the packed scene through a pinned slot into the workspace, on `st`
+int stage_scene(const spm_scene* s, const Layout& L, char* ws, hipStream_t st) {
+  const size_t bytes = L.scene_ints * sizeof(int);
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return fail(SPM_ERR_HIP, "hipGetDevice failed");
+  std::lock_guard<std::mutex> lock(g_stage_mu);
+  StageSlot& sl = g_stage[g_stage_next++ % kStageSlots];
+  if (sl.pending) {
+    if (hipEventSynchronize(sl.ev) != hipSuccess) return fail(SPM_ERR_HIP, "staging event wait failed");
+    sl.pending = false;
+  }
+  if (sl.cap < bytes) {  // grows to the largest scene seen, then stays
+    if (sl.host) (void)hipHostFree(sl.host);
+    sl.host = nullptr;
+    sl.cap = 0;
+    const size_t cap = std::max(bytes, (size_t)1 << 16);
+    if (hipHostMalloc(&sl.host, cap, hipHostMallocDefault) != hipSuccess || !sl.host)
+      return fail(SPM_ERR_HIP, "pinned staging allocation of %zu bytes failed", cap);
+    sl.cap = cap;
+  }
+  if (!sl.ev || sl.dev != dev) {
+    if (sl.ev) (void)hipEventDestroy(sl.ev);
+    sl.ev = nullptr;
+    if (hipEventCreateWithFlags(&sl.ev, hipEventDisableTiming) != hipSuccess)
+      return fail(SPM_ERR_HIP, "staging event creation failed");
+    sl.dev = dev;
+  }
+  pack_scene(s, L, (int*)sl.host);
+  if (hipMemcpyAsync(ws + L.off_scene, sl.host, bytes, hipMemcpyHostToDevice, st) != hipSuccess)
+    return fail(SPM_ERR_HIP, "scene upload failed");
+  if (hipEventRecord(sl.ev, st) != hipSuccess) return fail(SPM_ERR_HIP, "staging event record failed");
+  sl.pending = true;
+  return SPM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
 int spm_build(const spm_scene* s, const spm_out* out, void* d_ws, size_t ws_bytes, void* stream) {
-  return spm_build_ex(s, out, d_ws, ws_bytes, stream, nullptr);
+  // every check that can fail runs before any device work is queued
+  int rc = check_counts(s);
+  if (rc) return rc;
+  if ((rc = check_ptrs(s))) return rc;
+  if ((rc = check_out(out))) return rc;
+  Layout L = make_layout(s->width, s->height, s->n_polys, s->n_vertices, s->n_points, s->n_segs);
+  if (!d_ws) return fail(SPM_ERR_INVALID_ARG, "workspace is NULL");
+  if (ws_bytes < L.total) return fail(SPM_ERR_CAPACITY, "workspace has %zu bytes, needs %zu", ws_bytes, L.total);
+  if ((rc = spm_validate(s))) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(st, &cs) != hipSuccess) return fail(SPM_ERR_HIP, "hipStreamIsCapturing failed");
+  if (cs != hipStreamCaptureStatusNone)
+    return fail(SPM_ERR_INVALID_ARG, "spm_build stages a host scene and cannot be captured; capture spm_build_ex "
+                                     "with a device scene instead");
+  char* ws = (char*)d_ws;
+  if ((rc = stage_scene(s, L, ws, st))) return rc;
+  const int* sc = (const int*)(ws + L.off_scene);
+  spm_scene dev = *s;
+  dev.poly_start = sc + L.sc_poly;
+  dev.vx = sc + L.sc_vx;
+  dev.vy = sc + L.sc_vy;
+  dev.pts = sc + L.sc_pts;
+  dev.segs = sc + L.sc_segs;
+  return spm_build_ex(&dev, out, d_ws, ws_bytes, stream, nullptr);
 }
 
 int spm_batch_query_sizes(const spm_batch* b, size_t* workspace_bytes) {

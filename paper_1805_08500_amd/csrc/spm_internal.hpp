@@ -105,6 +105,9 @@ struct Layout {
   size_t off_gens, off_vis, off_sgen, off_sgcost, off_sgbb, off_inside, off_cost64, off_gxy, off_misc;
   size_t off_vsorted, off_vtx2gid, off_gorder, off_costpos, off_qctr, off_rmask, off_cmark;
   size_t off_obins, off_order;
+  // a host scene staged into the workspace (spm_build): poly_start, vx, vy, pts, segs, each at
+  // a 16-int boundary from off_scene
+  size_t off_scene, scene_ints, sc_poly, sc_vx, sc_vy, sc_pts, sc_segs;
   int ocap;   // capacity of each work class (the most tiles any tile shape gives)
   size_t total;
 };
@@ -151,6 +154,15 @@ inline Layout make_layout(int W, int H, int n_polys, int nv, int np, int ns) {
   if (tiles_of(W, H, 16) > L.ocap) L.ocap = tiles_of(W, H, 16);
   L.off_obins = take(kOrderBins * sizeof(int));
   L.off_order = take((size_t)kOrderBins * (size_t)(L.ocap > 0 ? L.ocap : 1) * sizeof(int));
+  size_t si = 0;
+  auto part = [&](size_t ints) { size_t r = si; si = align_up(si + ints, 16); return r; };
+  L.sc_poly = part((size_t)n_polys + 1);
+  L.sc_vx = part((size_t)nv);
+  L.sc_vy = part((size_t)nv);
+  L.sc_pts = part(2 * (size_t)np);
+  L.sc_segs = part(4 * (size_t)ns);
+  L.scene_ints = si;
+  L.off_scene = take(si * sizeof(int));
   L.total = o;
   return L;
 }

@@ -146,8 +146,28 @@ class Builder:
         self.samples = int(samples)
         self.walk = int(walk)
 
+    def build_host(self, scene=None, stream=None) -> Map:
+        """Queue one build through spm_build from a host scene (default: the scene this builder's device
+        scene was made from): the library validates it, stages it through pinned memory into the
+        workspace and builds from there.  The scene must have the same counts as the device scene."""
+        keep = []
+        hs = _host_scene_struct((scene if scene is not None else self.ds.scene).flat(), keep)
+        for f in ("width", "height", "n_polys", "n_vertices", "n_points", "n_segs"):
+            if getattr(hs, f) != getattr(self.ds.c, f):
+                raise ValueError(f"scene {f} {getattr(hs, f)} differs from the builder's {getattr(self.ds.c, f)}")
+        if stream is not None:
+            handle = stream.cuda_stream
+        elif self.ws.device.type == "cuda":
+            handle = torch.cuda.current_stream(self.ws.device).cuda_stream
+        else:
+            handle = 0   # not a device buffer: the library's host checks run, and no build can follow
+        C.check(C.lib().spm_build(ctypes.byref(hs), ctypes.byref(self.out), self.ws.data_ptr(), self.ws_bytes,
+                                  ctypes.c_void_p(handle)))
+        return self.map
+
     def build(self, stream=None, timer: Timer = None, stats: torch.Tensor = None) -> Map:
-        """Queue one build on `stream` (default: torch's current stream)."""
+        """Queue one build of the device scene through spm_build_ex on `stream` (default: torch's
+        current stream)."""
         if stream is None:
             stream = torch.cuda.current_stream(self.ws.device)
         opts = C.SpmBuildOpts(self.tile[0], self.tile[1], timer.h if timer is not None else None,
@@ -221,20 +241,28 @@ class SPMDistance(torch.autograd.Function):
     """D(agents) as a differentiable function of the source positions.
 
     forward(pts (n_points, 2), segs (n_segs, 4), agents (n, 2), builder): rounds the
-    source coordinates to the integer lattice the exact predicates need, writes them
-    into the builder's device scene, rebuilds the map and returns D per agent.
-    backward: gradients for pts and segs through the fixed parent chains
+    source coordinates to the integer lattice the exact predicates need (so a move of
+    less than half a unit leaves the map unchanged), rebuilds the map from the updated
+    host scene through spm_build, which validates it first (a source moved onto or into
+    an obstacle, out of the domain, or a segment made to touch an obstacle or shrink to
+    a point raises SpmError and leaves the builder's scene as it was), and returns D per
+    agent.  backward: gradients for pts and segs through the fixed parent chains
     (spm_backward); agents and builder get none.
     """
 
     @staticmethod
     def forward(ctx, pts, segs, agents, builder):
         ds = builder.ds
+        sc = ds.scene
+        new_pts = torch.round(pts.detach()).to(torch.int64).cpu().numpy().reshape(-1, 2) if ds.n_points else None
+        new_segs = torch.round(segs.detach()).to(torch.int64).cpu().numpy().reshape(-1, 4) if ds.n_segs else None
+        moved = type(sc)(sc.width, sc.height, sc.polys, new_pts, new_segs)
+        builder.build_host(moved)
+        ds.scene = moved
         if ds.n_points:
-            ds.t["pts"].copy_(torch.round(pts.detach()).to(torch.int32).reshape(-1))
+            ds.t["pts"].copy_(torch.from_numpy(np.ascontiguousarray(new_pts.reshape(-1), np.int32)))
         if ds.n_segs:
-            ds.t["segs"].copy_(torch.round(segs.detach()).to(torch.int32).reshape(-1))
-        builder.build()
+            ds.t["segs"].copy_(torch.from_numpy(np.ascontiguousarray(new_segs.reshape(-1), np.int32)))
         D = agent_distance(builder, agents)
         ctx.save_for_backward(agents)
         ctx.builder = builder

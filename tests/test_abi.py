@@ -120,6 +120,49 @@ def test_build_rejects_null_arguments_before_device_work(C):
     assert rc == C.SPM_ERR_INVALID_ARG
 
 
+def test_host_build_error_codes_before_device_work(C):
+    """spm_build takes a host scene and runs every check that can fail before any HIP call: each
+    error code below comes back with the workspace and outputs never touched (their addresses are
+    fake).  The HIP error is forced by the missing device, so that case only runs without a GPU."""
+    from paper_1805_08500_amd.spm import _host_scene_struct
+    L = C.lib()
+    fake = 4096
+    out = C.SpmOut(fake, fake, fake, fake, fake, fake, fake)
+    big = ctypes.c_size_t(1 << 40)
+
+    def rc_of(scene, ws=fake, nbytes=big, o=out):
+        keep = []
+        hs = _host_scene_struct(scene.flat(), keep)
+        return L.spm_build(ctypes.byref(hs), ctypes.byref(o) if o is not None else None,
+                           ctypes.c_void_p(ws) if ws else None, nbytes, None)
+
+    ok = Scene(40, 40, [_rect_poly(10, 10, 20, 20)], np.asarray([[2, 2]]), np.asarray([[25, 30, 35, 22]]))
+    cases = [
+        (lambda: rc_of(ok, o=None), C.SPM_ERR_INVALID_ARG, b"NULL"),
+        (lambda: rc_of(ok, o=C.SpmOut()), C.SPM_ERR_INVALID_ARG, b"NULL"),
+        (lambda: rc_of(ok, ws=0), C.SPM_ERR_INVALID_ARG, b"workspace"),
+        (lambda: rc_of(ok, nbytes=ctypes.c_size_t(100)), C.SPM_ERR_CAPACITY, b"needs"),
+        (lambda: rc_of(Scene(40, 40, [_rect_poly(10, 10, 20, 20)[::-1]], np.asarray([[2, 2]]), None)),
+         C.SPM_ERR_GEOMETRY, b"counter-clockwise"),
+        (lambda: rc_of(Scene(40, 40, [_rect_poly(10, 10, 20, 20)], np.asarray([[15, 15]]), None)),
+         C.SPM_ERR_GEOMETRY, b"inside"),
+        (lambda: rc_of(Scene(40, 40, [_rect_poly(10, 10, 20, 20)], None, np.asarray([[0, 15, 30, 15]]))),
+         C.SPM_ERR_GEOMETRY, b"meets"),
+        (lambda: rc_of(Scene(40, 40, [_rect_poly(10, 10, 50, 20)], np.asarray([[2, 2]]), None)),
+         C.SPM_ERR_RANGE, b"outside"),
+        (lambda: rc_of(Scene(40, 40, [_rect_poly(10, 10, 20, 20)], np.asarray([[2, 41]]), None)),
+         C.SPM_ERR_RANGE, b"outside"),
+        (lambda: rc_of(Scene(9000, 40, [], np.asarray([[2, 2]]), None)), C.SPM_ERR_RANGE, b"outside"),
+        (lambda: rc_of(Scene(40, 40, [_rect_poly(10, 10, 20, 20)], None, None)), C.SPM_ERR_INVALID_ARG, b"source"),
+    ]
+    for k, (call, code, what) in enumerate(cases):
+        assert call() == code, (k, L.spm_last_error())
+        assert what in L.spm_last_error(), (k, L.spm_last_error())
+    import torch
+    if not torch.cuda.is_available():
+        assert rc_of(ok) == C.SPM_ERR_HIP, L.spm_last_error()
+
+
 def test_build_rejects_bad_walk_before_device_work(C):
     """The walk option is checked on the host, before any device pointer is touched."""
     L = C.lib()
@@ -234,3 +277,36 @@ def test_build_entry_reaches_the_build_module():
     )
     r = subprocess.run([sys.executable, "-c", script], capture_output=True, text=True, timeout=240, cwd=ROOT)
     assert r.returncode == 0 and r.stdout.strip().endswith("ok"), r.stderr[-2000:]
+
+
+def test_source_update_is_validated_before_rebuilding(C):
+    """SPMDistance rebuilds through spm_build, whose host validation refuses a source moved onto or
+    into an obstacle, out of the domain, or a segment made to touch an obstacle or shrink to a
+    point; the builder keeps its scene.  (The builder here holds host buffers, which is enough to
+    reach those checks; with no GPU a valid update fails at the first HIP call instead.)"""
+    import torch
+    import paper_1805_08500_amd as spm
+    from paper_1805_08500_amd._lib import SpmError
+    scene = Scene(40, 40, [_rect_poly(10, 10, 20, 20)], np.asarray([[2, 2], [30, 5]]),
+                  np.asarray([[25, 30, 35, 22]]))
+    b = spm.Builder(spm.DeviceScene(scene, device="cpu"))
+    agents = torch.tensor([[5.5, 5.5]])
+    segs = torch.tensor([[25.0, 30.0, 35.0, 22.0]])
+    pts = torch.tensor([[2.0, 2.0], [30.0, 5.0]])
+    bad = [
+        (torch.tensor([[15.2, 14.9], [30.0, 5.0]]), segs, C.SPM_ERR_GEOMETRY),    # into the obstacle
+        (torch.tensor([[10.4, 13.0], [30.0, 5.0]]), segs, C.SPM_ERR_GEOMETRY),    # rounds onto its edge
+        (torch.tensor([[-0.7, 2.0], [30.0, 5.0]]), segs, C.SPM_ERR_RANGE),        # out of the domain
+        (pts, torch.tensor([[5.0, 15.0, 30.0, 15.0]]), C.SPM_ERR_GEOMETRY),       # segment through it
+        (pts, torch.tensor([[25.0, 30.0, 25.2, 29.9]]), C.SPM_ERR_GEOMETRY),      # segment of length 0
+    ]
+    for k, (p, s, code) in enumerate(bad):
+        with pytest.raises(SpmError) as e:
+            spm.SPMDistance.apply(p, s, agents, b)
+        assert e.value.code == code, (k, str(e.value))
+        assert np.array_equal(b.ds.scene.points, scene.points) and np.array_equal(b.ds.scene.segs, scene.segs)
+    if not torch.cuda.is_available():
+        with pytest.raises(SpmError) as e:
+            spm.SPMDistance.apply(torch.tensor([[3.2, 2.0], [30.0, 5.0]]), segs, agents, b)
+        assert e.value.code == C.SPM_ERR_HIP
+        assert np.array_equal(b.ds.scene.points, scene.points)
