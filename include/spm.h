@@ -177,6 +177,22 @@ typedef struct {
 int spm_build_ex(const spm_scene* dev_scene, const spm_out* out, void* d_ws, size_t ws_bytes, void* stream,
                  const spm_build_opts* opts);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the build
+ * of spm_build_ex with default options, using a workspace inside the library
+ * instead of d_ws -- a static device array of SPM_NOALLOC_MAX_WS bytes per
+ * GPU, held from the library's load until the process ends.  dev_scene and
+ * out are as for spm_build_ex (device memory, the scene validated
+ * beforehand); nothing is allocated and the host never waits.  Scenes whose
+ * workspace (spm_query_sizes) exceeds SPM_NOALLOC_MAX_WS fail with
+ * SPM_ERR_CAPACITY before any launch.  Every call on one GPU shares that
+ * array: calls that can overlap on one GPU (different streams without
+ * ordering, or different host threads) race and give unspecified outputs;
+ * calls ordered on one stream are safe.  Each build clears the counters it
+ * uses, so leftovers of an earlier call do not matter. */
+#define SPM_NOALLOC_MAX_WS (16u << 20)
+int spm_build_noalloc(const spm_scene* dev_scene, const spm_out* out, void* stream);
+
 /* ---------------------------------------------------------------------
  * Batched builds.  Many independent scenes are built by one launch per
  * stage; the pixel stage is a single persistent launch whose workgroups take

@@ -20,6 +20,7 @@ SPM_ERR_HIP = -5
 SPM_ERR_UNREACHABLE = -6
 SPM_N_STAGES = 8
 SPM_MAX_SIDE = 8192
+SPM_NOALLOC_MAX_WS = 16 << 20
 GEN_POINT, GEN_SEGMENT, GEN_VERTEX = 0, 1, 2
 
 STAGES = ("ingest", "edge_sort", "gorder", "genvis", "relax", "gsort", "pixel", "total")
@@ -74,6 +75,7 @@ def lib():
     L.spm_query_sizes.argtypes = [sp, P(c_i32), P(ctypes.c_size_t)]
     L.spm_build.argtypes = [sp, op, c_vp, ctypes.c_size_t, c_vp]
     L.spm_build_ex.argtypes = [sp, op, c_vp, ctypes.c_size_t, c_vp, P(SpmBuildOpts)]
+    L.spm_build_noalloc.argtypes = [sp, op, c_vp]
     L.spm_timer_create.argtypes = [P(c_vp)]
     L.spm_timer_destroy.argtypes = [c_vp]
     L.spm_timer_reset.argtypes = [c_vp]
@@ -92,7 +94,7 @@ def lib():
     L.spm_graph_capture_batch.argtypes = [bp, c_vp, ctypes.c_size_t, c_vp, P(c_vp)]
     L.spm_graph_launch.argtypes = [c_vp, c_vp]
     L.spm_graph_destroy.argtypes = [c_vp]
-    for name in ("spm_validate", "spm_query_sizes", "spm_build", "spm_build_ex", "spm_timer_create",
+    for name in ("spm_validate", "spm_query_sizes", "spm_build", "spm_build_ex", "spm_build_noalloc", "spm_timer_create",
                  "spm_timer_destroy", "spm_timer_reset", "spm_timer_elapsed", "spm_query_path",
                  "spm_batch_query_sizes", "spm_batch_prepare", "spm_build_batch", "spm_graph_capture_batch",
                  "spm_graph_launch", "spm_graph_destroy", "spm_agent_query_ws", "spm_agent_distance",

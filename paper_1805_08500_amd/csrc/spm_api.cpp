@@ -589,6 +589,53 @@ int spm_build(const spm_scene* s, const spm_out* out, void* d_ws, size_t ws_byte
   return spm_build_ex(&dev, out, d_ws, ws_bytes, stream, nullptr);
 }
 
+}  // extern "C"
+
+namespace {
+
+// Device scratch of spm_build_noalloc: one array per GPU, allocated with the
+// code object and kept until the process ends.  Host code never uses the
+// array's name as an address: each device's address comes from
+// hipGetSymbolAddress with that device current, once, and is kept per device.
+constexpr size_t kScratchBytes = (size_t)SPM_NOALLOC_MAX_WS;
+constexpr int kMaxDevices = 64;
+__device__ __align__(256) unsigned char scratch[kScratchBytes];
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+int scratch_address(void** out) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return fail(SPM_ERR_HIP, "hipGetDevice failed");
+  if (dev < 0 || dev >= kMaxDevices) return fail(SPM_ERR_HIP, "device %d beyond the %d supported", dev, kMaxDevices);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) return fail(SPM_ERR_HIP, "hipGetSymbolAddress(scratch) failed: %s", hipGetErrorString(e));
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return SPM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int spm_build_noalloc(const spm_scene* s, const spm_out* out, void* stream) {
+  int rc = check_counts(s);
+  if (rc) return rc;
+  if ((rc = check_ptrs(s))) return rc;
+  if ((rc = check_out(out))) return rc;
+  const Layout L = make_layout(s->width, s->height, s->n_polys, s->n_vertices, s->n_points, s->n_segs);
+  if (L.total > kScratchBytes)
+    return fail(SPM_ERR_CAPACITY, "scene needs %zu bytes of workspace; spm_build_noalloc holds at most %zu",
+                L.total, kScratchBytes);
+  void* ws = nullptr;
+  if ((rc = scratch_address(&ws))) return rc;
+  return spm_build_ex(s, out, ws, kScratchBytes, stream, nullptr);
+}
+
 int spm_batch_query_sizes(const spm_batch* b, size_t* workspace_bytes) {
   BatchLayout B;
   int rc = batch_layout(b, B);

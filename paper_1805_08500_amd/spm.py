@@ -165,6 +165,15 @@ class Builder:
                                   ctypes.c_void_p(handle)))
         return self.map
 
+    def build_noalloc(self, stream=None) -> Map:
+        """Queue one build of the device scene through spm_build_noalloc: the library's static device
+        workspace instead of this builder's (nothing is allocated; calls on one GPU share it)."""
+        if stream is None:
+            stream = torch.cuda.current_stream(self.ws.device)
+        C.check(C.lib().spm_build_noalloc(ctypes.byref(self.ds.c), ctypes.byref(self.out),
+                                          ctypes.c_void_p(stream.cuda_stream)))
+        return self.map
+
     def build(self, stream=None, timer: Timer = None, stats: torch.Tensor = None) -> Map:
         """Queue one build of the device scene through spm_build_ex on `stream` (default: torch's
         current stream)."""
