@@ -148,7 +148,7 @@ int spm_timer_elapsed(spm_timer* t, float* ms /* [SPM_N_STAGES] */, int32_t* n_b
  * -1 = none).  walk selects how a tile goes through the generators: 0 = by
  * the scene's largest possible generator count G (np + ns + nv); 1 = in order
  * of a lower bound over the tile, every estimate in registers (G <= 512);
- * 2 = the same with the least estimates cached and refilled (G <= 4096);
+ * 2 = the same with the least estimates cached and refilled (G <= 8192);
  * 3 = seed searches, then (cost, id) order.  A forced walk that does not fit
  * G fails with SPM_ERR_INVALID_ARG.  strip, samples and walk change speed
  * only, never an output bit.

@@ -132,13 +132,17 @@ constexpr int kSeedWide = SPM_SEED_WIDE;   // candidates per round once a seed s
 // from the scene's largest possible generator count):
 //   kWalkCached  up to kEstCache * 64 generators: lower-bound order, every
 //                estimate in registers;
-//   kWalkRefill  up to kEstWalkMax: lower-bound order, the least kEstCache
-//                per lane in registers, refilled when needed;
+//   kWalkRefill  up to kEstWalkMax (8192): lower-bound order, the least
+//                kEstCache per lane in registers, refilled when needed;
 //   kWalkCost    beyond: seed searches, then (cost, id) order.
 enum { kWalkCached = 0, kWalkRefill = 1, kWalkCost = 2 };
-constexpr int kEstWalkMax = 64 * 64;
+constexpr int kEstWalkMax = 128 * 64;   // a lane owns up to 128 generators (two 64-bit taken masks)
+#ifndef SPM_REFILL_AUTO_MAX
+#define SPM_REFILL_AUTO_MAX 4096
+#endif
+constexpr int kRefillAutoMax = SPM_REFILL_AUTO_MAX;   // largest generator count that picks it by default
 inline int walk_mode(int gmax) {
-  return gmax <= kEstCache * 64 ? kWalkCached : (gmax <= kEstWalkMax ? kWalkRefill : kWalkCost);
+  return gmax <= kEstCache * 64 ? kWalkCached : (gmax <= kRefillAutoMax ? kWalkRefill : kWalkCost);
 }
 #ifndef SPM_SEED_SHARE
 #define SPM_SEED_SHARE 1   // later seed searches of a tile skip the candidates earlier ones tried
@@ -603,17 +607,18 @@ __device__ __forceinline__ int tile_work(int tile, int W, int H, int W32, int G,
       const int nj = lane < G ? (G - lane + 63) / 64 : 0;   // generators this lane owns
       float ec[kEstCache];
       int ej[kEstCache];
-      u64 taken = 0;        // per lane: the j already taken out
+      u64 taken0 = 0, taken1 = 0;   // per lane: the j already taken out (j < 64, j >= 64)
+      auto is_taken = [&](int j) -> bool { return ((j < 64 ? taken0 : taken1) >> (j & 63)) & 1ull; };
       float T = INFINITY;   // least estimate left out of the caches (wave-uniform)
       auto refill = [&]() {
         float tl = INFINITY;
 #pragma unroll
         for (int q = 0; q < kEstCache; ++q) {
-          ec[q] = (q < nj && !((taken >> q) & 1ull)) ? est_box(lane + 64 * q) : INFINITY;
+          ec[q] = (q < nj && !((taken0 >> q) & 1ull)) ? est_box(lane + 64 * q) : INFINITY;
           ej[q] = q;
         }
         for (int j = kEstCache; j < nj; ++j) {
-          if ((taken >> j) & 1ull) continue;
+          if (is_taken(j)) continue;
           const float v = est_box(lane + 64 * j);
           float mx = ec[0];
           int ms = 0;
@@ -653,7 +658,8 @@ __device__ __forceinline__ int tile_work(int tile, int W, int H, int W32, int G,
         for (int q = 1; q < kEstCache; ++q)
           if (q == bs) jq = ej[q];
         if (lane == wl) {
-          taken |= 1ull << jq;
+          if (jq < 64) taken0 |= 1ull << jq;
+          else taken1 |= 1ull << (jq - 64);
 #pragma unroll
           for (int q = 0; q < kEstCache; ++q)
             if (q == bs) ec[q] = INFINITY;

@@ -474,9 +474,9 @@ int spm_build_ex(const spm_scene* s, const spm_out* out, void* d_ws, size_t ws_b
     return fail(SPM_ERR_INVALID_ARG, "samples %d below -1", opts->samples);
   if (opts && (opts->walk < 0 || opts->walk > 3))
     return fail(SPM_ERR_INVALID_ARG, "walk %d outside 0..3", opts->walk);
-  if (opts && ((opts->walk == 1 && L.Gmax > 512) || (opts->walk == 2 && L.Gmax > 4096)))
+  if (opts && ((opts->walk == 1 && L.Gmax > 512) || (opts->walk == 2 && L.Gmax > 8192)))
     return fail(SPM_ERR_INVALID_ARG, "walk %d needs at most %d generators (scene has up to %d)", opts->walk,
-                opts->walk == 1 ? 512 : 4096, L.Gmax);
+                opts->walk == 1 ? 512 : 8192, L.Gmax);
   SingleSrc src;
   fill_dev(src.d, s, out, (char*)d_ws, L, tw, opts ? (u64*)opts->d_stats : nullptr);
   if (opts && opts->strip) src.d.strip = opts->strip;

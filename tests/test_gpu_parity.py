@@ -115,7 +115,7 @@ def test_tile_shapes_bitwise(spm, tile):
 
 
 @pytest.mark.parametrize("make,walks", [(lambda: config2(1), (1, 2, 3)), (lambda: profiling_grid(20, seed=2), (2, 3)),
-                                        (lambda: random_small(5), (1, 2, 3))])
+                                        (lambda: random_small(5), (1, 2, 3)), (lambda: config3(1), (2, 3))])
 def test_walk_modes_bitwise(spm, make, walks):
     """Every walk of the pixel stage gives the same map bit for bit (the (value, position) order decides)."""
     import torch
@@ -153,8 +153,10 @@ def test_edge_cases(oracle_mod, spm):
         ("pixel-on-segment", Scene(20, 20, [_rect_poly(12, 12, 16, 16)], None, np.asarray([[0, 0, 10, 10]]))),
         ("diagonal-edge", Scene(24, 24, [np.asarray([(4, 4), (14, 4), (14, 14)])], np.asarray([[20, 2]]), None)),
     ]
+    # the strip behind its block is a near-tie almost everywhere: the routes above and below are mirror images
+    bound = {"thin-strip": 0.2}
     for name, sc in cases:
-        _full(oracle_mod, spm, sc, name, max_ambiguous=0.15)
+        _full(oracle_mod, spm, sc, name, max_ambiguous=bound.get(name, 0.05))
 
 
 def test_max_side_sampled(oracle_mod, spm):
