@@ -1,23 +1,27 @@
 """Benchmark: shortest-path-map builds on one MI355X.
 
-One step = one complete spm_build (device ingest, generator visibility,
-relaxation, cost sort, inside mask and pixel propagation) of the 1024 x 1024
-scene with 60 convex obstacles, 3 point sources and 2 segment sources, with
-the scene already resident in device memory.
+One step = one complete build (spm_build_ex: device ingest, generator
+visibility, relaxation, cost sort, inside mask, pixel propagation) of the
+headline workload, the 2048 x 2048 maze (randomized-DFS 64 x 64 cells of 32 px
+with 4 px walls, 4 exit segment sources, seed 1), with the scene already
+resident in device memory.  --workload convex1024 selects the 1024 x 1024
+scene with 60 convex obstacles instead.
 
 value = W * H * G / t_step / 1e6  (Mpixel*generator/s; G = point sources +
 segment sources + corner generators, the dense pair count the paper's method
 shades).
 
-Prints one JSON line.  roofline.achieved = the pixel kernel's algorithmic
-lane-ops per launch / its average launch time, against 256 CUs x 4 SIMDs x
-16 lanes x 2.4 GHz.  Algorithmic work per unit (what the method computes,
-not what culling avoids): 8 lane-ops per pixel-generator pair (the cone
-bound of every pair), 20 more per pixel-segment pair (the closest point),
-8 per accepted candidate and 9 per examined lane-edge visibility test; the
-last two counted by one instrumented build outside the timed region.
-executed_ops_frac gives the same ratio for the operations the kernel
-actually executes after culling.
+Prints one JSON line.  roofline: the pixel kernel (the dominant one), bound by
+32-bit VALU issue.  achieved = the algorithmic lane-ops of one launch / its
+average launch time (HIP events on the build stream, over the timed builds);
+the algorithmic work is counted in the method's own units by one instrumented
+build outside the timed region: 8 lane-ops per pixel-generator bound test
+(the cone bound of Procedure 3), 8 per accepted candidate (square root, add,
+compare, select), 9 per examined lane-edge visibility test (orientations and
+compares) and 20 per pixel-segment closest point (Section 4).  peak = 256 CUs
+x 4 SIMDs x 16 lanes x 2.4 GHz.  The issue counters of the same kernel
+(VALU busy, lane utilisation, executed lane-op rate) come from the committed
+rocprofv3 summary while the kernel source is unchanged since it was taken.
 """
 from __future__ import annotations
 
@@ -25,6 +29,7 @@ import argparse
 import hashlib
 import json
 import os
+import statistics
 import sys
 import time
 
@@ -33,21 +38,21 @@ sys.path.insert(0, ROOT)
 
 METRIC = "SPM build Mpixel·gen/s + % VALU roofline; batched & backward vs plain"
 PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9      # CUs x SIMDs x lanes x clock: one 32-bit VALU op per lane per cycle
-# arithmetic lane-ops per counted unit of the instrumented pixel kernel
-# algorithmic lane-ops per unit of the method
+# algorithmic lane-ops per unit of the method (counted by the instrumented pixel kernel)
 ALG = {
-    "pair": 8,          # per (pixel, generator): the cone bound cost + |p - g| against the current value
-    "segment_pair": 20, # per (pixel, segment source): the clamped closest point
-    "accept": 8,        # per accepted candidate: square root, add, compare, select
-    "lane_edge": 9,     # per examined (pixel, generator, edge): orientations and compares
+    "bound": 8,          # per (pixel, generator) bound test: cost + |p - g| against the pixel's value
+    "accept": 8,         # per accepted candidate: square root, add, compare, select
+    "lane_edge": 9,      # per examined (pixel, generator, edge) visibility test
+    "segment": 20,       # per (pixel, segment source) closest point q*
 }
-# lane-ops per unit of what the culled kernel executes (instrumented counters)
-OPS = {
-    "tile_bound": 12,    # per generator per tile: box gap (4 sub/max), squares, sqrt, scale, add, compare
-    "lane_bound": 9,     # per (pixel, generator): 2 sub, mul+mad, sub, cvt, 2 mul, compare
-    "relevance": 30,     # per (tile, edge): facing test, box ranges of 3 affine forms, compares
-    "lane_edge": 12,     # per (pixel, generator, edge): 4 mad (two orientations), 2 med3, mul, 2 mad, 3 compares
-    "accept": 4,         # per accepted candidate: cvt, sqrt, mad, compare
+# instrumented counters (spm_build_opts.d_stats order)
+STAT_NAMES = ["tiles", "walk_steps", "lane_bound", "wave_vis", "relevance", "lane_edge", "one_edge_hides", "accept",
+              "occ_cache_tests", "occ_cache_hits", "segment_lanes"]
+WORKLOADS = {
+    "maze2048": "maze-2048: 2048x2048 grid, randomized-DFS maze of 64x64 cells (32 px, 4 px walls, exact union "
+                "boundary), 4 exit segment sources on the outer boundary, seed %d",
+    "convex1024": "convex-1024: 1024x1024 grid, 60 convex hulls (6-10 seeded points in 20-80 px boxes), 3 point "
+                  "sources, 2 segment sources, seed %d",
 }
 
 
@@ -57,10 +62,12 @@ def _parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--seed", type=int, default=1)
+    ap.add_argument("--workload", choices=sorted(WORKLOADS), default="maze2048")
     ap.add_argument("--tile", default="8x8")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-extras", action="store_true", help="skip the batched and backward figures")
-    ap.add_argument("--cpu-pixels", type=int, default=1 << 20, help="oracle pixel sample for the CPU baseline")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the secondary workload, the batched and backward figures and the host-scene build")
+    ap.add_argument("--cpu-pixels", type=int, default=2048, help="oracle pixel sample per CPU-baseline run")
     ap.add_argument("--sweep", type=int, default=0, metavar="SOURCES",
                     help="only run the Profiling-style sweep (k x k squares on 1000^2, k in 2..20) with this many "
                          "random single sources per map, print its JSON line and exit")
@@ -74,48 +81,109 @@ def _file_hash(path):
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def _traffic(kernel_src_hash):
-    """HBM bytes per k_pixel launch from the committed rocprofv3 counter summary, if the
-    kernel source has not changed since the counters were taken."""
-    p = os.path.join(ROOT, "profiles", "k_pixel_convex1024_traffic.json")
+def _profile(name, kernel_src_hash):
+    """A committed rocprofv3 summary (profiles/<name>.json), if the pixel kernel's source is the one it was
+    taken with; else None."""
+    p = os.path.join(ROOT, "profiles", name + ".json")
     if not os.path.exists(p):
         return None
     with open(p) as f:
         t = json.load(f)
-    if t.get("source_hash") != kernel_src_hash:
-        return None
-    return t.get("bytes_per_launch")
+    return t if t.get("source_hash") == kernel_src_hash else None
 
 
-def _cpu_baseline(scene, G, npix):
+def _scene(workload, seed):
+    from scenegen import config2, config3
+    return config3(seed) if workload == "maze2048" else config2(seed)
+
+
+def _time_builds(spm, torch, b, steps, warmup):
+    stream = torch.cuda.current_stream()
+    for _ in range(warmup):
+        b.build(stream)
+    torch.cuda.synchronize()
+    timer = spm.Timer()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        b.build(stream, timer=timer)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    stages, nb = timer.elapsed()
+    return (t1 - t0) * 1e3 / steps, {k: v / max(nb, 1) for k, v in stages.items()}
+
+
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _cpu_baseline(scene, G, npix, gpu_map):
+    """The oracle (plain C, OpenMP) on the host cores: generator costs over the whole scene plus a seeded pixel
+    sample, extrapolated to all pixels; median of 3 runs on every thread, one run on 1 thread with a smaller
+    sample.  The GPU map is compared with the oracle on the first sample (parity on the bench's own workload)."""
     import numpy as np
     from oracle import oracle as O
     O.build()
     threads = O.max_threads()
-    t0 = time.perf_counter()
-    cost, _ = O.costs(scene, nthreads=threads)
-    t1 = time.perf_counter()
-    rng = np.random.default_rng(123)
-    WH0 = scene.width * scene.height
-    pix = np.arange(WH0, dtype=np.int64) if npix >= WH0 else np.unique(rng.integers(0, WH0, npix))
-    t2 = time.perf_counter()
-    O.pixels(scene, cost, pix, nthreads=threads)
-    t3 = time.perf_counter()
     WH = scene.width * scene.height
-    t_full = (t1 - t0) + (t3 - t2) * WH / len(pix)
+
+    def run(nthreads, n, seed):
+        rng = np.random.default_rng(seed)
+        pix = np.unique(rng.integers(0, WH, n))
+        t0 = time.perf_counter()
+        cost, _ = O.costs(scene, nthreads=nthreads)
+        t1 = time.perf_counter()
+        r = O.pixels(scene, cost, pix, nthreads=nthreads)
+        t2 = time.perf_counter()
+        return (t1 - t0) + (t2 - t1) * WH / len(pix), t1 - t0, t2 - t1, pix, r
+
+    runs = [run(threads, npix, 100 + k) for k in range(3)]
+    t_all = statistics.median(r[0] for r in runs)
+    one = run(1, max(64, npix // 8), 200)
+    pix, r = runs[0][3], runs[0][4]
+    d = gpu_map["dist"].reshape(-1)[pix].astype(np.float64)
+    p = gpu_map["parent"].reshape(-1)[pix]
+    D = r["dist64"]
+    fin = np.isfinite(D)
+    with np.errstate(invalid="ignore"):
+        amb = fin & ((r["second"] - D) <= 1e-5 * D + 1e-6)
+    rel = np.abs(d[fin] - D[fin]) / np.maximum(D[fin], 1e-30)
+    parity = {"pixels": int(len(pix)), "free": int(fin.sum()),
+              "finite_masks_equal": bool(np.array_equal(np.isfinite(d), fin)),
+              "max_rel_err": float(rel.max()) if rel.size else 0.0,
+              "parent_differs_clear": int((fin & ~amb & (p != r["parent"])).sum()),
+              "parent_differs_near_tie": int((amb & (p != r["parent"])).sum()),
+              "ambiguous_frac": float(amb.sum()) / max(1, int(fin.sum()))}
     return {
-        "value": WH * G / t_full / 1e6, "unit": "Mpixel·gen/s", "cores": int(threads), "kind": "oracle",
-        "sample": (f"generator costs ({t1 - t0:.2f} s) + {len(pix)} of {WH} pixels ({t3 - t2:.2f} s) of the same "
-                   f"scene" + ("" if len(pix) == WH else ", extrapolated to all pixels")),
+        "value": WH * G / t_all / 1e6, "unit": "Mpixel·gen/s", "cores": int(threads), "kind": "oracle",
+        "sample": (f"median of 3 runs, each: generator costs of the whole scene + {npix} random pixels (seeds 100-102) "
+                   f"extrapolated to all {WH} pixels; {threads} OpenMP threads"),
+        "cpu_model": _cpu_model(), "host_cpus": os.cpu_count(),
+        "seconds_per_run": [round(x[0], 3) for x in runs],
+        "costs_s": round(statistics.median(x[1] for x in runs), 4),
+        "one_thread": {"value": WH * G / one[0] / 1e6, "costs_s": round(one[1], 3),
+                       "sample": f"{len(one[3])} random pixels, extrapolated"},
+        "parity_on_sample": parity,
     }
 
 
 def _batched(spm, torch, reps=10):
-    """256 mixed scenes (sides 128-1024, 4-80 hulls, 1-5 points, 0-3 segments), one hipGraph replay
-    per batched build.  Throughput = sum over scenes of W * H * G / t."""
+    """256 mixed scenes (sides 128-1024, 4-80 hulls, 1-5 points, 0-3 segments), one hipGraph replay per batched
+    build.  Throughput = sum over scenes of W * H * G / t."""
     from scenegen import config4_list
     scenes = config4_list()
-    bb = spm.BatchBuilder(scenes, check=False)
+    from paper_1805_08500_amd import autotune
+    t0 = time.perf_counter()
+    tiles = autotune.tune(scenes, cache_path=None)
+    tune_s = time.perf_counter() - t0
+    bb = spm.BatchBuilder(scenes, check=False, tile_w=tiles)
     s = torch.cuda.Stream()
     with torch.cuda.stream(s):
         bb.build(s)
@@ -134,13 +202,16 @@ def _batched(spm, torch, reps=10):
     ms = e0.elapsed_time(e1) / reps
     return {"workload": "256 scenes, sides in {128,256,512,1024}, 4-80 convex hulls, 1-5 points, 0-3 segments, "
                         "seed 7; one hipGraph replay per build",
+            "tiles": {str(k): v for k, v in tiles.items()}, "tuning_s": round(tune_s, 2),
             "scenes": len(scenes), "pixels": int(sum(x.width * x.height for x in scenes)), "pairs": pairs,
             "ms_per_batch": ms, "value": pairs / (ms * 1e-3) / 1e6, "unit": "Mpixel·gen/s"}
 
 
-def _backward(spm, torch, b, scene, reps=20):
-    """4096 agents on the plain workload: map rebuild + agent distances (forward) and the adjoint."""
-    from scenegen import config5_agents
+def _backward(spm, torch, reps=20):
+    """4096 agents on the 1024 x 1024 convex-hull scene: map rebuild + agent distances (forward) and the adjoint."""
+    from scenegen import config2, config5_agents
+    scene = config2(1)
+    b = spm.Builder(spm.DeviceScene(scene, "cuda:0"))
     A = torch.from_numpy(config5_agents(scene, 4096, seed=11)).cuda()
     w = torch.full((A.shape[0],), 1.0 / A.shape[0], device="cuda")
     for _ in range(3):
@@ -164,6 +235,21 @@ def _backward(spm, torch, b, scene, reps=20):
             "backward_agents_per_s": A.shape[0] / (bwd * 1e-3)}
 
 
+def _host_scene(spm, torch, b, scene, reps=10):
+    """spm_build from the host scene (validation, pinned staging, upload, build): the rate with the PCIe copy and
+    the host checks inside the timed region (never the headline value)."""
+    for _ in range(2):
+        b.build_host(scene)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        b.build_host(scene)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / reps
+    G = int(b.map.n_gen.item())
+    return {"ms_per_build": ms, "value": scene.width * scene.height * G / (ms * 1e-3) / 1e6, "unit": "Mpixel·gen/s"}
+
+
 # The paper's own timings of its Profiling maps (Table 1: polygons, computation seconds; GTX 970),
 # quoted as context next to the sweep, never as a target.
 PAPER_PROFILING = {2: (4, 0.0014), 4: (16, 0.0054), 6: (36, 0.0456), 8: (64, 0.1251), 10: (100, 0.2701),
@@ -171,8 +257,8 @@ PAPER_PROFILING = {2: (4, 0.0014), 4: (16, 0.0054), 6: (36, 0.0456), 8: (64, 0.1
 
 
 def _sweep(n_sources):
-    """Profiling-style maps: 1000 x 1000, k x k rows of squares (each half its cell's width), one random
-    free source per build, n_sources builds per map.  Reports the mean whole-build time per map."""
+    """Profiling-style maps: 1000 x 1000, k x k rows of squares (each half its cell's width), one random free
+    source per build, n_sources builds per map.  Reports the mean whole-build time per map."""
     import torch
 
     import paper_1805_08500_amd as spm
@@ -197,9 +283,24 @@ def _sweep(n_sources):
                      "ms_per_build": ms, "pixel_ms": stages["pixel"] / max(nb, 1),
                      "Mpixel_gen_per_s": 1e6 * (sum(G) / len(G)) / (ms * 1e-3) / 1e6,
                      "paper_comp_s_gtx970": paper_s})
+        print(json.dumps({"sweep_row": rows[-1]}), file=sys.stderr, flush=True)
         del builders
     return {"sweep": "profiling-style maps, 1000x1000, k x k squares, %d random single sources each" % n_sources,
             "rows": rows}
+
+
+def _measure(spm, torch, np, workload, seed, tile, steps, warmup):
+    tw, th = (int(x) for x in tile.split("x"))
+    scene = _scene(workload, seed)
+    b = spm.Builder(spm.DeviceScene(scene, "cuda:0"), tile=(tw, th))
+    ms_step, stage_avg = _time_builds(spm, torch, b, steps, warmup)
+    G = int(b.map.n_gen.item())
+    # one instrumented build (outside the timed region) for the work counts
+    stats = torch.zeros(16, dtype=torch.int64, device="cuda:0")
+    b.build(torch.cuda.current_stream(), stats=stats)
+    torch.cuda.synchronize()
+    s = stats.cpu().numpy().astype(np.float64)
+    return scene, b, G, ms_step, stage_avg, {k: int(v) for k, v in zip(STAT_NAMES, s)}
 
 
 def main():
@@ -225,46 +326,22 @@ def main():
     import torch
 
     import paper_1805_08500_amd as spm
-    from scenegen import config2
 
-    tw, th = (int(x) for x in args.tile.split("x"))
-    scene = config2(args.seed)
-    ds = spm.DeviceScene(scene, "cuda:0")
-    b = spm.Builder(ds, tile=(tw, th))
-    stream = torch.cuda.current_stream()
-    for _ in range(args.warmup):
-        b.build(stream)
-    torch.cuda.synchronize()
-    G = int(b.map.n_gen.item())
+    scene, b, G, ms_step, stage_avg, counts = _measure(spm, torch, np, args.workload, args.seed, args.tile,
+                                                       args.steps, args.warmup)
     W, H = scene.width, scene.height
-
-    # timed region: exactly K whole builds
-    timer = spm.Timer()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        b.build(stream, timer=timer)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    stages, nb = timer.elapsed()
-    ms_step = (t1 - t0) * 1e3 / args.steps
-    stage_avg = {k: v / max(nb, 1) for k, v in stages.items()}
-
-    # one instrumented build (outside the timed region) for the work counts
-    stats = torch.zeros(8, dtype=torch.int64, device="cuda:0")
-    b.build(stream, stats=stats)
-    torch.cuda.synchronize()
-    s = stats.cpu().numpy().astype(np.float64)
-    executed = (s[1] * 64 * OPS["tile_bound"] + s[2] * OPS["lane_bound"] + s[4] * 64 * OPS["relevance"]
-                + s[5] * OPS["lane_edge"] + s[7] * OPS["accept"])
-    n_segs = 0 if scene.segs is None else len(scene.segs)
-    ops = (W * H * G * ALG["pair"] + W * H * n_segs * ALG["segment_pair"] + s[7] * ALG["accept"]
-           + s[5] * ALG["lane_edge"])
+    ops = (counts["lane_bound"] * ALG["bound"] + counts["accept"] * ALG["accept"]
+           + counts["lane_edge"] * ALG["lane_edge"] + counts["segment_lanes"] * ALG["segment"])
     t_pix = stage_avg["pixel"] * 1e-3
     achieved = ops / t_pix / 1e12
     peak = PEAK_LANE_OPS / 1e12
     src_hash = _file_hash(os.path.join(ROOT, "paper_1805_08500_amd", "csrc", "k_pixel.hip"))
-
+    prof = _profile("k_pixel_%s_counters" % args.workload, src_hash)
+    traffic = None
+    counters = None
+    if prof:
+        traffic = prof.get("hbm_bytes_per_launch")
+        counters = prof.get("derived")
     pairs = W * H * G
     out = {
         "metric": METRIC,
@@ -279,24 +356,35 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "convex-1024: 1024x1024 grid, 60 convex hulls (6-10 seeded points in 20-80 px "
-                               "boxes), 3 point sources, 2 segment sources, seed %d" % args.seed,
-                   "W": W, "H": H, "G": G, "E": scene.n_vertices, "tile": args.tile},
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TOP/s",
-                     "frac": achieved / peak, "traffic": _traffic(src_hash), "kernel": "k_pixel",
-                     "executed_ops_frac": executed / t_pix / 1e12 / peak,
-                     "ops_per_launch": ops},
+        "config": {"workload": WORKLOADS[args.workload] % args.seed, "W": W, "H": H, "G": G,
+                   "E": scene.n_vertices, "tile": args.tile},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TOP/s", "frac": achieved / peak,
+                     "traffic": traffic, "kernel": "k_pixel",
+                     "algorithmic_lane_ops_per_launch": ops,
+                     "ops_per_unit": ALG,
+                     "units_per_launch": {"bound": counts["lane_bound"], "accept": counts["accept"],
+                                          "lane_edge": counts["lane_edge"], "segment": counts["segment_lanes"]},
+                     "k_pixel_ms": stage_avg["pixel"],
+                     "counters": counters},
         "stages_ms": stage_avg,
         "k_pixel_Mpixel_gen_per_s": pairs / t_pix / 1e6,
-        "work_counts": {k: int(v) for k, v in zip(
-            ["tiles", "gen_batches", "lane_bound", "wave_vis", "relevance", "lane_edge", "occluded", "accept"], s)},
+        "work_counts": counts,
         "k_pixel_source_hash": src_hash,
     }
     if not args.no_extras:
+        other = "convex1024" if args.workload == "maze2048" else "maze2048"
+        sc2, b2, G2, ms2, st2, c2 = _measure(spm, torch, np, other, args.seed, args.tile, args.steps, args.warmup)
+        out["secondary"] = {"workload": WORKLOADS[other] % args.seed, "ms_per_step": ms2, "G": G2,
+                            "value": sc2.width * sc2.height * G2 / (ms2 * 1e-3) / 1e6, "unit": "Mpixel·gen/s",
+                            "stages_ms": st2}
+        del b2
+        out["host_scene_build"] = _host_scene(spm, torch, b, scene)
         out["batched"] = _batched(spm, torch)
-        out["backward"] = _backward(spm, torch, b, scene)
+        out["backward"] = _backward(spm, torch)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = _cpu_baseline(scene, G, args.cpu_pixels)
+        b.build()
+        torch.cuda.synchronize()
+        out["cpu_baseline"] = _cpu_baseline(scene, G, args.cpu_pixels, b.map.host())
     print(json.dumps(out), flush=True)
 
 

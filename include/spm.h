@@ -149,15 +149,21 @@ int spm_timer_elapsed(spm_timer* t, float* ms /* [SPM_N_STAGES] */, int32_t* n_b
  * the scene's largest possible generator count G (np + ns + nv); 1 = in order
  * of a lower bound over the tile, every estimate in registers (G <= 512);
  * 2 = the same with the least estimates cached and refilled (G <= 8192);
- * 3 = seed searches, then (cost, id) order.  A forced walk that does not fit
+ * 3 = seed searches, then (cost, id) order; 4 = spatial clusters of 8
+ * generators in order of a lower bound over the tile, a cluster that one edge
+ * hides from the whole tile skipped at once (G <= 8192).  A forced walk that does not fit
  * G fails with SPM_ERR_INVALID_ARG.  strip, samples and walk change speed
  * only, never an output bit.
  * d_stats, when not NULL, selects the instrumented pixel kernel, which adds
- * its work counters (unsigned 64-bit: [0] tiles, [1] batches of 64
- * lane-parallel generator bound or seed-search tests, [2] lane bound tests,
- * [3] wave visibility tests, [4] edge relevance or seed-search edge tests (x64
- * lanes), [5] lane edge tests, [6] occluded tiles, [7] accepted candidates) to
- * the 8 device counters. */
+ * its work counters to SPM_N_STATS unsigned 64-bit device counters: [0]
+ * tiles, [1] generators taken by the lower-bound walk or batches of 64
+ * lane-parallel bound / seed-search tests, [2] lane bound tests, [3] wave
+ * visibility tests, [4] edge relevance or seed-search edge tests (x64 lanes),
+ * [5] lane edge tests, [6] tests ended by one edge hiding the whole tile, [7]
+ * accepted candidates, [8] occluder-cache tests, [9] occluder-cache hits,
+ * [10] lane closest-point computations for segment sources; the rest stay
+ * zero. */
+#define SPM_N_STATS 16
 typedef struct {
   int32_t tile_w, tile_h;
   spm_timer* timer;

@@ -21,6 +21,7 @@ SPM_ERR_UNREACHABLE = -6
 SPM_N_STAGES = 8
 SPM_MAX_SIDE = 8192
 SPM_NOALLOC_MAX_WS = 16 << 20
+SPM_N_STATS = 16
 GEN_POINT, GEN_SEGMENT, GEN_VERTEX = 0, 1, 2
 
 STAGES = ("ingest", "edge_sort", "gorder", "genvis", "relax", "gsort", "pixel", "total")

@@ -713,6 +713,7 @@ __device__ __forceinline__ void gsort_wave(const S& src, int wid) {
     d.sgcost[rank] = cf;
     d.sgbb[rank] = make_int4(min(r.x, r.x2), min(r.y, r.y2), max(r.x, r.x2), max(r.y, r.y2));
   }
+  if (lane == 0) d.krank[g] = cf < INFINITY ? rank : -1;
 }
 
 // The generator sort and the parents in one launch: the first nsort

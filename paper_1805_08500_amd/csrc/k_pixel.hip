@@ -27,7 +27,137 @@
 
 namespace spm {
 
-enum { ST_TILES = 0, ST_BATCHES, ST_BOUND, ST_VISWAVE, ST_RELEV, ST_LANEEDGE, ST_OCCL, ST_ACCEPT };
+enum { ST_TILES = 0, ST_BATCHES, ST_BOUND, ST_VISWAVE, ST_RELEV, ST_LANEEDGE, ST_OCCL, ST_ACCEPT, ST_CACHE_TEST,
+       ST_CACHE_HIT, ST_SEG_LANE, ST_COUNT };
+
+// Occluder cache of one tile: one obstacle edge per lane.  The exact test of
+// a candidate generator g against a tile first asks whether a single edge hides
+// the whole tile box from g (every segment from the box to g properly crosses
+// it, the box strictly on its obstacle side: Procedure 2's shadow of that edge
+// covers the tile).  Every lane tries its own edge, so one pass tries 64
+// occluders; an edge that the full test finds hiding the box takes the next
+// slot (round robin).  Candidates that a tile cannot see are mostly hidden by
+// the walls around the tile or around the generator, the same few edges over
+// and over, so most tests end here.  A hit is exact (the same test the full
+// scan applies to every edge); a miss only falls back to the full test.
+struct OccCache {
+  unsigned w, v;   // this lane's edge w -> v (obstacle on the left), x | y << 16 (doubled coordinates
+                   // are below 2^15); w == v: an empty slot
+  int slot;        // next slot to fill (wave-uniform)
+  __device__ __forceinline__ void reset() {
+    w = v = 0u;
+    slot = 0;
+  }
+  // does some cached edge hide the box (bx0..by1) from g?
+  __device__ __forceinline__ bool hides(int gx, int gy, int bx0, int by0, int bx1, int by1) const {
+    const int wx = (int)(w & 0xffffu), wy = (int)(w >> 16), vx = (int)(v & 0xffffu), vy = (int)(v >> 16);
+    EdgeRec r;
+    r.wx = wx; r.wy = wy; r.vx = vx; r.vy = vy;
+    r.a = wy - vy;
+    r.b = vx - wx;
+    r.c = -(r.a * wx + r.b * wy);
+    r.nc = -r.c;
+    bool rel, occ;
+    edge_vs_cone(r, gx, gy, bx0, by0, bx1, by1, bx0 - gx, bx1 - gx, by0 - gy, by1 - gy, rel, occ);
+    return ballot(occ) != 0ull;
+  }
+  __device__ __forceinline__ void insert(const EdgeRec& r) {   // r wave-uniform
+    if (lane_id() == (slot & 63)) {
+      w = (unsigned)r.wx | ((unsigned)r.wy << 16);
+      v = (unsigned)r.vx | ((unsigned)r.vy << 16);
+    }
+    ++slot;
+  }
+  // Fills the slots with edges near the box (bx0..by1) whose line has the
+  // whole box strictly on its obstacle side (only such an edge can hide the
+  // box from anything): the edges of the chunks within 32, then 128 units of
+  // the box, until every slot is taken.  The walls around a tile hide most of
+  // what it cannot see, so the cache starts warm.
+  template <class GEO>
+  __device__ void fill_near(const GEO& geo, int bx0, int by0, int bx1, int by1) {
+    const int lane = lane_id();
+    for (int cb = 0; cb < geo.NC && slot < 64; cb += kWave) {
+      const int ci = cb + lane;
+      int gap = 1 << 30;
+      if (ci < geo.NC) {
+        const int4 bb = geo.chunk(ci);
+        gap = max(max(max(bb.x - bx1, bx0 - bb.z), max(bb.y - by1, by0 - bb.w)), 0);
+      }
+      const u64 near = ballot(gap <= 64), mid = ballot(gap > 64 && gap <= 256);
+      for (int cl = 0; cl < 2 && slot < 64; ++cl) {
+        u64 cm = cl ? mid : near;
+        while (cm && slot < 64) {
+          const int chunk = cb + first_bit(cm);
+          cm &= cm - 1;
+          const int e = chunk * kChunk + lane;
+          bool ok = false;
+          EdgeRec r = {0, 0, 0, 0, 0, 0, 0, 0};
+          if (e < geo.E) {
+            r = geo.edge(e);
+            const int loE = mad24(r.a, r.a > 0 ? bx0 : bx1, mad24(r.b, r.b > 0 ? by0 : by1, r.c));
+            ok = loE > 0;
+          }
+          u64 om = ballot(ok);
+          while (om && slot < 64) {
+            const int ql = first_bit(om);
+            om &= om - 1;
+            const unsigned pw = (unsigned)readlane(r.wx, ql) | ((unsigned)readlane(r.wy, ql) << 16);
+            const unsigned pv = (unsigned)readlane(r.vx, ql) | ((unsigned)readlane(r.vy, ql) << 16);
+            if (lane == slot) { w = pw; v = pv; }
+            ++slot;
+          }
+        }
+      }
+    }
+  }
+  // Does some cached edge hide the whole box K (kx0..ky1) from the whole box
+  // (bx0..by1)?  The points g that an edge hides the box from form a convex
+  // set (every segment from the box to g crosses the open edge), so K is
+  // hidden iff its four corners are.
+  __device__ __forceinline__ bool hides_box(int kx0, int ky0, int kx1, int ky1, int bx0, int by0, int bx1,
+                                            int by1) const {
+    const int wx = (int)(w & 0xffffu), wy = (int)(w >> 16), vx = (int)(v & 0xffffu), vy = (int)(v >> 16);
+    EdgeRec r;
+    r.wx = wx; r.wy = wy; r.vx = vx; r.vy = vy;
+    r.a = wy - vy;
+    r.b = vx - wx;
+    r.c = -(r.a * wx + r.b * wy);
+    r.nc = -r.c;
+    bool all = true;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int gx = (q & 1) ? kx1 : kx0, gy = (q & 2) ? ky1 : ky0;
+      bool rel, occ;
+      edge_vs_cone(r, gx, gy, bx0, by0, bx1, by1, bx0 - gx, bx1 - gx, by0 - gy, by1 - gy, rel, occ);
+      all = all && occ;
+    }
+    return ballot(all) != 0ull;
+  }
+};
+
+// Takes the least estimate out of a register cache of N slots per lane (lane
+// l, slot q: entry l + 64 q) and returns its entry, or -1 when the cache is
+// empty; v = the estimate.  Ties go to the lower lane, then the lower slot.
+template <int N>
+__device__ __forceinline__ int slot_pop(float (&ec)[N], float& v) {
+  const int lane = lane_id();
+  float bv = INFINITY;
+  int bs = 0;
+#pragma unroll
+  for (int q = 0; q < N; ++q)
+    if (ec[q] < bv) { bv = ec[q]; bs = q; }
+  // estimates are >= 0, so their bits order as unsigned
+  const unsigned key = __float_as_uint(bv);
+  const unsigned mk = wave_min_u32(key);
+  if (mk >= 0x7f800000u) return -1;
+  const int wl = first_bit(ballot(key == mk));
+  const int ws = readlane(bs, wl);
+#pragma unroll
+  for (int q = 0; q < N; ++q)
+    if (lane == wl && q == ws) ec[q] = INFINITY;
+  v = __uint_as_float(mk);
+  return wl + 64 * ws;
+}
 
 // Box (doubled pixel-centre coordinates) of the lanes set in m.
 template <int TW>
@@ -135,14 +265,23 @@ constexpr int kSeedWide = SPM_SEED_WIDE;   // candidates per round once a seed s
 //   kWalkRefill  up to kEstWalkMax (8192): lower-bound order, the least
 //                kEstCache per lane in registers, refilled when needed;
 //   kWalkCost    beyond: seed searches, then (cost, id) order.
-enum { kWalkCached = 0, kWalkRefill = 1, kWalkCost = 2 };
+//   kWalkCluster up to kClusterWalkMax: spatial clusters of kCluster
+//                generators in order of a lower bound over the tile, every
+//                cluster estimate in registers; a cluster that one edge hides
+//                from the whole tile is skipped at once, the members of the
+//                others are tried one by one.
+enum { kWalkCached = 0, kWalkRefill = 1, kWalkCost = 2, kWalkCluster = 3 };
+constexpr int kClSlots = 16;                                   // cluster estimates per lane
+constexpr int kClusterWalkMax = kClSlots * 64 * kCluster;      // 8192 generators
 constexpr int kEstWalkMax = 128 * 64;   // a lane owns up to 128 generators (two 64-bit taken masks)
 #ifndef SPM_REFILL_AUTO_MAX
 #define SPM_REFILL_AUTO_MAX 4096
 #endif
 constexpr int kRefillAutoMax = SPM_REFILL_AUTO_MAX;   // largest generator count that picks it by default
 inline int walk_mode(int gmax) {
-  return gmax <= kEstCache * 64 ? kWalkCached : (gmax <= kRefillAutoMax ? kWalkRefill : kWalkCost);
+  if (gmax <= kEstCache * 64) return kWalkCached;
+  if (gmax <= kRefillAutoMax) return kWalkRefill;
+  return gmax <= kClusterWalkMax ? kWalkCluster : kWalkCost;
 }
 #ifndef SPM_SEED_SHARE
 #define SPM_SEED_SHARE 1   // later seed searches of a tile skip the candidates earlier ones tried
@@ -439,11 +578,32 @@ __device__ int seed_search(const Geo& geo, const GenRec* sgen, const float* sgco
 //   samples: how many seed searches (seed_search) to run, each from a pixel
 //            still without a value after the seeds tried so far.
 // Returns this tile's per-lane winner position (for the next tile).
-template <int TW, bool STATS, int WALK>
+// The cost-sorted generator table as the tile walk reads it: the 64-byte
+// records with separate float costs and boxes (global memory, or an LDS copy
+// for small scenes).
+struct TabFull {
+  const GenRec* sgen;
+  const float* cost;
+  const int4* bb;
+  // spatial clusters (cluster walk): kCluster sorted positions per cluster, their box and least cost
+  const int* clk;
+  const int4* clbb;
+  const float* clc;
+  int ncl;
+  __device__ __forceinline__ float c(int k) const { return cost[k]; }
+  __device__ __forceinline__ int4 box(int k) const { return bb[k]; }
+  __device__ __forceinline__ int4 seg(int k) const { return make_int4(sgen[k].x, sgen[k].y, sgen[k].x2, sgen[k].y2); }
+  // a corner (then nb = its previous and next vertex)?
+  __device__ __forceinline__ bool corner(int k, int4& nb) const {
+    nb = make_int4(sgen[k].ux, sgen[k].uy, sgen[k].nx, sgen[k].ny);
+    return sgen[k].kind == SPM_GEN_VERTEX;
+  }
+  __device__ __forceinline__ int id(int k) const { return sgen[k].id; }
+};
+template <int TW, bool STATS, int WALK, class TAB, class GEO>
 __device__ __forceinline__ int tile_work(int tile, int W, int H, int W32, int G, const unsigned* __restrict__ inside,
-                                         const GenRec* sgen, const float* sgcost, const int4* sgbb, const Geo& geo,
-                                         float* __restrict__ dist, int* __restrict__ parent, int prevpos,
-                                         int samples, u64* st) {
+                                         const TAB& tab, const GEO& geo, float* __restrict__ dist,
+                                         int* __restrict__ parent, int prevpos, int samples, u64* st) {
   constexpr int TH = 64 / TW;
   constexpr int QL[4] = {0, TW / 2, (TH / 2) * TW, (TH / 2) * TW + TW / 2};  // first lane of each quadrant
   const int lane = lane_id();
@@ -474,6 +634,8 @@ __device__ __forceinline__ int tile_work(int tile, int W, int H, int W32, int G,
     int occ[kOccHints];   // the edges that last hid the whole tile from a generator (most recent first)
 #pragma unroll
     for (int h = 0; h < kOccHints; ++h) occ[h] = -1;
+    OccCache oc;
+    oc.reset();
     int sblk = -1;   // the edge that last blocked a seed candidate
 
     // Evaluate sorted generator k (cost gc, bounding box x0..y1) for every
@@ -492,7 +654,8 @@ __device__ __forceinline__ int tile_work(int tile, int W, int H, int W32, int G,
         const float room = room_below(best, gc);
         need = active && room > 0.0f && (float)d2 < 4.0f * room * room * (1.0f + 1e-6f);
       } else {
-        ax = sgen[k].x; ay = sgen[k].y; bx = sgen[k].x2; by = sgen[k].y2;
+        const int4 sg = tab.seg(k);
+        ax = sg.x; ay = sg.y; bx = sg.z; by = sg.w;
         const RPt q = seg_closest(ax, ay, bx, by, px, py, &clamp);
         (void)q;
         float dd;
@@ -507,6 +670,7 @@ __device__ __forceinline__ int tile_work(int tile, int W, int H, int W32, int G,
         }
         cc = gc + dd;
         need = active && lex_less(cc, k, best, bpos);
+        if (STATS) st[ST_SEG_LANE] += __popcll(ballot(active));
       }
       const u64 nm = ballot(need);
       if (STATS) st[ST_BOUND] += __popcll(act);
@@ -519,7 +683,6 @@ __device__ __forceinline__ int tile_work(int tile, int W, int H, int W32, int G,
       const u64 mA = is_seg ? ballot(need && clamp == 0) : nm;
       const u64 mB = is_seg ? ballot(need && clamp == 1) : 0ull;
       const u64 mI = nm & ~mA & ~mB;
-      const bool gv = !is_seg && sgen[k].kind == SPM_GEN_VERTEX;
       u64 bl = 0;
       for (int grp = 0; grp < 2; ++grp) {
         const u64 m = grp ? mB : mA;
@@ -528,9 +691,18 @@ __device__ __forceinline__ int tile_work(int tile, int W, int H, int W32, int G,
         int bx0, by0, bx1, by1;
         mask_box<TW>(m, i0, j0, bx0, by0, bx1, by1);
         const int gx = grp ? bx : ax, gy = grp ? by : ay;
-        bl |= wave_blocked_uniform<STATS>(geo, px, py, m, gx, gy, gv, gv ? sgen[k].ux : 0, gv ? sgen[k].uy : 0,
-                                          gv ? sgen[k].nx : 0, gv ? sgen[k].ny : 0, false, 0, 0, 0, 0, bx0, by0,
-                                          bx1, by1, occ, st);
+        if (STATS) st[ST_CACHE_TEST] += 1;
+        if (oc.hides(gx, gy, bx0, by0, bx1, by1)) {
+          if (STATS) st[ST_CACHE_HIT] += 1;
+          bl |= m;
+          continue;
+        }
+        int4 nb;
+        const bool gv = !is_seg && tab.corner(k, nb);
+        int found = -1;
+        bl |= wave_blocked_uniform<STATS>(geo, px, py, m, gx, gy, gv, gv ? nb.x : 0, gv ? nb.y : 0, gv ? nb.z : 0,
+                                          gv ? nb.w : 0, false, 0, 0, 0, 0, bx0, by0, bx1, by1, occ, st, &found);
+        if (found >= 0) oc.insert(geo.edge(found));
       }
       if (mI) {
         if (STATS) st[ST_VISWAVE] += 1;
@@ -564,9 +736,9 @@ __device__ __forceinline__ int tile_work(int tile, int W, int H, int W32, int G,
         const int h = lane + 64 * q;
         float v = INFINITY;
         if (h < G) {
-          const int4 b = sgbb[h];
+          const int4 b = tab.box(h);
           const float dx = (float)max(max(b.x - bx1, bx0 - b.z), 0), dy = (float)max(max(b.y - by1, by0 - b.w), 0);
-          v = (sgcost[h] + 0.5f * fsqrt(dx * dx + dy * dy)) * (1.0f - 4e-6f);
+          v = (tab.c(h) + 0.5f * fsqrt(dx * dx + dy * dy)) * (1.0f - 4e-6f);
         }
         ec[q] = v;
       }
@@ -576,8 +748,8 @@ __device__ __forceinline__ int tile_work(int tile, int W, int H, int W32, int G,
         const int k = seed_pop(ec, rej, m);
         if (k < 0 || m > UB) break;
         if (STATS) st[ST_BATCHES] += 1;
-        const int4 kb = sgbb[k];
-        const float kc = unif(sgcost[k]);
+        const int4 kb = tab.box(k);
+        const float kc = unif(tab.c(k));
         const int kx0 = uni(kb.x), ky0 = uni(kb.y), kx1 = uni(kb.z), ky1 = uni(kb.w);
         if (!(box_may_win(kc, kx0, ky0, kx1, ky1, qx0, qy0, qx1 - 2, qy1 - 2, ubq[0]) ||
               box_may_win(kc, kx0, ky0, kx1, ky1, qx1, qy0, qx1 + TW - 2, qy1 - 2, ubq[1]) ||
@@ -585,6 +757,68 @@ __device__ __forceinline__ int tile_work(int tile, int W, int H, int W32, int G,
               box_may_win(kc, kx0, ky0, kx1, ky1, qx1, qy1, qx1 + TW - 2, qy1 + TH - 2, ubq[3])))
           continue;
         try_gen(k, kc, kx0, ky0, kx1, ky1);
+      }
+    } else if constexpr (WALK == kWalkCluster) {
+      // Spatial clusters of kCluster generators in order of a lower bound
+      // over the active pixels' box, cost + |box - cluster box| (shaded as in
+      // the other walks); every member's own bound is at least its cluster's,
+      // so the walk stops once the least cluster estimate exceeds the tile's
+      // largest value.  A cluster that one cached edge hides from the whole
+      // box is skipped; the members of the others are tried in turn.
+      int bx0, by0, bx1, by1;
+      mask_box<TW>(act, i0, j0, bx0, by0, bx1, by1);
+      oc.fill_near(geo, bx0, by0, bx1, by1);
+      auto est_of = [&](const int4& b, float c) -> float {
+        const float dx = (float)max(max(b.x - bx1, bx0 - b.z), 0), dy = (float)max(max(b.y - by1, by0 - b.w), 0);
+        return (c + 0.5f * fsqrt(dx * dx + dy * dy)) * (1.0f - 4e-6f);
+      };
+      float ec[kClSlots];
+#pragma unroll
+      for (int q = 0; q < kClSlots; ++q) {
+        const int c = lane + 64 * q;
+        ec[q] = c < tab.ncl ? est_of(tab.clbb[c], tab.clc[c]) : INFINITY;
+      }
+      for (;;) {
+        float m;
+        const int c = slot_pop<kClSlots>(ec, m);
+        if (c < 0 || m > UB) break;
+        if (STATS) st[ST_BATCHES] += 1;
+        const int4 kb = tab.clbb[c];
+        const int cx0 = uni(kb.x), cy0 = uni(kb.y), cx1 = uni(kb.z), cy1 = uni(kb.w);
+        if (STATS) st[ST_CACHE_TEST] += 1;
+        if (oc.hides_box(cx0, cy0, cx1, cy1, bx0, by0, bx1, by1)) {
+          if (STATS) st[ST_CACHE_HIT] += 1;
+          continue;
+        }
+        int k = -1;
+        float kc = INFINITY, ek = INFINITY;
+        int4 b = make_int4(0, 0, 0, 0);
+        if (lane < kCluster) {
+          k = tab.clk[c * kCluster + lane];
+          if (k >= 0) {
+            b = tab.box(k);
+            kc = tab.c(k);
+            ek = est_of(b, kc);
+          }
+        }
+        u64 mm = ballot(k >= 0 && ek <= UB);
+        while (mm) {
+          // the least estimate first (the likely winner tightens the bounds for the rest)
+          const float e_here = ((mm >> lane) & 1ull) ? ek : INFINITY;
+          const unsigned mk = wave_min_u32(__float_as_uint(e_here));
+          const int jl = first_bit(ballot(__float_as_uint(e_here) == mk) & mm);
+          mm &= ~(1ull << jl);
+          if (__uint_as_float(mk) > UB) break;   // the bounds tightened since: the rest are larger still
+          const float gc = readlane_f(kc, jl);
+          const int kx0 = readlane_i(b.x, jl), ky0 = readlane_i(b.y, jl), kx1 = readlane_i(b.z, jl),
+                    ky1 = readlane_i(b.w, jl);
+          if (!(box_may_win(gc, kx0, ky0, kx1, ky1, qx0, qy0, qx1 - 2, qy1 - 2, ubq[0]) ||
+                box_may_win(gc, kx0, ky0, kx1, ky1, qx1, qy0, qx1 + TW - 2, qy1 - 2, ubq[1]) ||
+                box_may_win(gc, kx0, ky0, kx1, ky1, qx0, qy1, qx1 - 2, qy1 + TH - 2, ubq[2]) ||
+                box_may_win(gc, kx0, ky0, kx1, ky1, qx1, qy1, qx1 + TW - 2, qy1 + TH - 2, ubq[3])))
+            continue;
+          try_gen(readlane_i(k, jl), gc, kx0, ky0, kx1, ky1);
+        }
       }
     } else if constexpr (WALK == kWalkRefill) {
       // All generators in order of a lower bound of their value over the
@@ -600,9 +834,9 @@ __device__ __forceinline__ int tile_work(int tile, int W, int H, int W32, int G,
       int bx0, by0, bx1, by1;
       mask_box<TW>(act, i0, j0, bx0, by0, bx1, by1);
       auto est_box = [&](int h) -> float {
-        const int4 b = sgbb[h];
+        const int4 b = tab.box(h);
         const float dx = (float)max(max(b.x - bx1, bx0 - b.z), 0), dy = (float)max(max(b.y - by1, by0 - b.w), 0);
-        return (sgcost[h] + 0.5f * fsqrt(dx * dx + dy * dy)) * (1.0f - 4e-6f);
+        return (tab.c(h) + 0.5f * fsqrt(dx * dx + dy * dy)) * (1.0f - 4e-6f);
       };
       const int nj = lane < G ? (G - lane + 63) / 64 : 0;   // generators this lane owns
       float ec[kEstCache];
@@ -666,8 +900,8 @@ __device__ __forceinline__ int tile_work(int tile, int W, int H, int W32, int G,
         }
         const int k = wl + 64 * readlane_i(jq, wl);
         if (STATS) st[ST_BATCHES] += 1;
-        const int4 kb = sgbb[k];
-        const float kc = unif(sgcost[k]);
+        const int4 kb = tab.box(k);
+        const float kc = unif(tab.c(k));
         const int kx0 = uni(kb.x), ky0 = uni(kb.y), kx1 = uni(kb.z), ky1 = uni(kb.w);
         if (!(box_may_win(kc, kx0, ky0, kx1, ky1, qx0, qy0, qx1 - 2, qy1 - 2, ubq[0]) ||
               box_may_win(kc, kx0, ky0, kx1, ky1, qx1, qy0, qx1 + TW - 2, qy1 - 2, ubq[1]) ||
@@ -696,7 +930,8 @@ __device__ __forceinline__ int tile_work(int tile, int W, int H, int W32, int G,
           // sample the first pixel without a value, starting from the tile centre
           const u64 hi = un & ~((1ull << ((TH / 2) * TW + TW / 2)) - 1ull);
           const int l = first_bit(hi ? hi : un);
-          k = seed_search<STATS>(geo, sgen, sgcost, sgbb, G, readlane_i(px, l), readlane_i(py, l), rej, sblk, st);
+          k = seed_search<STATS>(geo, tab.sgen, tab.cost, tab.bb, G, readlane_i(px, l), readlane_i(py, l), rej, sblk,
+                                 st);
           bool seen = k < 0;
 #pragma unroll
           for (int t = 0; t < kMaxTried; ++t) seen |= t < ntried && tried[t] == k;
@@ -706,21 +941,21 @@ __device__ __forceinline__ int tile_work(int tile, int W, int H, int W32, int G,
         for (int t = 0; t < kMaxTried; ++t)
           if (t == ntried) tried[t] = k;
         ntried = min(ntried + 1, kMaxTried);
-        const int4 kb = sgbb[k];
-        try_gen(k, unif(sgcost[k]), uni(kb.x), uni(kb.y), uni(kb.z), uni(kb.w));
+        const int4 kb = tab.box(k);
+        try_gen(k, unif(tab.c(k)), uni(kb.x), uni(kb.y), uni(kb.z), uni(kb.w));
       }
     }
     // the walk in (cost, id) order
     const int g = lane;   // this lane's generator within a walk batch is base + g
     for (int base = 0; base < G; base += 64) {
-      if (sgcost[base] > UB) break;
+      if (tab.c(base) > UB) break;
       if (STATS) st[ST_BATCHES] += 1;
       // lane-parallel tile bound against the four quadrants
       float c = INFINITY;
       int4 bb = make_int4(0, 0, 0, 0);
       if (base + g < G) {
-        c = sgcost[base + g];
-        bb = sgbb[base + g];
+        c = tab.c(base + g);
+        bb = tab.box(base + g);
       }
       auto bound = [&]() {
         return base + g < G && (box_may_win(c, bb.x, bb.y, bb.z, bb.w, qx0, qy0, qx1 - 2, qy1 - 2, ubq[0]) ||
@@ -752,13 +987,12 @@ __device__ __forceinline__ int tile_work(int tile, int W, int H, int W32, int G,
   if (valid) {
     const size_t o = (size_t)j * W + i;
     dist[o] = best;
-    parent[o] = best < INFINITY ? sgen[bpos].id : -1;
+    parent[o] = best < INFINITY ? tab.id(bpos) : -1;
   }
   __builtin_amdgcn_s_setprio(0);
   return best < INFINITY ? bpos : -1;
 }
 
-constexpr int kPixelThreads = 512;
 #ifndef SPM_TILE_ORDER
 #define SPM_TILE_ORDER 1   // hand out work items by k_tile_order's classes (0: row-major)
 #endif
@@ -861,68 +1095,26 @@ __global__ __launch_bounds__(kOrderThreads) void k_tile_order(int W, int H, int 
 // the same XCD, each handing out every kQueues-th item.  That keeps the
 // number of contended atomics small: a single queue for every wavefront of
 // the chip serialises at one address.  Queue positions map to items through
-// the work order of k_tile_order when one is given (order != nullptr).  LDSD: the cost-sorted generator
-// table, the edges and the chunk boxes are first staged in LDS, so the
-// wave-uniform reads of the hot loops are LDS broadcasts instead of L2 round
-// trips.
-template <int TW, bool STATS, bool LDSD, int WALK>
-__global__ __launch_bounds__(kPixelThreads, WALK == kWalkCached ? SPM_PIXEL_MIN_WAVES_CACHED : SPM_PIXEL_MIN_WAVES) void k_pixel(int W, int H, int W32, int Gmax, int* misc,
-                                                         const unsigned* __restrict__ inside,
-                                                         const GenRec* __restrict__ sgen_g,
-                                                         const float* __restrict__ sgcost_g,
-                                                         const int4* __restrict__ sgbb_g,
-                                                         const EdgeRec* __restrict__ edges_g,
-                                                         const EdgeExt* __restrict__ ext,
-                                                         const int4* __restrict__ chunks_g, int E, int NC,
-                                                         float* __restrict__ dist, int* __restrict__ parent,
-                                                         int strip, int samples, int* __restrict__ qctr,
-                                                         const int* __restrict__ obins,
-                                                         const int* __restrict__ order, int ocap,
-                                                         u64* __restrict__ stats) {
+// the work order of k_tile_order when one is given (order != nullptr).
+//
+// LDSD: the cost-sorted generator table, the edges and the chunk boxes are
+// first staged in LDS (when they fit 64 KB), so the wave-uniform reads of the
+// hot loops are LDS broadcasts instead of L2 round trips.  (Compact 20-byte
+// generator and 8-byte edge records in 160 KB of LDS per 1024-thread
+// workgroup were measured for the large scenes: slower than L2, since the
+// large scenes are bound by VALU issue, not by load latency.)
+constexpr int kPixelThreads = 512;
+
+template <int TW, bool STATS, int WALK, class TAB, class GEO>
+__device__ __forceinline__ void pixel_items(int W, int H, int W32, int G, const unsigned* __restrict__ inside,
+                                            const TAB& tab, const GEO& geo, float* __restrict__ dist,
+                                            int* __restrict__ parent, int strip, int samples,
+                                            int* __restrict__ qctr, const int* __restrict__ order, int ocap,
+                                            const int* opre, u64* st) {
   constexpr int TH = 64 / TW;
-  extern __shared__ int4 smem[];
-  __shared__ int opre[kOrderBins];   // first queue position of each work class
-  const int G = misc[MISC_REACHED];
-  const GenRec* sgen = sgen_g;
-  const float* sgcost = sgcost_g;
-  const int4* sgbb = sgbb_g;
-  Geo geo{edges_g, ext, chunks_g, E, NC};
-  if (LDSD) {
-    GenRec* s_gen = (GenRec*)smem;
-    int4* s_bb = (int4*)(s_gen + Gmax);
-    EdgeRec* s_edges = (EdgeRec*)(s_bb + Gmax);
-    int4* s_chunks = (int4*)(s_edges + E);
-    float* s_cost = (float*)(s_chunks + NC);
-    const int t = threadIdx.x, nt = blockDim.x;
-    const int4* src = (const int4*)sgen_g;
-    for (int k = t; k < G * 4; k += nt) ((int4*)s_gen)[k] = src[k];
-    for (int k = t; k < G; k += nt) { s_bb[k] = sgbb_g[k]; s_cost[k] = sgcost_g[k]; }
-    const int4* se = (const int4*)edges_g;
-    for (int k = t; k < E * 2; k += nt) ((int4*)s_edges)[k] = se[k];
-    for (int k = t; k < NC; k += nt) s_chunks[k] = chunks_g[k];
-    __syncthreads();
-    sgen = s_gen;
-    sgcost = s_cost;
-    sgbb = s_bb;
-    geo.edges = s_edges;
-    geo.chunks = s_chunks;
-  }
-  if (order && threadIdx.x < 64) {
-    // exclusive prefix of the class sizes
-    const int l = lane_id();
-    int v = l < kOrderBins ? obins[l] : 0;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-      const int u = __shfl_up(v, o, 64);
-      if (l >= o) v += u;
-    }
-    if (l < kOrderBins) opre[l] = v - obins[l];
-  }
-  __syncthreads();
   const int ntx = (W + TW - 1) / TW, nty = (H + TH - 1) / TH;
   const int spr = (ntx + strip - 1) / strip;   // strips per tile row
   const int nitems = spr * nty;
-  u64 st[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   const int wpb = blockDim.x / kWave;
   const int nw = gridDim.x * wpb;                       // wavefronts in the grid
   const int nq = min(kQueues, (int)gridDim.x);          // queues in use (each has a workgroup)
@@ -942,16 +1134,65 @@ __global__ __launch_bounds__(kPixelThreads, WALK == kWalkCached ? SPM_PIXEL_MIN_
     const int t0 = sx * strip, t1 = min(t0 + strip, ntx);
     int prev = -1;
     for (int t = t0; t < t1; ++t)
-      prev = tile_work<TW, STATS, WALK>(ty * ntx + t, W, H, W32, G, inside, sgen, sgcost, sgbb, geo, dist, parent, prev,
-                                  samples, st);
+      prev = tile_work<TW, STATS, WALK>(ty * ntx + t, W, H, W32, G, inside, tab, geo, dist, parent, prev, samples,
+                                        st);
     int n = 0;
     if (lane_id() == 0) n = atomicAdd(&qctr[q * kQueueStride], 1);
     n = __shfl(n, 0, 64);
     pos = nw + q + nq * n;
   }
+}
+
+template <int TW, bool STATS, bool LDSD, int WALK>
+__global__ __launch_bounds__(kPixelThreads, WALK == kWalkCached ? SPM_PIXEL_MIN_WAVES_CACHED : SPM_PIXEL_MIN_WAVES)
+void k_pixel(int W, int H, int W32, int Gmax, int* misc, const unsigned* __restrict__ inside,
+             const GenRec* __restrict__ sgen_g, const float* __restrict__ sgcost_g, const int4* __restrict__ sgbb_g,
+             const EdgeRec* __restrict__ edges_g, const EdgeExt* __restrict__ ext, const int4* __restrict__ chunks_g,
+             int E, int NC, const int* __restrict__ clk, const int4* __restrict__ clbb, const float* __restrict__ clc,
+             float* __restrict__ dist, int* __restrict__ parent, int strip, int samples, int* __restrict__ qctr,
+             const int* __restrict__ obins, const int* __restrict__ order, int ocap, u64* __restrict__ stats) {
+  extern __shared__ int4 smem[];
+  __shared__ int opre[kOrderBins];   // first queue position of each work class
+  const int G = misc[MISC_REACHED];
+  const int t = threadIdx.x, nt = blockDim.x;
+  u64 st[ST_COUNT] = {};
+  if (order && t < 64) {
+    // exclusive prefix of the class sizes
+    const int l = lane_id();
+    int v = l < kOrderBins ? obins[l] : 0;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const int u = __shfl_up(v, o, 64);
+      if (l >= o) v += u;
+    }
+    if (l < kOrderBins) opre[l] = v - obins[l];
+  }
+  TabFull tab{sgen_g, sgcost_g, sgbb_g, clk, clbb, clc, (misc[MISC_G] + kCluster - 1) / kCluster};
+  Geo geo{edges_g, ext, chunks_g, E, NC};
+  if (LDSD) {
+    GenRec* s_gen = (GenRec*)smem;
+    int4* s_bb = (int4*)(s_gen + Gmax);
+    EdgeRec* s_edges = (EdgeRec*)(s_bb + Gmax);
+    int4* s_chunks = (int4*)(s_edges + E);
+    float* s_cost = (float*)(s_chunks + NC);
+    const int4* src = (const int4*)sgen_g;
+    for (int k = t; k < G * 4; k += nt) ((int4*)s_gen)[k] = src[k];
+    for (int k = t; k < G; k += nt) { s_bb[k] = sgbb_g[k]; s_cost[k] = sgcost_g[k]; }
+    const int4* se = (const int4*)edges_g;
+    for (int k = t; k < E * 2; k += nt) ((int4*)s_edges)[k] = se[k];
+    for (int k = t; k < NC; k += nt) s_chunks[k] = chunks_g[k];
+    tab.sgen = s_gen;
+    tab.cost = s_cost;
+    tab.bb = s_bb;
+    geo.edges = s_edges;
+    geo.chunks = s_chunks;
+  }
+  __syncthreads();
+  pixel_items<TW, STATS, WALK>(W, H, W32, G, inside, tab, geo, dist, parent, strip, samples, qctr, order, ocap, opre,
+                               st);
   if (STATS && lane_id() == 0) {
 #pragma unroll
-    for (int s = 0; s < 8; ++s) atomicAdd(&stats[s], st[s]);
+    for (int s = 0; s < ST_COUNT; ++s) atomicAdd(&stats[s], st[s]);
   }
 }
 
@@ -967,6 +1208,44 @@ static int device_cus() {
   return cached[dev];
 }
 
+// Spatial clusters for the cluster walk: kCluster consecutive positions of the
+// spatial generator order (sources first, then corners in Morton order of
+// their edges) form a cluster; its members are their cost-sorted positions
+// (-1 for an unreached generator or past the end), its box the union of their
+// boxes and its cost their least float cost.  One thread per position; the
+// kCluster threads of a cluster are neighbouring lanes of one wavefront.
+__global__ __launch_bounds__(256) void k_clusters(const int* __restrict__ misc, const int* __restrict__ gorder,
+                                                  const int* __restrict__ krank, const int4* __restrict__ sgbb,
+                                                  const float* __restrict__ sgcost, int* __restrict__ clk,
+                                                  int4* __restrict__ clbb, float* __restrict__ clc, int Gmax) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  const int Gc = misc[MISC_G];
+  const int ncl = (Gc + kCluster - 1) / kCluster;
+  int k = -1;
+  if (p < Gc) k = krank[gorder[p]];
+  int4 b = make_int4(1 << 20, 1 << 20, -(1 << 20), -(1 << 20));
+  float c = INFINITY;
+  if (k >= 0) {
+    b = sgbb[k];
+    c = sgcost[k];
+  }
+#pragma unroll
+  for (int o = 1; o < kCluster; o <<= 1) {
+    b.x = min(b.x, __shfl_xor(b.x, o, 64));
+    b.y = min(b.y, __shfl_xor(b.y, o, 64));
+    b.z = max(b.z, __shfl_xor(b.z, o, 64));
+    b.w = max(b.w, __shfl_xor(b.w, o, 64));
+    c = fminf(c, __shfl_xor(c, o, 64));
+  }
+  if (p < ncl * kCluster && p < ((Gmax + kCluster - 1) / kCluster) * kCluster) {
+    clk[p] = k;
+    if (p % kCluster == 0) {
+      clbb[p / kCluster] = c < INFINITY ? b : make_int4(0, 0, 0, 0);
+      clc[p / kCluster] = c;
+    }
+  }
+}
+
 template <int TW, bool STATS, bool LDSD, int WALK>
 static hipError_t launch_variant(const Dev& d, hipStream_t s, size_t shm) {
   auto kern = k_pixel<TW, STATS, LDSD, WALK>;
@@ -980,6 +1259,11 @@ static hipError_t launch_variant(const Dev& d, hipStream_t s, size_t shm) {
   const long long max_blocks = (waves_needed + (kPixelThreads / 64) - 1) / (kPixelThreads / 64);
   if (blocks > max_blocks) blocks = max_blocks;
   if (blocks < 1) blocks = 1;
+  if (WALK == kWalkCluster && d.Gmax > 0) {
+    const int npos = (d.Gmax + kCluster - 1) / kCluster * kCluster;
+    hipLaunchKernelGGL(k_clusters, dim3((unsigned)((npos + 255) / 256)), dim3(256), 0, s, d.misc, d.gorder, d.krank,
+                       d.sgbb, d.sgcost, d.clk, d.clbb, d.clc, d.Gmax);
+  }
   // the work order matters only when some items wait for a free wavefront
   const int* order = nullptr;
   if (SPM_TILE_ORDER && waves_needed > blocks * (kPixelThreads / 64) && order_fused(d)) {
@@ -996,8 +1280,8 @@ static hipError_t launch_variant(const Dev& d, hipStream_t s, size_t shm) {
     order = d.order;
   }
   hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(kPixelThreads), shm, s, d.W, d.H, d.W32, d.Gmax, d.misc,
-                     d.inside, d.sgen, d.sgcost, d.sgbb, d.edges, d.ext, d.chunks, d.E, d.NC, d.dist, d.parent,
-                     d.strip, d.samples, d.qctr, d.obins, order, d.ocap, d.stats);
+                     d.inside, d.sgen, d.sgcost, d.sgbb, d.edges, d.ext, d.chunks, d.E, d.NC, d.clk, d.clbb, d.clc,
+                     d.dist, d.parent, d.strip, d.samples, d.qctr, d.obins, order, d.ocap, d.stats);
   return hipGetLastError();
 }
 
@@ -1015,6 +1299,7 @@ static hipError_t launch_tw(const Dev& d, hipStream_t s) {
   switch (d.walk > 0 ? d.walk - 1 : walk_mode(d.Gmax)) {
     case kWalkCached: return launch_tw_walk<TW, kWalkCached>(d, s);
     case kWalkRefill: return launch_tw_walk<TW, kWalkRefill>(d, s);
+    case kWalkCluster: return launch_tw_walk<TW, kWalkCluster>(d, s);
     default: return launch_tw_walk<TW, kWalkCost>(d, s);
   }
 }
@@ -1038,7 +1323,7 @@ __global__ __launch_bounds__(kPixelThreads, SPM_PIXEL_MIN_WAVES) void k_pixel_ba
   __shared__ int item_scene, item_t0, item_t1, staged, next_tile;
   const int tid = threadIdx.x;
   if (tid == 0) staged = -1;
-  u64 st[8];
+  u64 st[ST_COUNT];
   for (;;) {
     if (tid == 0) {
       const int it = atomicAdd(ctr, 1);
@@ -1096,8 +1381,8 @@ __global__ __launch_bounds__(kPixelThreads, SPM_PIXEL_MIN_WAVES) void k_pixel_ba
         const int tb = min(ta + d.strip, item_t1);
         int prev = -1;
         for (int tile = ta; tile < tb; ++tile)
-          prev = tile_work<TW, false, WALK>(tile, d.W, d.H, d.W32, G, d.inside, sgen, sgcost, sgbb, geo, d.dist, d.parent,
-                                      prev, d.samples, st);
+          prev = tile_work<TW, false, WALK>(tile, d.W, d.H, d.W32, G, d.inside, TabFull{sgen, sgcost, sgbb}, geo, d.dist,
+                                            d.parent, prev, d.samples, st);
       }
     }
     __syncthreads();

@@ -327,6 +327,10 @@ void fill_dev(Dev& d, const spm_scene* s, const spm_out* out, char* ws, const La
   d.cmark = (int*)(ws + L.off_cmark);
   d.obins = (int*)(ws + L.off_obins);
   d.order = (int*)(ws + L.off_order);
+  d.krank = (int*)(ws + L.off_krank);
+  d.clk = (int*)(ws + L.off_clk);
+  d.clbb = (int4*)(ws + L.off_clbb);
+  d.clc = (float*)(ws + L.off_clc);
   d.ocap = L.ocap;
   d.dist = out->dist; d.parent = out->parent; d.gen_kind = out->gen_kind; d.gen_xy = out->gen_xy;
   d.gen_cost = out->gen_cost; d.gen_parent = out->gen_parent; d.n_gen = out->n_gen;
@@ -472,9 +476,9 @@ int spm_build_ex(const spm_scene* s, const spm_out* out, void* d_ws, size_t ws_b
     return fail(SPM_ERR_INVALID_ARG, "strip %d outside 0..%d", opts->strip, kMaxStrip);
   if (opts && opts->samples < -1)
     return fail(SPM_ERR_INVALID_ARG, "samples %d below -1", opts->samples);
-  if (opts && (opts->walk < 0 || opts->walk > 3))
-    return fail(SPM_ERR_INVALID_ARG, "walk %d outside 0..3", opts->walk);
-  if (opts && ((opts->walk == 1 && L.Gmax > 512) || (opts->walk == 2 && L.Gmax > 8192)))
+  if (opts && (opts->walk < 0 || opts->walk > 4))
+    return fail(SPM_ERR_INVALID_ARG, "walk %d outside 0..4", opts->walk);
+  if (opts && ((opts->walk == 1 && L.Gmax > 512) || ((opts->walk == 2 || opts->walk == 4) && L.Gmax > 8192)))
     return fail(SPM_ERR_INVALID_ARG, "walk %d needs at most %d generators (scene has up to %d)", opts->walk,
                 opts->walk == 1 ? 512 : 8192, L.Gmax);
   SingleSrc src;

@@ -50,6 +50,7 @@ constexpr int kMaxStrip = 64;
 constexpr int kQueues = 8;         // pixel-stage work queues (one per XCD)
 constexpr int kQueueStride = 32;   // ints between queue counters (one 128-byte line each)
 constexpr int kOrderBins = 32;     // pixel-stage work classes (tiles ranked by a distance lower bound)
+constexpr int kCluster = 8;        // generators per spatial cluster of the pixel stage's cluster walk
 #ifndef SPM_SEG_COLS
 #define SPM_SEG_COLS 16
 #endif
@@ -105,6 +106,7 @@ struct Layout {
   size_t off_gens, off_vis, off_sgen, off_sgcost, off_sgbb, off_inside, off_cost64, off_gxy, off_misc;
   size_t off_vsorted, off_vtx2gid, off_gorder, off_costpos, off_qctr, off_rmask, off_cmark;
   size_t off_obins, off_order;
+  size_t off_krank, off_clk, off_clbb, off_clc;   // generator clusters of the pixel stage
   // a host scene staged into the workspace (spm_build): poly_start, vx, vy, pts, segs, each at
   // a 16-int boundary from off_scene
   size_t off_scene, scene_ints, sc_poly, sc_vx, sc_vy, sc_pts, sc_segs;
@@ -154,6 +156,11 @@ inline Layout make_layout(int W, int H, int n_polys, int nv, int np, int ns) {
   if (tiles_of(W, H, 16) > L.ocap) L.ocap = tiles_of(W, H, 16);
   L.off_obins = take(kOrderBins * sizeof(int));
   L.off_order = take((size_t)kOrderBins * (size_t)(L.ocap > 0 ? L.ocap : 1) * sizeof(int));
+  const size_t ncl = (G1 + kCluster - 1) / kCluster;
+  L.off_krank = take(G1 * sizeof(int));
+  L.off_clk = take(ncl * kCluster * sizeof(int));
+  L.off_clbb = take(ncl * 16);
+  L.off_clc = take(ncl * sizeof(float));
   size_t si = 0;
   auto part = [&](size_t ints) { size_t r = si; si = align_up(si + ints, 16); return r; };
   L.sc_poly = part((size_t)n_polys + 1);
@@ -203,6 +210,10 @@ struct Dev {
   int* cmark;     // the barrier-free rounds' progress marks, kChaosSlots of them kQueueStride ints apart
   int* obins;     // pixel-stage work classes: item count of each (kOrderBins)
   int* order;     // work items of class c at order[c * ocap ...], in no particular order within it
+  int* krank;     // canonical generator g: its position in the cost-sorted table, -1 when unreached
+  int* clk;       // cluster c: the sorted positions of its kCluster members (-1: none), in spatial order
+  int4* clbb;     // cluster c: bounding box of its members
+  float* clc;     // cluster c: least float cost of its members (+inf: none)
   int ocap;
   // outputs
   float* dist;
@@ -231,6 +242,10 @@ struct Geo {
   const EdgeExt* ext;
   const int4* chunks;
   int E, NC;
+#ifdef __HIPCC__
+  __device__ __forceinline__ EdgeRec edge(int e) const { return edges[e]; }
+  __device__ __forceinline__ int4 chunk(int c) const { return chunks[c]; }
+#endif
 };
 
 // ------------------------------------------------------------------------
@@ -418,7 +433,8 @@ __device__ __forceinline__ RPt seg_closest(int ax, int ay, int bx, int by, int p
 // lane).  Exact 64-bit predicates over every edge of the chunks whose bounding
 // box meets the box (cx0..cy1), which must contain P and Q.  P may be an
 // obstacle corner (pv = 1 with its neighbours), Q is free.
-__device__ __forceinline__ bool lane_visible_rational(const Geo& d, int px, int py, bool pv, int pux, int puy,
+template <class GEO>
+__device__ __forceinline__ bool lane_visible_rational(const GEO& d, int px, int py, bool pv, int pux, int puy,
                                                       int pnx, int pny, RPt q, bool need, int cx0, int cy0,
                                                       int cx1, int cy1) {
   bool blocked = false;
@@ -429,7 +445,7 @@ __device__ __forceinline__ bool lane_visible_rational(const Geo& d, int px, int 
     int ci = cb + lane_id();
     bool hit = false;
     if (ci < d.NC) {
-      int4 bb = d.chunks[ci];
+      int4 bb = d.chunk(ci);
       hit = bb.x <= cx1 && bb.z >= cx0 && bb.y <= cy1 && bb.w >= cy0;
     }
     u64 cm = ballot(hit);
@@ -440,7 +456,7 @@ __device__ __forceinline__ bool lane_visible_rational(const Geo& d, int px, int 
       int e1 = min(e0 + kChunk, d.E);
       if (ballot(need && !blocked) == 0) return false;
       for (int e = e0; e < e1; ++e) {
-        EdgeRec r = d.edges[e];
+        EdgeRec r = d.edge(e);
         if (need && !blocked) {
           long long o1 = dqx * (r.wy - py) - dqy * (r.wx - px);
           long long o2 = dqx * (r.vy - py) - dqy * (r.vx - px);
@@ -474,13 +490,14 @@ __device__ __forceinline__ bool lane_visible_rational(const Geo& d, int px, int 
 // between the chunk box and the lanes' box (doubled units): touching or within
 // 64, within 256, farther.  Walking the near classes first finds the nearby
 // occluders -- which usually decide visibility -- before the far ones.
-__device__ __forceinline__ void chunk_classes(const int4* chunks, int NC, int cb, int cx0, int cy0, int cx1, int cy1,
+template <class GEO>
+__device__ __forceinline__ void chunk_classes(const GEO& d, int NC, int cb, int cx0, int cy0, int cx1, int cy1,
                                               int bx0, int by0, int bx1, int by1, u64 cls[3]) {
   const int ci = cb + lane_id();
   bool hit = false;
   int gap = 0;
   if (ci < NC) {
-    const int4 bb = chunks[ci];
+    const int4 bb = d.chunk(ci);
     hit = bb.x <= cx1 && bb.z >= cx0 && bb.y <= cy1 && bb.w >= cy0;
     gap = max(max(max(bb.x - bx1, bx0 - bb.z), max(bb.y - by1, by0 - bb.w)), 0);
   }
@@ -555,11 +572,13 @@ __device__ __forceinline__ void edge_vs_cone(const EdgeRec& r, int gx, int gy, i
 //             first, tried before the scan as occluders of the whole box;
 //             the occluder found goes to the front.  Neighbouring generators
 //             are often hidden by the same few edges.
-template <bool STATS>
-__device__ __forceinline__ u64 wave_blocked_uniform(const Geo& d, int px, int py, u64 need, int gx, int gy, bool gvert,
+//   found:    when not null, receives the index of the edge that hid the
+//             whole box (hint or scan), or keeps its value when none did.
+template <bool STATS, class GEO>
+__device__ __forceinline__ u64 wave_blocked_uniform(const GEO& d, int px, int py, u64 need, int gx, int gy, bool gvert,
                                                     int gux, int guy, int gnx, int gny, bool pv, int pux, int puy,
                                                     int pnx, int pny, int bx0, int by0, int bx1, int by1,
-                                                    int* occ_hint, u64* st) {
+                                                    int* occ_hint, u64* st, int* found = nullptr) {
   const int lane = lane_id();
   const bool me = (need >> lane) & 1ull;
   bool blk = false;
@@ -578,9 +597,10 @@ __device__ __forceinline__ u64 wave_blocked_uniform(const Geo& d, int px, int py
     for (int h = 0; h < kOccHints; ++h) {
       if (occ_hint[h] < 0) break;
       bool rel, occ;
-      edge_vs_cone(d.edges[occ_hint[h]], gx, gy, bx0, by0, bx1, by1, rx0, rx1, ry0, ry1, rel, occ);
+      edge_vs_cone(d.edge(occ_hint[h]), gx, gy, bx0, by0, bx1, by1, rx0, rx1, ry0, ry1, rel, occ);
       if (ballot(occ)) {
         if (STATS) st[6] += 1;
+        if (found) *found = occ_hint[h];
         occ_hint_front(occ_hint, h);
         return need;
       }
@@ -588,7 +608,7 @@ __device__ __forceinline__ u64 wave_blocked_uniform(const Geo& d, int px, int py
   }
   for (int cb = 0; cb < d.NC; cb += kWave) {
     u64 cls[3];
-    chunk_classes(d.chunks, d.NC, cb, cx0, cy0, cx1, cy1, bx0, by0, bx1, by1, cls);
+    chunk_classes(d, d.NC, cb, cx0, cy0, cx1, cy1, bx0, by0, bx1, by1, cls);
     for (int cl = 0; cl < 3; ++cl) {
     u64 cm = cls[cl];
     while (cm) {
@@ -598,7 +618,7 @@ __device__ __forceinline__ u64 wave_blocked_uniform(const Geo& d, int px, int py
       bool rel = false, occ = false;
       EdgeRec r = {0, 0, 0, 0, 0, 0, 0, 0};
       if (e < d.E) {
-        r = d.edges[e];
+        r = d.edge(e);
         edge_vs_cone(r, gx, gy, bx0, by0, bx1, by1, rx0, rx1, ry0, ry1, rel, occ);
       }
       if (STATS) st[4] += 1;
@@ -606,6 +626,7 @@ __device__ __forceinline__ u64 wave_blocked_uniform(const Geo& d, int px, int py
       if (om) {
         if (STATS) st[6] += 1;
         if (occ_hint) occ_hint_push(occ_hint, chunk * kChunk + first_bit(om));
+        if (found) *found = chunk * kChunk + first_bit(om);
         return need;
       }
       u64 rm = ballot(rel);
@@ -645,7 +666,7 @@ __device__ __forceinline__ u64 wave_blocked_uniform(const Geo& d, int px, int py
       int ci = cb + lane;
       bool hit = false;
       if (ci < d.NC) {
-        int4 bb = d.chunks[ci];
+        int4 bb = d.chunk(ci);
         hit = bb.x <= cx1 && bb.z >= cx0 && bb.y <= cy1 && bb.w >= cy0;
       }
       u64 cm = ballot(hit);
@@ -654,7 +675,7 @@ __device__ __forceinline__ u64 wave_blocked_uniform(const Geo& d, int px, int py
         cm &= cm - 1;
         const int e0 = chunk * kChunk, e1 = min(e0 + kChunk, d.E);
         for (int e = e0; e < e1; ++e) {
-          EdgeRec r = d.edges[e];
+          EdgeRec r = d.edge(e);
           if (mine && !blk) {
             int ow = mad24(A, r.wx, mad24(B, r.wy, C));
             if (ow == 0) {
@@ -709,8 +730,8 @@ __device__ __forceinline__ void edge_vs_band(const EdgeRec& r, int ax, int ay, i
 
 //   occ_hint: as for wave_blocked_uniform (an edge tried first as an occluder
 //             of the whole band, updated with the occluder found).
-template <bool STATS>
-__device__ __forceinline__ u64 wave_blocked_perp(const Geo& d, int px, int py, u64 need, int ax, int ay, int bx,
+template <bool STATS, class GEO>
+__device__ __forceinline__ u64 wave_blocked_perp(const GEO& d, int px, int py, u64 need, int ax, int ay, int bx,
                                                  int by, bool pv, int pux, int puy, int pnx, int pny, int bx0,
                                                  int by0, int bx1, int by1, int* occ_hint, u64* st) {
   const int lane = lane_id();
@@ -743,7 +764,7 @@ __device__ __forceinline__ u64 wave_blocked_perp(const Geo& d, int px, int py, u
     for (int h = 0; h < kOccHints; ++h) {
       if (occ_hint[h] < 0) break;
       bool rel, occ;
-      edge_vs_band(d.edges[occ_hint[h]], ax, ay, bx, by, ex, ey, Pmin, Pmax, bx0, by0, bx1, by1, rel, occ);
+      edge_vs_band(d.edge(occ_hint[h]), ax, ay, bx, by, ex, ey, Pmin, Pmax, bx0, by0, bx1, by1, rel, occ);
       if (ballot(occ)) {
         if (STATS) st[6] += 1;
         occ_hint_front(occ_hint, h);
@@ -753,7 +774,7 @@ __device__ __forceinline__ u64 wave_blocked_perp(const Geo& d, int px, int py, u
   }
   for (int cb = 0; cb < d.NC; cb += kWave) {
     u64 cls[3];
-    chunk_classes(d.chunks, d.NC, cb, cx0, cy0, cx1, cy1, bx0, by0, bx1, by1, cls);
+    chunk_classes(d, d.NC, cb, cx0, cy0, cx1, cy1, bx0, by0, bx1, by1, cls);
     for (int cl = 0; cl < 3; ++cl) {
     u64 cm = cls[cl];
     while (cm) {
@@ -763,7 +784,7 @@ __device__ __forceinline__ u64 wave_blocked_perp(const Geo& d, int px, int py, u
       bool rel = false, occ = false;
       EdgeRec r = {0, 0, 0, 0, 0, 0, 0, 0};
       if (e < d.E) {
-        r = d.edges[e];
+        r = d.edge(e);
         edge_vs_band(r, ax, ay, bx, by, ex, ey, Pmin, Pmax, bx0, by0, bx1, by1, rel, occ);
       }
       if (STATS) st[4] += 1;

@@ -119,7 +119,7 @@ class Builder:
     tile: pixel tile of one wavefront; strip: tiles per work item (0 = library
     default); samples: seed searches per tile (0 = default, -1 = none); walk:
     how tiles go through the generators (0 = by generator count, 1 = register
-    cache, 2 = refilled cache, 3 = seed searches and cost order).  strip,
+    cache, 2 = refilled cache, 3 = seed searches and cost order, 4 = spatial clusters).  strip,
     samples and walk change speed only."""
 
     def __init__(self, dscene: DeviceScene, tile=(8, 8), strip: int = 0, samples: int = 0, walk: int = 0):

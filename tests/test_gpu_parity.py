@@ -114,8 +114,9 @@ def test_tile_shapes_bitwise(spm, tile):
     assert np.array_equal(a["dist"], b["dist"]) and np.array_equal(a["parent"], b["parent"])
 
 
-@pytest.mark.parametrize("make,walks", [(lambda: config2(1), (1, 2, 3)), (lambda: profiling_grid(20, seed=2), (2, 3)),
-                                        (lambda: random_small(5), (1, 2, 3)), (lambda: config3(1), (2, 3))])
+@pytest.mark.parametrize("make,walks", [(lambda: config2(1), (1, 2, 3, 4)), (lambda: profiling_grid(20, seed=2), (2, 3, 4)),
+                                        (lambda: random_small(5), (1, 2, 3, 4)), (lambda: config3(1), (2, 3, 4)),
+                                        (lambda: config3(3), (3, 4))])
 def test_walk_modes_bitwise(spm, make, walks):
     """Every walk of the pixel stage gives the same map bit for bit (the (value, position) order decides)."""
     import torch
