@@ -181,9 +181,9 @@ def _batched(spm, torch, reps=10):
     scenes = config4_list()
     from paper_1805_08500_amd import autotune
     t0 = time.perf_counter()
-    tiles = autotune.tune(scenes, cache_path=None)
+    tuned = autotune.tune(scenes, cache_path=None)
     tune_s = time.perf_counter() - t0
-    bb = spm.BatchBuilder(scenes, check=False, tile_w=tiles)
+    bb = spm.BatchBuilder(scenes, check=False, tuned=tuned)
     s = torch.cuda.Stream()
     with torch.cuda.stream(s):
         bb.build(s)
@@ -202,7 +202,8 @@ def _batched(spm, torch, reps=10):
     ms = e0.elapsed_time(e1) / reps
     return {"workload": "256 scenes, sides in {128,256,512,1024}, 4-80 convex hulls, 1-5 points, 0-3 segments, "
                         "seed 7; one hipGraph replay per build",
-            "tiles": {str(k): v for k, v in tiles.items()}, "tuning_s": round(tune_s, 2),
+            "tuned": {"tile_w": {str(k): v for k, v in tuned["tile_w"].items()}, "pixel_waves": tuned["pixel_waves"],
+                      "walk": tuned["walk"], "tuning_s": round(tune_s, 2), "pixel_ms": tuned["times"]["batch"]},
             "scenes": len(scenes), "pixels": int(sum(x.width * x.height for x in scenes)), "pairs": pairs,
             "ms_per_batch": ms, "value": pairs / (ms * 1e-3) / 1e6, "unit": "Mpixel·gen/s"}
 

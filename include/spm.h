@@ -201,16 +201,22 @@ int spm_build_noalloc(const spm_scene* dev_scene, const spm_out* out, void* stre
 
 /* ---------------------------------------------------------------------
  * Batched builds.  Many independent scenes are built by one launch per
- * stage; the pixel stage is a single persistent launch whose workgroups take
- * (scene, slice of tiles) items from a device queue.  The paper motivates
- * cheap rebuilds of many maps for dynamic scenes (Section 1); this batches
- * them.  Each scene follows the conventions above and gets its own outputs.
+ * stage over all of them; the pixel stage is a single persistent launch whose
+ * workgroups take (scene, slice of 64 tiles) items from one device queue,
+ * each scene with its own tile shape.  The paper motivates cheap rebuilds of
+ * many maps for dynamic scenes (Section 1); this batches them.  Each scene
+ * follows the conventions above (validated beforehand) and gets its own
+ * outputs.  Zero-initialised option fields select the defaults.
  * ------------------------------------------------------------------- */
 typedef struct {
   int32_t n;                /* number of scenes, >= 1 */
   const spm_scene* scenes;  /* [n] device-memory scenes (counts are host values) */
   const spm_out* outs;      /* [n] outputs, sized by spm_query_sizes per scene */
   const int32_t* tile_w;    /* [n] tile width per scene: 8 (8x8), 16 (16x4) or 4 (4x16); NULL = all 8 */
+  int32_t pixel_waves;      /* waves per SIMD of the persistent pixel launch, 1..8 (fewer if they do not
+                               fit); 0 = as many as fit */
+  int32_t walk;             /* 0 = by the batch's largest possible generator count; 1..3 as in
+                               spm_build_opts.walk (the cluster walk, 4, is not offered for batches) */
 } spm_batch;
 
 /* Device workspace bytes for a batch (host arithmetic only). */

@@ -48,7 +48,7 @@ class SpmBuildOpts(ctypes.Structure):
 
 class SpmBatch(ctypes.Structure):
     _fields_ = [("n", c_i32), ("scenes", ctypes.POINTER(SpmScene)), ("outs", ctypes.POINTER(SpmOut)),
-                ("tile_w", ctypes.POINTER(c_i32))]
+                ("tile_w", ctypes.POINTER(c_i32)), ("pixel_waves", c_i32), ("walk", c_i32)]
 
 
 class SpmMapHost(ctypes.Structure):

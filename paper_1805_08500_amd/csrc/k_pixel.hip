@@ -1310,14 +1310,13 @@ hipError_t launch_pixel(const Dev& d, hipStream_t s) {
   return launch_tw<8>(d, s);
 }
 
-// Batched pixel stage: one persistent launch per tile shape used in the batch
-// (each compiled for that shape alone, which keeps its register budget that
-// of k_pixel).  A workgroup takes a work item -- kSlice tiles of one scene --
-// from the launch's queue, skips scenes of another tile shape, stages the
-// scene's generator table and edges in LDS when it differs from the scene
-// already staged, and its wavefronts share the slice's tiles through an LDS
-// counter.
-template <bool LDSD, int TW, int WALK>
+// Batched pixel stage: one persistent launch for every tile of every scene.
+// A workgroup takes a work item -- kSlice tiles of one scene -- from the
+// launch's queue, stages the scene's generator table and edges in LDS when
+// it differs from the scene already staged, and its wavefronts share the
+// slice's tiles through an LDS counter.  Each scene keeps its own tile shape
+// (the walk is compiled for all three shapes and chosen per scene).
+template <bool LDSD, int WALK>
 __global__ __launch_bounds__(kPixelThreads, SPM_PIXEL_MIN_WAVES) void k_pixel_batch(BatchSrc src, int* ctr) {
   extern __shared__ int4 smem[];
   __shared__ int item_scene, item_t0, item_t1, staged, next_tile;
@@ -1331,7 +1330,7 @@ __global__ __launch_bounds__(kPixelThreads, SPM_PIXEL_MIN_WAVES) void k_pixel_ba
       if (src.locate(STG_SLICE, it, sc, local)) {
         const Dev& d0 = src.scene(sc);
         const int nt = tiles_of(d0.W, d0.H, d0.tile_w);
-        item_scene = d0.tile_w == TW ? sc : -2;
+        item_scene = sc;
         item_t0 = local * kSlice;
         item_t1 = min(nt, item_t0 + kSlice);
       } else {
@@ -1342,66 +1341,70 @@ __global__ __launch_bounds__(kPixelThreads, SPM_PIXEL_MIN_WAVES) void k_pixel_ba
     __syncthreads();
     const int sc = item_scene;
     if (sc == -1) break;
-    if (sc >= 0) {
-      const Dev& d = src.scene(sc);
-      const int G = d.misc[MISC_REACHED];
-      const GenRec* sgen = d.sgen;
-      const float* sgcost = d.sgcost;
-      const int4* sgbb = d.sgbb;
-      Geo geo{d.edges, d.ext, d.chunks, d.E, d.NC};
-      if (LDSD) {
-        GenRec* s_gen = (GenRec*)smem;
-        int4* s_bb = (int4*)(s_gen + d.Gmax);
-        EdgeRec* s_edges = (EdgeRec*)(s_bb + d.Gmax);
-        int4* s_chunks = (int4*)(s_edges + d.E);
-        float* s_cost = (float*)(s_chunks + d.NC);
-        if (sc != staged) {
-          const int4* gsrc = (const int4*)d.sgen;
-          for (int k = tid; k < G * 4; k += blockDim.x) ((int4*)s_gen)[k] = gsrc[k];
-          for (int k = tid; k < G; k += blockDim.x) { s_bb[k] = d.sgbb[k]; s_cost[k] = d.sgcost[k]; }
-          const int4* se = (const int4*)d.edges;
-          for (int k = tid; k < d.E * 2; k += blockDim.x) ((int4*)s_edges)[k] = se[k];
-          for (int k = tid; k < d.NC; k += blockDim.x) s_chunks[k] = d.chunks[k];
-          __syncthreads();
-          if (tid == 0) staged = sc;
-        }
-        sgen = s_gen;
-        sgcost = s_cost;
-        sgbb = s_bb;
-        geo.edges = s_edges;
-        geo.chunks = s_chunks;
+    const Dev& d = src.scene(sc);
+    const int G = d.misc[MISC_REACHED];
+    TabFull tab{d.sgen, d.sgcost, d.sgbb};
+    Geo geo{d.edges, d.ext, d.chunks, d.E, d.NC};
+    if (LDSD) {
+      GenRec* s_gen = (GenRec*)smem;
+      int4* s_bb = (int4*)(s_gen + d.Gmax);
+      EdgeRec* s_edges = (EdgeRec*)(s_bb + d.Gmax);
+      int4* s_chunks = (int4*)(s_edges + d.E);
+      float* s_cost = (float*)(s_chunks + d.NC);
+      if (sc != staged) {
+        const int4* gsrc = (const int4*)d.sgen;
+        for (int k = tid; k < G * 4; k += blockDim.x) ((int4*)s_gen)[k] = gsrc[k];
+        for (int k = tid; k < G; k += blockDim.x) { s_bb[k] = d.sgbb[k]; s_cost[k] = d.sgcost[k]; }
+        const int4* se = (const int4*)d.edges;
+        for (int k = tid; k < d.E * 2; k += blockDim.x) ((int4*)s_edges)[k] = se[k];
+        for (int k = tid; k < d.NC; k += blockDim.x) s_chunks[k] = d.chunks[k];
+        __syncthreads();
+        if (tid == 0) staged = sc;
       }
-      // the slice's tiles in strips of d.strip consecutive tiles (seeded left to right)
-      for (;;) {
-        int t = 0;
-        if (lane_id() == 0) t = atomicAdd(&next_tile, d.strip);
-        t = __shfl(t, 0, 64);
-        const int ta = item_t0 + t;
-        if (ta >= item_t1) break;
-        const int tb = min(ta + d.strip, item_t1);
-        int prev = -1;
-        for (int tile = ta; tile < tb; ++tile)
-          prev = tile_work<TW, false, WALK>(tile, d.W, d.H, d.W32, G, d.inside, TabFull{sgen, sgcost, sgbb}, geo, d.dist,
-                                            d.parent, prev, d.samples, st);
+      tab = TabFull{s_gen, s_cost, s_bb};
+      geo.edges = s_edges;
+      geo.chunks = s_chunks;
+    }
+    // the slice's tiles in strips of d.strip consecutive tiles (seeded left to right)
+    for (;;) {
+      int t = 0;
+      if (lane_id() == 0) t = atomicAdd(&next_tile, d.strip);
+      t = __shfl(t, 0, 64);
+      const int ta = item_t0 + t;
+      if (ta >= item_t1) break;
+      const int tb = min(ta + d.strip, item_t1);
+      int prev = -1;
+      for (int tile = ta; tile < tb; ++tile) {
+        if (d.tile_w == 16)
+          prev = tile_work<16, false, WALK>(tile, d.W, d.H, d.W32, G, d.inside, tab, geo, d.dist, d.parent, prev,
+                                            d.samples, st);
+        else if (d.tile_w == 4)
+          prev = tile_work<4, false, WALK>(tile, d.W, d.H, d.W32, G, d.inside, tab, geo, d.dist, d.parent, prev,
+                                           d.samples, st);
+        else
+          prev = tile_work<8, false, WALK>(tile, d.W, d.H, d.W32, G, d.inside, tab, geo, d.dist, d.parent, prev,
+                                           d.samples, st);
       }
     }
     __syncthreads();
   }
 }
 
-__global__ void k_reset_counters(int* ctr) {
-  if (threadIdx.x < 3) ctr[16 * threadIdx.x] = 0;
+__global__ void k_reset_counter(int* ctr) {
+  if (threadIdx.x == 0) *ctr = 0;
 }
 
-template <int TW, int WALK>
-static hipError_t launch_batch_tw_walk(const BatchSrc& b, const Plan& p, int* ctr, hipStream_t s) {
+template <int WALK>
+static hipError_t launch_batch_walk(const BatchSrc& b, const Plan& p, int* ctr, hipStream_t s) {
   const size_t shm = p.pixel_lds;
   const bool lds = shm > 0 && shm <= kPixelLdsMax;
-  auto kern = lds ? k_pixel_batch<true, TW, WALK> : k_pixel_batch<false, TW, WALK>;
+  auto kern = lds ? k_pixel_batch<true, WALK> : k_pixel_batch<false, WALK>;
   const size_t use = lds ? shm : 0;
   int per_cu = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kPixelThreads, use) != hipSuccess || per_cu < 1)
     per_cu = 1;
+  // waves per SIMD asked for: a 512-thread workgroup holds two waves of each of the CU's four SIMDs
+  if (p.pixel_waves > 0) per_cu = max(1, min(per_cu, p.pixel_waves / 2));
   long long blocks = (long long)device_cus() * per_cu;
   if (blocks > p.total[STG_SLICE]) blocks = p.total[STG_SLICE];
   if (blocks < 1) blocks = 1;
@@ -1409,23 +1412,15 @@ static hipError_t launch_batch_tw_walk(const BatchSrc& b, const Plan& p, int* ct
   return hipGetLastError();
 }
 
-template <int TW>
-static hipError_t launch_batch_tw(const BatchSrc& b, const Plan& p, int* ctr, hipStream_t s) {
-  switch (walk_mode(p.maxGmax)) {
-    case kWalkCached: return launch_batch_tw_walk<TW, kWalkCached>(b, p, ctr, s);
-    case kWalkRefill: return launch_batch_tw_walk<TW, kWalkRefill>(b, p, ctr, s);
-    default: return launch_batch_tw_walk<TW, kWalkCost>(b, p, ctr, s);
-  }
-}
-
-// ctr: three queue counters, 16 ints apart (one per tile shape)
+// ctr: the queue counter of the launch (reset by a kernel, so the launch can sit in a graph)
 hipError_t launch_pixel_batch(const BatchSrc& b, const Plan& p, int* ctr, hipStream_t s) {
-  hipLaunchKernelGGL(k_reset_counters, dim3(1), dim3(64), 0, s, ctr);
-  hipError_t e = hipSuccess;
-  if ((p.tw_mask & 2) && (e = launch_batch_tw<8>(b, p, ctr, s)) != hipSuccess) return e;
-  if ((p.tw_mask & 1) && (e = launch_batch_tw<4>(b, p, ctr + 16, s)) != hipSuccess) return e;
-  if ((p.tw_mask & 4) && (e = launch_batch_tw<16>(b, p, ctr + 32, s)) != hipSuccess) return e;
-  return hipSuccess;
+  hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(64), 0, s, ctr);
+  const int w = p.walk > 0 ? p.walk - 1 : walk_mode(p.maxGmax);
+  switch (w) {
+    case kWalkCached: return launch_batch_walk<kWalkCached>(b, p, ctr, s);
+    case kWalkRefill: return launch_batch_walk<kWalkRefill>(b, p, ctr, s);
+    default: return launch_batch_walk<kWalkCost>(b, p, ctr, s);
+  }
 }
 
 }  // namespace spm

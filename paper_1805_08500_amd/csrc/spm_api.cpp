@@ -356,7 +356,6 @@ void plan_add(Plan& p, const Dev& d) {
   p.maxW = std::max(p.maxW, d.W);
   p.maxE = std::max(p.maxE, d.E);
   p.maxNC = std::max(p.maxNC, d.NC);
-  p.tw_mask |= d.tile_w == 4 ? 1 : (d.tile_w == 16 ? 4 : 2);
   p.pixel_lds = std::max(p.pixel_lds, pixel_lds_bytes(d.Gmax, d.E, d.NC));
   p.genvis_lds = std::max(p.genvis_lds, (size_t)d.E * sizeof(EdgeRec) + (size_t)d.NC * 16);
 }
@@ -415,6 +414,9 @@ struct BatchLayout {
 
 int batch_layout(const spm_batch* b, BatchLayout& B) {
   if (!b || b->n < 1 || !b->scenes || !b->outs) return fail(SPM_ERR_INVALID_ARG, "empty or NULL batch");
+  if (b->pixel_waves < 0 || b->pixel_waves > 8)
+    return fail(SPM_ERR_INVALID_ARG, "pixel_waves %d outside 0..8", b->pixel_waves);
+  if (b->walk < 0 || b->walk > 3) return fail(SPM_ERR_INVALID_ARG, "batch walk %d outside 0..3", b->walk);
   const int n = b->n;
   size_t o = 0;
   auto take = [&](size_t bytes) { size_t r = o; o = align_up(o + (bytes ? bytes : 1), 256); return r; };
@@ -438,7 +440,7 @@ int batch_layout(const spm_batch* b, BatchLayout& B) {
   return SPM_OK;
 }
 
-void batch_devs(const spm_batch* b, const BatchLayout& B, char* ws, std::vector<Dev>& devs, Plan& p) {
+int batch_devs(const spm_batch* b, const BatchLayout& B, char* ws, std::vector<Dev>& devs, Plan& p) {
   const int n = b->n;
   devs.resize(n);
   p = Plan{};
@@ -447,6 +449,12 @@ void batch_devs(const spm_batch* b, const BatchLayout& B, char* ws, std::vector<
     fill_dev(devs[i], &b->scenes[i], &b->outs[i], ws + B.off_scene[i], B.L[i], tw, nullptr);
     plan_add(p, devs[i]);
   }
+  p.pixel_waves = b->pixel_waves;
+  p.walk = b->walk;
+  if ((p.walk == 1 && p.maxGmax > 512) || (p.walk == 2 && p.maxGmax > 8192))
+    return fail(SPM_ERR_INVALID_ARG, "batch walk %d needs at most %d generators per scene (a scene has up to %d)",
+                p.walk, p.walk == 1 ? 512 : 8192, p.maxGmax);
+  return SPM_OK;
 }
 
 }  // namespace
@@ -657,7 +665,7 @@ int spm_batch_prepare(const spm_batch* b, void* d_ws, size_t ws_bytes) {
   char* ws = (char*)d_ws;
   std::vector<Dev> devs;
   Plan p;
-  batch_devs(b, B, ws, devs, p);
+  if ((rc = batch_devs(b, B, ws, devs, p))) return rc;
   const int n = b->n;
   std::vector<int> offs((size_t)STG_COUNT * (n + 1), 0);
   for (int k = 0; k < STG_COUNT; ++k) {
@@ -684,7 +692,7 @@ int spm_build_batch(const spm_batch* b, void* d_ws, size_t ws_bytes, void* strea
   char* ws = (char*)d_ws;
   std::vector<Dev> devs;
   Plan p;
-  batch_devs(b, B, ws, devs, p);
+  if ((rc = batch_devs(b, B, ws, devs, p))) return rc;
   BatchSrc src{(const Dev*)(ws + B.off_tab), (const int*)(ws + B.off_offs), b->n};
   hipStream_t st = (hipStream_t)stream;
   int* ctr = (int*)(ws + B.off_ctr);

@@ -328,8 +328,9 @@ struct BatchSrc {
 struct Plan {
   long long total[STG_COUNT];
   int maxGmax, maxRW, maxW, maxE, maxNC;
-  int tw_mask;   // tile widths present: 1 = 4, 2 = 8, 4 = 16
   size_t pixel_lds, genvis_lds;
+  int pixel_waves;   // batched pixel stage: waves per SIMD asked for (0 = as many as fit)
+  int walk;          // batched pixel stage: forced walk (0 = by the largest generator count)
 };
 
 // host launchers (each queues kernels on the stream and returns hipError_t)

@@ -325,10 +325,18 @@ class BatchBuilder:
     """Outputs and workspace for batched builds of many independent scenes.
 
     tile_w: None (8x8 everywhere), a list of per-scene tile widths (8, 16, 4),
-    or a dict {side: tile_w} such as the one autotune.tune() returns.
+    or a dict {side: tile_w}; pixel_waves: waves per SIMD of the persistent
+    pixel launch (0 = as many as fit); walk: 0 = by the largest generator
+    count, 1-3 forced.  autotune.tune() returns all three as a dict that can be
+    passed as `tuned`.
     """
 
-    def __init__(self, scenes, device="cuda", tile_w=None, check: bool = True):
+    def __init__(self, scenes, device="cuda", tile_w=None, check: bool = True, pixel_waves: int = 0, walk: int = 0,
+                 tuned: dict = None):
+        if tuned is not None:
+            tile_w = tuned.get("tile_w", tile_w)
+            pixel_waves = int(tuned.get("pixel_waves", pixel_waves))
+            walk = int(tuned.get("walk", walk))
         self.ds = [DeviceScene(s, device, check=check) for s in scenes]
         n = len(self.ds)
         if n < 1:
@@ -348,12 +356,21 @@ class BatchBuilder:
         self._scenes = (C.SpmScene * n)(*[d.c for d in self.ds])
         self._outs = (C.SpmOut * n)(*[_out_struct(m) for m in self.maps])
         self._tiles = (C.c_i32 * n)(*tiles)
-        self.c = C.SpmBatch(n, self._scenes, self._outs, self._tiles)
+        self.pixel_waves = int(pixel_waves)
+        self.walk = int(walk)
+        self.c = C.SpmBatch(n, self._scenes, self._outs, self._tiles, self.pixel_waves, self.walk)
         ws = ctypes.c_size_t(0)
         C.check(C.lib().spm_batch_query_sizes(ctypes.byref(self.c), ctypes.byref(ws)))
         self.ws_bytes = int(ws.value)
         self.ws = torch.empty((self.ws_bytes,), dtype=torch.uint8, device=self.ds[0].t["vx"].device)
         C.check(C.lib().spm_batch_prepare(ctypes.byref(self.c), self.ws.data_ptr(), self.ws_bytes))
+
+    def set_options(self, pixel_waves: int = None, walk: int = None):
+        """Change the pixel launch's waves per SIMD or walk (no new spm_batch_prepare needed)."""
+        if pixel_waves is not None:
+            self.pixel_waves = self.c.pixel_waves = int(pixel_waves)
+        if walk is not None:
+            self.walk = self.c.walk = int(walk)
 
     def build(self, stream=None, timer: Timer = None):
         if stream is None:

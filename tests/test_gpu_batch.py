@@ -89,3 +89,33 @@ def test_config4_batch_sampled(oracle_mod, spm):
                 cost=cost, pix=pix, max_ambiguous=0.05)
         one = _single(spm, sc, 8)
         assert np.array_equal(one["dist"], h["dist"]) and np.array_equal(one["parent"], h["parent"]), k
+
+
+def test_autotuned_batch_is_exact_and_not_slower(spm):
+    """The tuner's choice (tile shape per side, waves per SIMD and walk of the pixel launch) gives the same maps
+    bit for bit as the defaults, and is not slower than them on this sample batch (its candidates include the
+    defaults; 15 % allowance for timing noise between the two measurements)."""
+    import torch
+    from paper_1805_08500_amd import autotune
+    scenes = config4_list()[:48]
+    tuned = autotune.tune(scenes, cache_path=None, reps=2)
+    print("[autotune]", {k: v for k, v in tuned.items() if k != "times"}, flush=True)
+    base = spm.BatchBuilder(scenes, check=False)
+    tb = spm.BatchBuilder(scenes, check=False, tuned=tuned)
+
+    def best_ms(bb):
+        bb.build()
+        torch.cuda.synchronize()
+        out = []
+        for _ in range(3):
+            t = spm.Timer()
+            for _ in range(3):
+                bb.build(timer=t)
+            st, n = t.elapsed()
+            out.append(st["total"] / n)
+        return min(out)
+    t_base, t_tuned = best_ms(base), best_ms(tb)
+    print(f"[autotune] default {t_base:.3f} ms, tuned {t_tuned:.3f} ms", flush=True)
+    assert t_tuned <= 1.15 * t_base
+    for k, (a, b) in enumerate(zip(base.maps, tb.maps)):
+        assert torch.equal(a.dist, b.dist) and torch.equal(a.parent, b.parent), k
