@@ -40,6 +40,14 @@ enum { ST_TILES = 0, ST_BATCHES, ST_BOUND, ST_VISWAVE, ST_RELEV, ST_LANEEDGE, ST
 // the walls around the tile or around the generator, the same few edges over
 // and over, so most tests end here.  A hit is exact (the same test the full
 // scan applies to every edge); a miss only falls back to the full test.
+// Least and greatest x * y over x in [x0, x1], y in [y0, y1] (24-bit products, exact here).
+__device__ __forceinline__ int imin_prod(int x0, int x1, int y0, int y1) {
+  return min(min(mul24(x0, y0), mul24(x0, y1)), min(mul24(x1, y0), mul24(x1, y1)));
+}
+__device__ __forceinline__ int imax_prod(int x0, int x1, int y0, int y1) {
+  return max(max(mul24(x0, y0), mul24(x0, y1)), max(mul24(x1, y0), mul24(x1, y1)));
+}
+
 struct OccCache {
   unsigned w, v;   // this lane's edge w -> v (obstacle on the left), x | y << 16 (doubled coordinates
                    // are below 2^15); w == v: an empty slot
@@ -110,28 +118,26 @@ struct OccCache {
       }
     }
   }
-  // Does some cached edge hide the whole box K (kx0..ky1) from the whole box
-  // (bx0..by1)?  The points g that an edge hides the box from form a convex
-  // set (every segment from the box to g crosses the open edge), so K is
-  // hidden iff its four corners are.
+  // Does some cached edge hide the whole box (bx0..by1) from the whole box K
+  // (kx0..ky1)?  For P in the box and k in K, the segment [k, P] properly
+  // crosses the open edge with P strictly on its obstacle side iff
+  // E(P) > 0 > E(k) and P lies strictly between the rays from k through w and
+  // through v (seen from k, v lies clockwise of w): orient(k, w, P) < 0 <
+  // orient(k, v, P).  orient(k, w, P) = cross(P - w, k - w) = ux zy - uy zx
+  // with u = P - w and z = k - w, whose four coordinates range independently
+  // over two boxes, so its extremes over both boxes are interval products:
+  // the test is exact for every P and every k at once.
   __device__ __forceinline__ bool hides_box(int kx0, int ky0, int kx1, int ky1, int bx0, int by0, int bx1,
                                             int by1) const {
     const int wx = (int)(w & 0xffffu), wy = (int)(w >> 16), vx = (int)(v & 0xffffu), vy = (int)(v >> 16);
-    EdgeRec r;
-    r.wx = wx; r.wy = wy; r.vx = vx; r.vy = vy;
-    r.a = wy - vy;
-    r.b = vx - wx;
-    r.c = -(r.a * wx + r.b * wy);
-    r.nc = -r.c;
-    bool all = true;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int gx = (q & 1) ? kx1 : kx0, gy = (q & 2) ? ky1 : ky0;
-      bool rel, occ;
-      edge_vs_cone(r, gx, gy, bx0, by0, bx1, by1, bx0 - gx, bx1 - gx, by0 - gy, by1 - gy, rel, occ);
-      all = all && occ;
-    }
-    return ballot(all) != 0ull;
+    const int a = wy - vy, b = vx - wx, c = -(a * wx + b * wy);
+    const int loEB = mad24(a, a > 0 ? bx0 : bx1, mad24(b, b > 0 ? by0 : by1, c));
+    const int hiEK = mad24(a, a > 0 ? kx1 : kx0, mad24(b, b > 0 ? ky1 : ky0, c));
+    const int fw_max = imax_prod(bx0 - wx, bx1 - wx, ky0 - wy, ky1 - wy) - imin_prod(by0 - wy, by1 - wy, kx0 - wx,
+                                                                                    kx1 - wx);
+    const int fv_min = imin_prod(bx0 - vx, bx1 - vx, ky0 - vy, ky1 - vy) - imax_prod(by0 - vy, by1 - vy, kx0 - vx,
+                                                                                    kx1 - vx);
+    return ballot(loEB > 0 && hiEK < 0 && fw_max < 0 && fv_min > 0) != 0ull;
   }
 };
 
