@@ -161,8 +161,9 @@ int spm_timer_elapsed(spm_timer* t, float* ms /* [SPM_N_STAGES] */, int32_t* n_b
  * visibility tests, [4] edge relevance or seed-search edge tests (x64 lanes),
  * [5] lane edge tests, [6] tests ended by one edge hiding the whole tile, [7]
  * accepted candidates, [8] occluder-cache tests, [9] occluder-cache hits,
- * [10] lane closest-point computations for segment sources; the rest stay
- * zero. */
+ * [10] lane closest-point computations for segment sources, [11] cluster
+ * members within the bound, [12] cluster members tried, [13] clusters hidden
+ * whole; the rest stay zero. */
 #define SPM_N_STATS 16
 typedef struct {
   int32_t tile_w, tile_h;

@@ -28,7 +28,7 @@
 namespace spm {
 
 enum { ST_TILES = 0, ST_BATCHES, ST_BOUND, ST_VISWAVE, ST_RELEV, ST_LANEEDGE, ST_OCCL, ST_ACCEPT, ST_CACHE_TEST,
-       ST_CACHE_HIT, ST_SEG_LANE, ST_COUNT };
+       ST_CACHE_HIT, ST_SEG_LANE, ST_CL_MEMBERS, ST_CL_TRIED, ST_CL_HIDDEN, ST_COUNT };
 
 // Occluder cache of one tile: one obstacle edge per lane.  The exact test of
 // a candidate generator g against a tile first asks whether a single edge hides
@@ -794,6 +794,7 @@ __device__ __forceinline__ int tile_work(int tile, int W, int H, int W32, int G,
         if (STATS) st[ST_CACHE_TEST] += 1;
         if (oc.hides_box(cx0, cy0, cx1, cy1, bx0, by0, bx1, by1)) {
           if (STATS) st[ST_CACHE_HIT] += 1;
+          if (STATS) st[ST_CL_HIDDEN] += 1;
           continue;
         }
         int k = -1;
@@ -808,6 +809,7 @@ __device__ __forceinline__ int tile_work(int tile, int W, int H, int W32, int G,
           }
         }
         u64 mm = ballot(k >= 0 && ek <= UB);
+        if (STATS) st[ST_CL_MEMBERS] += __popcll(mm);
         while (mm) {
           // the least estimate first (the likely winner tightens the bounds for the rest)
           const float e_here = ((mm >> lane) & 1ull) ? ek : INFINITY;
@@ -815,15 +817,11 @@ __device__ __forceinline__ int tile_work(int tile, int W, int H, int W32, int G,
           const int jl = first_bit(ballot(__float_as_uint(e_here) == mk) & mm);
           mm &= ~(1ull << jl);
           if (__uint_as_float(mk) > UB) break;   // the bounds tightened since: the rest are larger still
-          const float gc = readlane_f(kc, jl);
-          const int kx0 = readlane_i(b.x, jl), ky0 = readlane_i(b.y, jl), kx1 = readlane_i(b.z, jl),
-                    ky1 = readlane_i(b.w, jl);
-          if (!(box_may_win(gc, kx0, ky0, kx1, ky1, qx0, qy0, qx1 - 2, qy1 - 2, ubq[0]) ||
-                box_may_win(gc, kx0, ky0, kx1, ky1, qx1, qy0, qx1 + TW - 2, qy1 - 2, ubq[1]) ||
-                box_may_win(gc, kx0, ky0, kx1, ky1, qx0, qy1, qx1 - 2, qy1 + TH - 2, ubq[2]) ||
-                box_may_win(gc, kx0, ky0, kx1, ky1, qx1, qy1, qx1 + TW - 2, qy1 + TH - 2, ubq[3])))
-            continue;
-          try_gen(readlane_i(k, jl), gc, kx0, ky0, kx1, ky1);
+          // (the quadrant bounds of the other walks reject about 1 % of these members here: not worth
+          // their uniform float work; try_gen's per-lane bound decides)
+          if (STATS) st[ST_CL_TRIED] += 1;
+          try_gen(readlane_i(k, jl), readlane_f(kc, jl), readlane_i(b.x, jl), readlane_i(b.y, jl),
+                  readlane_i(b.z, jl), readlane_i(b.w, jl));
         }
       }
     } else if constexpr (WALK == kWalkRefill) {
