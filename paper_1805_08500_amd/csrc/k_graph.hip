@@ -134,7 +134,8 @@ __device__ __forceinline__ void genvis_points(const Dev& d, const Geo& geo, int 
 // interior angle.  Only the chunks whose box meets the segment's box and
 // straddles or touches its line can hold such an edge or vertex.
 __device__ __forceinline__ bool pair_visible(const Geo& geo, int px, int py, bool pvert, int pux, int puy, int pnx,
-                                             int pny, int gx, int gy, int gux, int guy, int gnx, int gny) {
+                                             int pny, int gx, int gy, int gux, int guy, int gnx, int gny,
+                                             int* found = nullptr) {
   const int lane = lane_id();
   if (into_interior(gux, guy, gx, gy, gnx, gny, px - gx, py - gy)) return false;
   if (pvert && into_interior(pux, puy, px, py, pnx, pny, gx - px, gy - py)) return false;
@@ -175,11 +176,81 @@ __device__ __forceinline__ bool pair_visible(const Geo& geo, int px, int py, boo
           }
         }
       }
-      if (ballot(blk)) return false;
+      const u64 bm = ballot(blk);
+      if (bm) {
+        if (found) *found = readlane(e, first_bit(bm));
+        return false;
+      }
     }
   }
   return true;
 }
+
+// Occluder cache of one row of the pair visibility, one edge per lane: edges
+// that the row's corner g lies strictly outside of (only those can block a
+// segment from g), first the nearby ones, then every edge a full test found
+// blocking.  The pair (P, g) is blocked by a cached edge when P lies strictly
+// on its obstacle side and the line P-g separates its endpoints strictly (a
+// proper crossing into the obstacle: the rule of pair_visible); a hit is
+// exact, a miss falls back to pair_visible.
+struct PairCache {
+  unsigned w, v;   // x | y << 16 of the edge's endpoints; w == v: empty
+  int slot;
+  __device__ __forceinline__ void fill_near(const Geo& geo, int gx, int gy) {
+    const int lane = lane_id();
+    w = v = 0u;
+    slot = 0;
+    for (int cb = 0; cb < geo.NC && slot < 64; cb += kWave) {
+      const int ci = cb + lane;
+      int gap = 1 << 30;
+      if (ci < geo.NC) {
+        const int4 bb = geo.chunks[ci];
+        gap = max(max(max(bb.x - gx, gx - bb.z), max(bb.y - gy, gy - bb.w)), 0);
+      }
+      const u64 near = ballot(gap <= 64), mid = ballot(gap > 64 && gap <= 256);
+      for (int cl = 0; cl < 2 && slot < 64; ++cl) {
+        u64 cm = cl ? mid : near;
+        while (cm && slot < 64) {
+          const int chunk = cb + first_bit(cm);
+          cm &= cm - 1;
+          const int e = chunk * kChunk + lane;
+          bool ok = false;
+          EdgeRec r = {0, 0, 0, 0, 0, 0, 0, 0};
+          if (e < geo.E) {
+            r = geo.edges[e];
+            ok = mad24(r.a, gx, mad24(r.b, gy, r.c)) < 0;
+          }
+          u64 om = ballot(ok);
+          while (om && slot < 64) {
+            const int ql = first_bit(om);
+            om &= om - 1;
+            const unsigned pw = (unsigned)readlane(r.wx, ql) | ((unsigned)readlane(r.wy, ql) << 16);
+            const unsigned pv = (unsigned)readlane(r.vx, ql) | ((unsigned)readlane(r.vy, ql) << 16);
+            if (lane == slot) { w = pw; v = pv; }
+            ++slot;
+          }
+        }
+      }
+    }
+  }
+  __device__ __forceinline__ void insert(const EdgeRec& r) {   // r wave-uniform, g strictly outside its line
+    if (lane_id() == (slot & 63)) {
+      w = (unsigned)r.wx | ((unsigned)r.wy << 16);
+      v = (unsigned)r.vx | ((unsigned)r.vy << 16);
+    }
+    ++slot;
+  }
+  // is the segment from P to g blocked by a cached edge?
+  __device__ __forceinline__ bool blocks(int px, int py, int gx, int gy) const {
+    const int wx = (int)(w & 0xffffu), wy = (int)(w >> 16), vx = (int)(v & 0xffffu), vy = (int)(v >> 16);
+    const int a = wy - vy, b = vx - wx, c = -(a * wx + b * wy);
+    const int A = py - gy, B = gx - px;
+    const int C = -(mul24(A, px) + mul24(B, py));
+    const int ow = mad24(A, wx, mad24(B, wy, C)), ov = mad24(A, vx, mad24(B, vy, C));
+    const bool blk = mad24(a, px, mad24(b, py, c)) > 0 && (float)ow * (float)ov < 0.0f;
+    return ballot(blk) != 0ull;
+  }
+};
 
 // Point columns by pairs (few edges): one wavefront per row of a
 // kGvPairRows x kGvPairRows block of the lower triangle of the matrix (blocks
@@ -265,6 +336,68 @@ __device__ __forceinline__ void genvis_pairs(const Dev& d, const Geo& geo, int w
   if (lane < nu && ((bits >> lane) & 1u) && u >= nsrc) atomicOr(&d.vis[(size_t)u * RW + (r >> 6)], 1ull << (r & 63));
 }
 
+// Point columns by row segments (many generators): wavefront wid takes the
+// kGvSeg pairs (row corner g, columns u in [s kGvSeg, min((s + 1) kGvSeg, r)))
+// of row r, one pair at a time: the corner rules, then the row's occluder
+// cache, then pair_visible (whose blocking edge joins the cache).  On the maze
+// almost every pair is blocked by a wall next to g, so the cache decides
+// nearly all of them.  Bits as in genvis_pairs.
+template <class S>
+__device__ __forceinline__ void genvis_rows(const Dev& d, const Geo& geo, int wid) {
+  const int RW = d.RW;
+  const int G = uni(d.misc[MISC_G]);
+  const int nsrc = d.np + d.ns;
+  const int lane = lane_id();
+  relax_init(d, wid, G, nsrc);
+  if ((long long)wid >= rowseg_prefix(d.Gmax)) return;
+  int lo = 0, hi = d.Gmax;   // the row: the largest r with rowseg_prefix(r) <= wid
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (rowseg_prefix(mid) <= wid) lo = mid;
+    else hi = mid;
+  }
+  const int r = lo, s = wid - (int)rowseg_prefix(r);
+  if (r >= G || r < nsrc) return;   // only corner rows are read
+  const int gpos = uni(d.gorder[r]);
+  const int gx = uni(d.gens[gpos].x), gy = uni(d.gens[gpos].y);
+  const int gux = uni(d.gens[gpos].ux), guy = uni(d.gens[gpos].uy), gnx = uni(d.gens[gpos].nx),
+            gny = uni(d.gens[gpos].ny);
+  const int u0 = s * kGvSeg, u1 = min(u0 + kGvSeg, r);
+  PairCache pc;
+  pc.fill_near(geo, gx, gy);
+  for (int ub = u0; ub < u1; ub += kWave) {
+    const int u = ub + lane;
+    const bool valid = u < u1;
+    GenRec gu = {};
+    if (valid) gu = d.gens[d.gorder[u]];
+    u64 todo = ballot(valid && gu.kind != SPM_GEN_SEGMENT);
+    bool seen = false;
+    while (todo) {
+      const int j = first_bit(todo);
+      todo &= todo - 1;
+      const int px = readlane(gu.x, j), py = readlane(gu.y, j);
+      const bool pv = readlane(gu.kind, j) == SPM_GEN_VERTEX;
+      const int pux = readlane(gu.ux, j), puy = readlane(gu.uy, j), pnx = readlane(gu.nx, j),
+                pny = readlane(gu.ny, j);
+      bool vj = false;
+      if (!into_interior(gux, guy, gx, gy, gnx, gny, px - gx, py - gy) &&
+          !(pv && into_interior(pux, puy, px, py, pnx, pny, gx - px, gy - py)) && !pc.blocks(px, py, gx, gy)) {
+        int found = -1;
+        vj = pair_visible(geo, px, py, pv, pux, puy, pnx, pny, gx, gy, gux, guy, gnx, gny, &found);
+        // a blocker found by the vertex rule may face away from g: the cache test holds only for edges g is outside of
+        if (found >= 0) {
+          const EdgeRec fr = geo.edges[found];
+          if (mad24(fr.a, gx, mad24(fr.b, gy, fr.c)) < 0) pc.insert(fr);
+        }
+      }
+      if (lane == j) seen = vj;
+    }
+    const u64 bits = ballot(seen);
+    if (bits && lane == 0) atomicOr(&d.vis[(size_t)r * RW + (ub >> 6)], bits);
+    if (seen && u >= nsrc) atomicOr(&d.vis[(size_t)u * RW + (r >> 6)], 1ull << (r & 63));
+  }
+}
+
 __device__ __forceinline__ void genvis_segments(const Dev& d, const Geo& geo, int item) {
   const int nsrc = d.np + d.ns;
   const int nblk = (d.Gmax - nsrc + kSegCols - 1) / kSegCols;
@@ -321,7 +454,8 @@ __global__ __launch_bounds__(256) void k_genvis(S src, int nblk_points) {
     geo.chunks = s_chunks;
   }
   if (pts) {
-    if (d.gv_sub <= 0) genvis_pairs<S>(d, geo, item * 4 + (threadIdx.x >> 6), d.gv_sub < 0);
+    if (d.gv_sub == -2) genvis_rows<S>(d, geo, item * 4 + (threadIdx.x >> 6));
+    else if (d.gv_sub <= 0) genvis_pairs<S>(d, geo, item * 4 + (threadIdx.x >> 6), d.gv_sub < 0);
     else genvis_points<S>(d, geo, item * 4 + (threadIdx.x >> 6));
   } else {
     genvis_segments(d, geo, item);

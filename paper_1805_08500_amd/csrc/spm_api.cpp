@@ -346,6 +346,8 @@ void fill_dev(Dev& d, const spm_scene* s, const spm_out* out, char* ws, const La
   if (L.Gmax >= SPM_GV_PAIR_MIN_GEN) d.gv_sub = 0;
   // up to kGvSpreadMaxGen generators each wavefront takes pairs from all over the triangle
   if (d.gv_sub == 0 && L.Gmax <= kGvSpreadMaxGen) d.gv_sub = -1;
+  // beyond, row segments with an occluder cache
+  if (d.gv_sub == 0 && SPM_GV_ROWS) d.gv_sub = -2;
   d.stats = stats;
 }
 

@@ -66,6 +66,19 @@ constexpr int kGvPairRows = SPM_GV_PAIR_ROWS;   // generator visibility by pairs
 #define SPM_GV_SPREAD_MAX_GEN 1024
 #endif
 constexpr int kGvSpreadMaxGen = SPM_GV_SPREAD_MAX_GEN;   // pairs dealt round-robin over the triangle up to this many generators
+#ifndef SPM_GV_ROWS
+#define SPM_GV_ROWS 1
+#endif
+constexpr int kGvSeg = 256;   // beyond: one wavefront per (row, 256 columns) with an occluder cache
+
+// Generator visibility by row segments: row r holds the pairs (r, u < r) in
+// ceil(r / kGvSeg) items; the items of rows 0 .. N-1 number
+// sum_{r < N} ceil(r / kGvSeg) = L q (q + 1) / 2 + (q + 1) (N - 1 - q L), q = (N - 1) / L.
+__host__ __device__ inline long long rowseg_prefix(long long N) {
+  if (N <= 1) return 0;
+  const long long L = kGvSeg, q = (N - 1) / L;
+  return L * q * (q + 1) / 2 + (q + 1) * (N - 1 - q * L);
+}
 
 // One obstacle edge w -> v (obstacle on the left), with its line function
 // E(x, y) = a x + b y + c, positive on the obstacle side.
@@ -230,7 +243,8 @@ struct Dev {
   int walk;        // pixel stage: 0 by generator count, else 1 + the walk (cached, refilled, cost order)
   int gv_sub;      // generator visibility: columns per wavefront (64, 32 or 16); 0: one pair at a time,
                    // lanes over edges (kGvPairRows x kGvPairRows blocks of the lower triangle);
-                   // -1: the same pairs dealt round-robin over the triangle
+                   // -1: the same pairs dealt round-robin over the triangle; -2: row segments of
+                   // kGvSeg pairs with an occluder cache
   u64* stats;
 };
 
@@ -276,6 +290,7 @@ __host__ __device__ inline int stage_count(const Dev& d, int stage) {
     case STG_CHUNK: return d.NC;
     case STG_ROW: return d.H;
     case STG_GVBLK: {
+      if (d.gv_sub == -2) return (int)((rowseg_prefix(d.Gmax) + 3) / 4);
       if (d.gv_sub <= 0) {
         const long long B = (d.Gmax + kGvPairRows - 1) / kGvPairRows;
         return (int)((kGvPairRows * (B * (B + 1) / 2) + 3) / 4);
