@@ -48,7 +48,7 @@ ALG = {
 # instrumented counters (spm_build_opts.d_stats order)
 STAT_NAMES = ["tiles", "walk_steps", "lane_bound", "wave_vis", "relevance", "lane_edge", "one_edge_hides", "accept",
               "occ_cache_tests", "occ_cache_hits", "segment_lanes", "cluster_members", "cluster_members_tried",
-              "clusters_hidden"]
+              "clusters_hidden", "cluster_members_umbra"]
 WORKLOADS = {
     "maze2048": "maze-2048: 2048x2048 grid, randomized-DFS maze of 64x64 cells (32 px, 4 px walls, exact union "
                 "boundary), 4 exit segment sources on the outer boundary, seed %d",

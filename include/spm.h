@@ -163,7 +163,8 @@ int spm_timer_elapsed(spm_timer* t, float* ms /* [SPM_N_STAGES] */, int32_t* n_b
  * accepted candidates, [8] occluder-cache tests, [9] occluder-cache hits,
  * [10] lane closest-point computations for segment sources, [11] cluster
  * members within the bound, [12] cluster members tried, [13] clusters hidden
- * whole; the rest stay zero. */
+ * whole, [14] cluster members that a cached edge hides from the whole tile
+ * (not tried); the rest stay zero. */
 #define SPM_N_STATS 16
 typedef struct {
   int32_t tile_w, tile_h;

@@ -28,7 +28,12 @@
 namespace spm {
 
 enum { ST_TILES = 0, ST_BATCHES, ST_BOUND, ST_VISWAVE, ST_RELEV, ST_LANEEDGE, ST_OCCL, ST_ACCEPT, ST_CACHE_TEST,
-       ST_CACHE_HIT, ST_SEG_LANE, ST_CL_MEMBERS, ST_CL_TRIED, ST_CL_HIDDEN, ST_COUNT };
+       ST_CACHE_HIT, ST_SEG_LANE, ST_CL_MEMBERS, ST_CL_TRIED, ST_CL_HIDDEN, ST_CL_UMBRA, ST_COUNT };
+
+// Packs two values of magnitude below 2^15 into one register, and back.
+__device__ __forceinline__ int pack16(int lo, int hi) { return (int)(((unsigned)lo & 0xffffu) | ((unsigned)hi << 16)); }
+__device__ __forceinline__ int lo16(int x) { return (int)(short)(x & 0xffff); }
+__device__ __forceinline__ int hi16(int x) { return x >> 16; }
 
 // Occluder cache of one tile: one obstacle edge per lane.  The exact test of
 // a candidate generator g against a tile first asks whether a single edge hides
@@ -40,21 +45,79 @@ enum { ST_TILES = 0, ST_BATCHES, ST_BOUND, ST_VISWAVE, ST_RELEV, ST_LANEEDGE, ST
 // the walls around the tile or around the generator, the same few edges over
 // and over, so most tests end here.  A hit is exact (the same test the full
 // scan applies to every edge); a miss only falls back to the full test.
-// Least and greatest x * y over x in [x0, x1], y in [y0, y1] (24-bit products, exact here).
-__device__ __forceinline__ int imin_prod(int x0, int x1, int y0, int y1) {
-  return min(min(mul24(x0, y0), mul24(x0, y1)), min(mul24(x1, y0), mul24(x1, y1)));
-}
-__device__ __forceinline__ int imax_prod(int x0, int x1, int y0, int y1) {
-  return max(max(mul24(x0, y0), mul24(x0, y1)), max(mul24(x1, y0), mul24(x1, y1)));
-}
-
 struct OccCache {
   unsigned w, v;   // this lane's edge w -> v (obstacle on the left), x | y << 16 (doubled coordinates
                    // are below 2^15); w == v: an empty slot
   int slot;        // next slot to fill (wave-uniform)
+  // The umbra of the tile box U (ux0..uy1, the active pixels' box) behind this
+  // lane's edge: the points g that the edge hides from every point of U.  For
+  // U strictly on the obstacle side (E > 0 on U) and g strictly on the free
+  // side (E(g) < 0), seen from g the edge runs clockwise from w to v, and U lies
+  // strictly inside that wedge iff every corner P of U satisfies
+  // cross(P - w, g - w) < 0 and cross(P - v, g - v) > 0.  Over the corners
+  // these are half-planes through w (through v); with E(g) < 0 the binding one
+  // is the corner direction most counter-clockwise seen from w (most clockwise
+  // seen from v).  So the umbra is the intersection of three open half-planes
+  // h_i(g) = A_i gx + B_i gy + C_i < 0: the edge line (i = 0), the tangent
+  // through w (1) and the tangent through v (2).  |A|, |B| < 2^15, |C| < 2^30,
+  // so each h_i is an exact int32 value.  A lane whose edge does not have U
+  // strictly on its obstacle side (or an empty slot) gets h_1 = 1: never.
+  int ab0, c0, ab1, c1, ab2, c2;   // (A_i | B_i << 16, C_i)
+  int ux0, uy0, ux1, uy1;          // U (wave-uniform)
   __device__ __forceinline__ void reset() {
     w = v = 0u;
     slot = 0;
+    ux0 = uy0 = ux1 = uy1 = 0;
+    ab0 = c0 = ab1 = ab2 = c2 = 0;
+    c1 = 1;
+  }
+  // Sets this lane's umbra from its edge (every lane; exact integer work).
+  __device__ __forceinline__ void set_umbra() {
+    const int wx = (int)(w & 0xffffu), wy = (int)(w >> 16), vx = (int)(v & 0xffffu), vy = (int)(v >> 16);
+    const int a = wy - vy, b = vx - wx, c = -(a * wx + b * wy);
+    const int loE = mad24(a, a > 0 ? ux0 : ux1, mad24(b, b > 0 ? uy0 : uy1, c));
+    // corner directions from w: keep the most counter-clockwise (cross(d, e) > 0: e is counter-clockwise of d)
+    int dx = ux0 - wx, dy = uy0 - wy;
+    auto ccw = [&](int ex, int ey) {
+      if (mul24(dx, ey) - mul24(dy, ex) > 0) { dx = ex; dy = ey; }
+    };
+    ccw(ux1 - wx, uy0 - wy);
+    ccw(ux0 - wx, uy1 - wy);
+    ccw(ux1 - wx, uy1 - wy);
+    // from v: keep the most clockwise
+    int ex = ux0 - vx, ey = uy0 - vy;
+    auto cw = [&](int fx, int fy) {
+      if (mul24(ex, fy) - mul24(ey, fx) < 0) { ex = fx; ey = fy; }
+    };
+    cw(ux1 - vx, uy0 - vy);
+    cw(ux0 - vx, uy1 - vy);
+    cw(ux1 - vx, uy1 - vy);
+    const bool ok = loE > 0;
+    ab0 = pack16(a, b);
+    c0 = c;
+    // cross(d, g - w) < 0:  -dy gx + dx gy + (dy wx - dx wy) < 0
+    ab1 = ok ? pack16(-dy, dx) : 0;
+    c1 = ok ? mul24(dy, wx) - mul24(dx, wy) : 1;
+    // cross(e, g - v) > 0:  ey gx - ex gy + (ex vy - ey vx) < 0
+    ab2 = pack16(ey, -ex);
+    c2 = mul24(ex, vy) - mul24(ey, vx);
+  }
+  // Does some cached edge hide the point g from the whole of U?
+  __device__ __forceinline__ bool umbra_hides(int gx, int gy) const {
+    const int h0 = mad24(lo16(ab0), gx, mad24(hi16(ab0), gy, c0));
+    const int h1 = mad24(lo16(ab1), gx, mad24(hi16(ab1), gy, c1));
+    const int h2 = mad24(lo16(ab2), gx, mad24(hi16(ab2), gy, c2));
+    return ballot(max(max(h0, h1), h2) < 0) != 0ull;
+  }
+  // Does some cached edge hide the whole box K (kx0..ky1) from the whole of
+  // U?  K lies in the (convex) umbra iff the largest value of each h_i over K
+  // is negative.
+  __device__ __forceinline__ bool umbra_hides_box(int kx0, int ky0, int kx1, int ky1) const {
+    auto hmax = [&](int ab, int c) {
+      const int A = lo16(ab), B = hi16(ab);
+      return mad24(A, A > 0 ? kx1 : kx0, mad24(B, B > 0 ? ky1 : ky0, c));
+    };
+    return ballot(max(max(hmax(ab0, c0), hmax(ab1, c1)), hmax(ab2, c2)) < 0) != 0ull;
   }
   // does some cached edge hide the box (bx0..by1) from g?
   __device__ __forceinline__ bool hides(int gx, int gy, int bx0, int by0, int bx1, int by1) const {
@@ -75,6 +138,11 @@ struct OccCache {
       v = (unsigned)r.vx | ((unsigned)r.vy << 16);
     }
     ++slot;
+  }
+  // the same, keeping the umbrae current
+  __device__ __forceinline__ void insert_umbra(const EdgeRec& r) {
+    insert(r);
+    set_umbra();
   }
   // Fills the slots with edges near the box (bx0..by1) whose line has the
   // whole box strictly on its obstacle side (only such an edge can hide the
@@ -118,27 +186,6 @@ struct OccCache {
       }
     }
   }
-  // Does some cached edge hide the whole box (bx0..by1) from the whole box K
-  // (kx0..ky1)?  For P in the box and k in K, the segment [k, P] properly
-  // crosses the open edge with P strictly on its obstacle side iff
-  // E(P) > 0 > E(k) and P lies strictly between the rays from k through w and
-  // through v (seen from k, v lies clockwise of w): orient(k, w, P) < 0 <
-  // orient(k, v, P).  orient(k, w, P) = cross(P - w, k - w) = ux zy - uy zx
-  // with u = P - w and z = k - w, whose four coordinates range independently
-  // over two boxes, so its extremes over both boxes are interval products:
-  // the test is exact for every P and every k at once.
-  __device__ __forceinline__ bool hides_box(int kx0, int ky0, int kx1, int ky1, int bx0, int by0, int bx1,
-                                            int by1) const {
-    const int wx = (int)(w & 0xffffu), wy = (int)(w >> 16), vx = (int)(v & 0xffffu), vy = (int)(v >> 16);
-    const int a = wy - vy, b = vx - wx, c = -(a * wx + b * wy);
-    const int loEB = mad24(a, a > 0 ? bx0 : bx1, mad24(b, b > 0 ? by0 : by1, c));
-    const int hiEK = mad24(a, a > 0 ? kx1 : kx0, mad24(b, b > 0 ? ky1 : ky0, c));
-    const int fw_max = imax_prod(bx0 - wx, bx1 - wx, ky0 - wy, ky1 - wy) - imin_prod(by0 - wy, by1 - wy, kx0 - wx,
-                                                                                    kx1 - wx);
-    const int fv_min = imin_prod(bx0 - vx, bx1 - vx, ky0 - vy, ky1 - vy) - imax_prod(by0 - vy, by1 - vy, kx0 - vx,
-                                                                                    kx1 - vx);
-    return ballot(loEB > 0 && hiEK < 0 && fw_max < 0 && fv_min > 0) != 0ull;
-  }
 };
 
 // Takes the least estimate out of a register cache of N slots per lane (lane
@@ -165,19 +212,27 @@ __device__ __forceinline__ int slot_pop(float (&ec)[N], float& v) {
   return wl + 64 * ws;
 }
 
-// Box (doubled pixel-centre coordinates) of the lanes set in m.
+// Least unsigned value over lanes 0..7, returned in every lane (the caller
+// reads it from lane 0's group): two quad exchanges, then the half-row mirror
+// (lane i of each group of 8 takes lane 7 - i).
+__device__ __forceinline__ unsigned min8_u32(unsigned v) {
+  v = min(v, (unsigned)__builtin_amdgcn_update_dpp(-1, (int)v, 0xB1, 0xF, 0xF, false));    // quad_perm 1,0,3,2
+  v = min(v, (unsigned)__builtin_amdgcn_update_dpp(-1, (int)v, 0x4E, 0xF, 0xF, false));    // quad_perm 2,3,0,1
+  v = min(v, (unsigned)__builtin_amdgcn_update_dpp(-1, (int)v, 0x141, 0xF, 0xF, false));   // row_half_mirror
+  return (unsigned)readlane((int)v, 0);
+}
+
+// Box (doubled pixel-centre coordinates) of the lanes set in m (m != 0; a
+// wave-uniform mask, so this is scalar work).  Lane l is column l % TW of row
+// l / TW: the rows are the first and last set bit divided by TW, the columns
+// the set bits of the OR of all rows (folded by halving shifts).
 template <int TW>
 __device__ __forceinline__ void mask_box(u64 m, int i0, int j0, int& bx0, int& by0, int& bx1, int& by1) {
-  constexpr int TH = 64 / TW;
-  constexpr u64 rowm = (TW == 64) ? ~0ull : ((1ull << TW) - 1ull);
-  unsigned cols = 0;
-  int r0 = TH, r1 = -1;
+  u64 f = m;
 #pragma unroll
-  for (int r = 0; r < TH; ++r) {
-    const unsigned bits = (unsigned)((m >> (r * TW)) & rowm);
-    cols |= bits;
-    if (bits) { r0 = min(r0, r); r1 = r; }
-  }
+  for (int s = 32; s >= TW; s >>= 1) f |= f >> s;
+  const unsigned cols = (unsigned)f & ((1u << TW) - 1u);
+  const int r0 = __builtin_ctzll(m) / TW, r1 = (63 - __builtin_clzll(m)) / TW;
   const int c0 = __builtin_ctz(cols), c1 = 31 - __builtin_clz(cols);
   bx0 = 2 * (i0 + c0) + 1;
   bx1 = 2 * (i0 + c1) + 1;
@@ -708,7 +763,10 @@ __device__ __forceinline__ int tile_work(int tile, int W, int H, int W32, int G,
         int found = -1;
         bl |= wave_blocked_uniform<STATS>(geo, px, py, m, gx, gy, gv, gv ? nb.x : 0, gv ? nb.y : 0, gv ? nb.z : 0,
                                           gv ? nb.w : 0, false, 0, 0, 0, 0, bx0, by0, bx1, by1, occ, st, &found);
-        if (found >= 0) oc.insert(geo.edge(found));
+        if (found >= 0) {
+          if constexpr (WALK == kWalkCluster) oc.insert_umbra(geo.edge(found));
+          else oc.insert(geo.edge(found));
+        }
       }
       if (mI) {
         if (STATS) st[ST_VISWAVE] += 1;
@@ -774,6 +832,8 @@ __device__ __forceinline__ int tile_work(int tile, int W, int H, int W32, int G,
       int bx0, by0, bx1, by1;
       mask_box<TW>(act, i0, j0, bx0, by0, bx1, by1);
       oc.fill_near(geo, bx0, by0, bx1, by1);
+      oc.ux0 = bx0; oc.uy0 = by0; oc.ux1 = bx1; oc.uy1 = by1;
+      oc.set_umbra();
       auto est_of = [&](const int4& b, float c) -> float {
         const float dx = (float)max(max(b.x - bx1, bx0 - b.z), 0), dy = (float)max(max(b.y - by1, by0 - b.w), 0);
         return (c + 0.5f * fsqrt(dx * dx + dy * dy)) * (1.0f - 4e-6f);
@@ -792,7 +852,7 @@ __device__ __forceinline__ int tile_work(int tile, int W, int H, int W32, int G,
         const int4 kb = tab.clbb[c];
         const int cx0 = uni(kb.x), cy0 = uni(kb.y), cx1 = uni(kb.z), cy1 = uni(kb.w);
         if (STATS) st[ST_CACHE_TEST] += 1;
-        if (oc.hides_box(cx0, cy0, cx1, cy1, bx0, by0, bx1, by1)) {
+        if (oc.umbra_hides_box(cx0, cy0, cx1, cy1)) {
           if (STATS) st[ST_CACHE_HIT] += 1;
           if (STATS) st[ST_CL_HIDDEN] += 1;
           continue;
@@ -813,15 +873,21 @@ __device__ __forceinline__ int tile_work(int tile, int W, int H, int W32, int G,
         while (mm) {
           // the least estimate first (the likely winner tightens the bounds for the rest)
           const float e_here = ((mm >> lane) & 1ull) ? ek : INFINITY;
-          const unsigned mk = wave_min_u32(__float_as_uint(e_here));
+          const unsigned mk = min8_u32(__float_as_uint(e_here));
           const int jl = first_bit(ballot(__float_as_uint(e_here) == mk) & mm);
           mm &= ~(1ull << jl);
           if (__uint_as_float(mk) > UB) break;   // the bounds tightened since: the rest are larger still
           // (the quadrant bounds of the other walks reject about 1 % of these members here: not worth
           // their uniform float work; try_gen's per-lane bound decides)
+          const int gx0 = readlane_i(b.x, jl), gy0 = readlane_i(b.y, jl), gx1 = readlane_i(b.z, jl),
+                    gy1 = readlane_i(b.w, jl);
+          // a point or corner that a cached edge hides from the whole tile: nothing to try
+          if (gx0 == gx1 && gy0 == gy1 && oc.umbra_hides(gx0, gy0)) {
+            if (STATS) st[ST_CL_UMBRA] += 1;
+            continue;
+          }
           if (STATS) st[ST_CL_TRIED] += 1;
-          try_gen(readlane_i(k, jl), readlane_f(kc, jl), readlane_i(b.x, jl), readlane_i(b.y, jl),
-                  readlane_i(b.z, jl), readlane_i(b.w, jl));
+          try_gen(readlane_i(k, jl), readlane_f(kc, jl), gx0, gy0, gx1, gy1);
         }
       }
     } else if constexpr (WALK == kWalkRefill) {
