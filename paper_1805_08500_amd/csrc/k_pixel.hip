@@ -646,8 +646,10 @@ struct TabFull {
   const GenRec* sgen;
   const float* cost;
   const int4* bb;
-  // spatial clusters (cluster walk): kCluster sorted positions per cluster, their box and least cost
-  const int* clk;
+  // spatial clusters (cluster walk): per member (sorted position, float cost bits) and box, kCluster
+  // per cluster; per cluster the box and least cost
+  const int2* clk;
+  const int4* clmb;
   const int4* clbb;
   const float* clc;
   int ncl;
@@ -661,6 +663,32 @@ struct TabFull {
   }
   __device__ __forceinline__ int id(int k) const { return sgen[k].id; }
 };
+// Edge records packed for LDS (the cluster walk of scenes whose full tables
+// do not fit): w and v as x | y << 16 (doubled coordinates are below 2^15);
+// the line terms are recomputed, the same integers the ingest stage stores.
+// The edge reads of the occluder searches then stay in the CU.
+struct GeoPacked {
+  const uint2* pe;
+  const EdgeExt* ext;
+  const int4* chunks;
+  int E, NC;
+  __device__ __forceinline__ EdgeRec edge(int e) const {
+    const uint2 p = pe[e];
+    EdgeRec r;
+    r.wx = (int)(p.x & 0xffffu);
+    r.wy = (int)(p.x >> 16);
+    r.vx = (int)(p.y & 0xffffu);
+    r.vy = (int)(p.y >> 16);
+    r.a = r.wy - r.vy;
+    r.b = r.vx - r.wx;
+    r.c = -(r.a * r.wx + r.b * r.wy);
+    r.nc = -r.c;
+    return r;
+  }
+  __device__ __forceinline__ int4 chunk(int c) const { return chunks[c]; }
+};
+size_t packed_edge_lds_bytes(int E, int NC) { return (size_t)NC * 16 + (size_t)E * 8; }
+
 template <int TW, bool STATS, int WALK, class TAB, class GEO>
 __device__ __forceinline__ int tile_work(int tile, int W, int H, int W32, int G, const unsigned* __restrict__ inside,
                                          const TAB& tab, const GEO& geo, float* __restrict__ dist,
@@ -861,10 +889,12 @@ __device__ __forceinline__ int tile_work(int tile, int W, int H, int W32, int G,
         float kc = INFINITY, ek = INFINITY;
         int4 b = make_int4(0, 0, 0, 0);
         if (lane < kCluster) {
-          k = tab.clk[c * kCluster + lane];
+          // the members' records are stored cluster by cluster: two coalesced loads
+          const int2 kk = tab.clk[c * kCluster + lane];
+          b = tab.clmb[c * kCluster + lane];
+          k = kk.x;
           if (k >= 0) {
-            b = tab.box(k);
-            kc = tab.c(k);
+            kc = __int_as_float(kk.y);
             ek = est_of(b, kc);
           }
         }
@@ -1218,7 +1248,8 @@ __global__ __launch_bounds__(kPixelThreads, WALK == kWalkCached ? SPM_PIXEL_MIN_
 void k_pixel(int W, int H, int W32, int Gmax, int* misc, const unsigned* __restrict__ inside,
              const GenRec* __restrict__ sgen_g, const float* __restrict__ sgcost_g, const int4* __restrict__ sgbb_g,
              const EdgeRec* __restrict__ edges_g, const EdgeExt* __restrict__ ext, const int4* __restrict__ chunks_g,
-             int E, int NC, const int* __restrict__ clk, const int4* __restrict__ clbb, const float* __restrict__ clc,
+             int E, int NC, const int2* __restrict__ clk, const int4* __restrict__ clmb,
+             const int4* __restrict__ clbb, const float* __restrict__ clc,
              float* __restrict__ dist, int* __restrict__ parent, int strip, int samples, int* __restrict__ qctr,
              const int* __restrict__ obins, const int* __restrict__ order, int ocap, u64* __restrict__ stats) {
   extern __shared__ int4 smem[];
@@ -1237,7 +1268,7 @@ void k_pixel(int W, int H, int W32, int Gmax, int* misc, const unsigned* __restr
     }
     if (l < kOrderBins) opre[l] = v - obins[l];
   }
-  TabFull tab{sgen_g, sgcost_g, sgbb_g, clk, clbb, clc, (misc[MISC_G] + kCluster - 1) / kCluster};
+  TabFull tab{sgen_g, sgcost_g, sgbb_g, clk, clmb, clbb, clc, (misc[MISC_G] + kCluster - 1) / kCluster};
   Geo geo{edges_g, ext, chunks_g, E, NC};
   if (LDSD) {
     GenRec* s_gen = (GenRec*)smem;
@@ -1257,9 +1288,24 @@ void k_pixel(int W, int H, int W32, int Gmax, int* misc, const unsigned* __restr
     geo.edges = s_edges;
     geo.chunks = s_chunks;
   }
-  __syncthreads();
-  pixel_items<TW, STATS, WALK>(W, H, W32, G, inside, tab, geo, dist, parent, strip, samples, qctr, order, ocap, opre,
-                               st);
+  if constexpr (!LDSD && WALK == kWalkCluster) {
+    // chunk boxes, then the packed edges
+    int4* s_chunks = smem;
+    uint2* s_pe = (uint2*)(s_chunks + NC);
+    for (int k = t; k < NC; k += nt) s_chunks[k] = chunks_g[k];
+    for (int k = t; k < E; k += nt) {
+      const EdgeRec r = edges_g[k];
+      s_pe[k] = make_uint2((unsigned)r.wx | ((unsigned)r.wy << 16), (unsigned)r.vx | ((unsigned)r.vy << 16));
+    }
+    __syncthreads();
+    const GeoPacked gp{s_pe, ext, s_chunks, E, NC};
+    pixel_items<TW, STATS, WALK>(W, H, W32, G, inside, tab, gp, dist, parent, strip, samples, qctr, order, ocap,
+                                 opre, st);
+  } else {
+    __syncthreads();
+    pixel_items<TW, STATS, WALK>(W, H, W32, G, inside, tab, geo, dist, parent, strip, samples, qctr, order, ocap,
+                                 opre, st);
+  }
   if (STATS && lane_id() == 0) {
 #pragma unroll
     for (int s = 0; s < ST_COUNT; ++s) atomicAdd(&stats[s], st[s]);
@@ -1281,13 +1327,15 @@ static int device_cus() {
 // Spatial clusters for the cluster walk: kCluster consecutive positions of the
 // spatial generator order (sources first, then corners in Morton order of
 // their edges) form a cluster; its members are their cost-sorted positions
-// (-1 for an unreached generator or past the end), its box the union of their
-// boxes and its cost their least float cost.  One thread per position; the
+// (-1 for an unreached generator or past the end), stored with their float
+// cost and box in cluster order, its box the union of their boxes and its
+// cost their least float cost.  One thread per position; the
 // kCluster threads of a cluster are neighbouring lanes of one wavefront.
 __global__ __launch_bounds__(256) void k_clusters(const int* __restrict__ misc, const int* __restrict__ gorder,
                                                   const int* __restrict__ krank, const int4* __restrict__ sgbb,
-                                                  const float* __restrict__ sgcost, int* __restrict__ clk,
-                                                  int4* __restrict__ clbb, float* __restrict__ clc, int Gmax) {
+                                                  const float* __restrict__ sgcost, int2* __restrict__ clk,
+                                                  int4* __restrict__ clmb, int4* __restrict__ clbb,
+                                                  float* __restrict__ clc, int Gmax) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   const int Gc = misc[MISC_G];
   const int ncl = (Gc + kCluster - 1) / kCluster;
@@ -1299,6 +1347,8 @@ __global__ __launch_bounds__(256) void k_clusters(const int* __restrict__ misc, 
     b = sgbb[k];
     c = sgcost[k];
   }
+  const int4 own_b = k >= 0 ? b : make_int4(0, 0, 0, 0);
+  const float own_c = c;
 #pragma unroll
   for (int o = 1; o < kCluster; o <<= 1) {
     b.x = min(b.x, __shfl_xor(b.x, o, 64));
@@ -1308,7 +1358,8 @@ __global__ __launch_bounds__(256) void k_clusters(const int* __restrict__ misc, 
     c = fminf(c, __shfl_xor(c, o, 64));
   }
   if (p < ncl * kCluster && p < ((Gmax + kCluster - 1) / kCluster) * kCluster) {
-    clk[p] = k;
+    clk[p] = make_int2(k, __float_as_int(own_c));
+    clmb[p] = own_b;
     if (p % kCluster == 0) {
       clbb[p / kCluster] = c < INFINITY ? b : make_int4(0, 0, 0, 0);
       clc[p / kCluster] = c;
@@ -1332,7 +1383,7 @@ static hipError_t launch_variant(const Dev& d, hipStream_t s, size_t shm) {
   if (WALK == kWalkCluster && d.Gmax > 0) {
     const int npos = (d.Gmax + kCluster - 1) / kCluster * kCluster;
     hipLaunchKernelGGL(k_clusters, dim3((unsigned)((npos + 255) / 256)), dim3(256), 0, s, d.misc, d.gorder, d.krank,
-                       d.sgbb, d.sgcost, d.clk, d.clbb, d.clc, d.Gmax);
+                       d.sgbb, d.sgcost, d.clk, d.clmb, d.clbb, d.clc, d.Gmax);
   }
   // the work order matters only when some items wait for a free wavefront
   const int* order = nullptr;
@@ -1350,7 +1401,8 @@ static hipError_t launch_variant(const Dev& d, hipStream_t s, size_t shm) {
     order = d.order;
   }
   hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(kPixelThreads), shm, s, d.W, d.H, d.W32, d.Gmax, d.misc,
-                     d.inside, d.sgen, d.sgcost, d.sgbb, d.edges, d.ext, d.chunks, d.E, d.NC, d.clk, d.clbb, d.clc,
+                     d.inside, d.sgen, d.sgcost, d.sgbb, d.edges, d.ext, d.chunks, d.E, d.NC, d.clk, d.clmb, d.clbb,
+                     d.clc,
                      d.dist, d.parent, d.strip, d.samples, d.qctr, d.obins, order, d.ocap, d.stats);
   return hipGetLastError();
 }
@@ -1359,6 +1411,16 @@ template <int TW, int WALK>
 static hipError_t launch_tw_walk(const Dev& d, hipStream_t s) {
   const size_t shm = pixel_lds_bytes(d.Gmax, d.E, d.NC);
   const bool lds = shm <= kPixelLdsMax;
+  if (!lds && WALK == kWalkCluster) {
+    // the cluster walk keeps the packed edges in LDS (at most 8192 edges: 66 KB)
+    const size_t pk = packed_edge_lds_bytes(d.E, d.NC);
+    if (pk > kPixelLdsMax) {
+      auto k0 = d.stats ? k_pixel<TW, true, false, WALK> : k_pixel<TW, false, false, WALK>;
+      const hipError_t e = hipFuncSetAttribute((const void*)k0, hipFuncAttributeMaxDynamicSharedMemorySize, (int)pk);
+      if (e != hipSuccess) return e;
+    }
+    return d.stats ? launch_variant<TW, true, false, WALK>(d, s, pk) : launch_variant<TW, false, false, WALK>(d, s, pk);
+  }
   if (d.stats)
     return lds ? launch_variant<TW, true, true, WALK>(d, s, shm) : launch_variant<TW, true, false, WALK>(d, s, 0);
   return lds ? launch_variant<TW, false, true, WALK>(d, s, shm) : launch_variant<TW, false, false, WALK>(d, s, 0);

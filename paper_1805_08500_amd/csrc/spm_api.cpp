@@ -328,7 +328,8 @@ void fill_dev(Dev& d, const spm_scene* s, const spm_out* out, char* ws, const La
   d.obins = (int*)(ws + L.off_obins);
   d.order = (int*)(ws + L.off_order);
   d.krank = (int*)(ws + L.off_krank);
-  d.clk = (int*)(ws + L.off_clk);
+  d.clk = (int2*)(ws + L.off_clk);
+  d.clmb = (int4*)(ws + L.off_clmb);
   d.clbb = (int4*)(ws + L.off_clbb);
   d.clc = (float*)(ws + L.off_clc);
   d.ocap = L.ocap;

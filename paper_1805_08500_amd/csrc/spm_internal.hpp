@@ -119,7 +119,7 @@ struct Layout {
   size_t off_gens, off_vis, off_sgen, off_sgcost, off_sgbb, off_inside, off_cost64, off_gxy, off_misc;
   size_t off_vsorted, off_vtx2gid, off_gorder, off_costpos, off_qctr, off_rmask, off_cmark;
   size_t off_obins, off_order;
-  size_t off_krank, off_clk, off_clbb, off_clc;   // generator clusters of the pixel stage
+  size_t off_krank, off_clk, off_clmb, off_clbb, off_clc;   // generator clusters of the pixel stage
   // a host scene staged into the workspace (spm_build): poly_start, vx, vy, pts, segs, each at
   // a 16-int boundary from off_scene
   size_t off_scene, scene_ints, sc_poly, sc_vx, sc_vy, sc_pts, sc_segs;
@@ -171,7 +171,8 @@ inline Layout make_layout(int W, int H, int n_polys, int nv, int np, int ns) {
   L.off_order = take((size_t)kOrderBins * (size_t)(L.ocap > 0 ? L.ocap : 1) * sizeof(int));
   const size_t ncl = (G1 + kCluster - 1) / kCluster;
   L.off_krank = take(G1 * sizeof(int));
-  L.off_clk = take(ncl * kCluster * sizeof(int));
+  L.off_clk = take(ncl * kCluster * 2 * sizeof(int));
+  L.off_clmb = take(ncl * kCluster * 16);
   L.off_clbb = take(ncl * 16);
   L.off_clc = take(ncl * sizeof(float));
   size_t si = 0;
@@ -224,7 +225,9 @@ struct Dev {
   int* obins;     // pixel-stage work classes: item count of each (kOrderBins)
   int* order;     // work items of class c at order[c * ocap ...], in no particular order within it
   int* krank;     // canonical generator g: its position in the cost-sorted table, -1 when unreached
-  int* clk;       // cluster c: the sorted positions of its kCluster members (-1: none), in spatial order
+  int2* clk;      // cluster c: (sorted position, float cost bits) of its kCluster members (position -1:
+                  // none), in spatial order
+  int4* clmb;     // cluster c: its members' boxes (same order)
   int4* clbb;     // cluster c: bounding box of its members
   float* clc;     // cluster c: least float cost of its members (+inf: none)
   int ocap;
