@@ -130,8 +130,9 @@ int spm_build(const spm_scene* host_scene, const spm_out* out, void* d_ws, size_
  * recorded event and returns the per-stage milliseconds summed over every
  * build recorded since the last reset (stage order: ingest, edge sort and
  * inside mask, generator order and chunk boxes, generator visibility,
- * relaxation, generator sort, pixel propagation (with its work order), total)
- * and the number of builds. */
+ * relaxation, generator sort (with the pixel kernel's work order and cluster
+ * tables when they need launches of their own), pixel propagation (the pixel
+ * kernel alone), total) and the number of builds. */
 typedef struct spm_timer spm_timer;
 int spm_timer_create(spm_timer** t);
 int spm_timer_destroy(spm_timer* t);

@@ -1367,8 +1367,12 @@ __global__ __launch_bounds__(256) void k_clusters(const int* __restrict__ misc, 
   }
 }
 
+// phase 0 queues what the pixel kernel reads besides the generator tables
+// (the cluster tables of the cluster walk, the work order when it is not built
+// in the sort's launch); phase 1 the pixel kernel itself.  Both phases take the
+// same decisions.
 template <int TW, bool STATS, bool LDSD, int WALK>
-static hipError_t launch_variant(const Dev& d, hipStream_t s, size_t shm) {
+static hipError_t launch_variant(const Dev& d, hipStream_t s, size_t shm, int phase) {
   auto kern = k_pixel<TW, STATS, LDSD, WALK>;
   int per_cu = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kPixelThreads, shm) != hipSuccess || per_cu < 1)
@@ -1380,16 +1384,24 @@ static hipError_t launch_variant(const Dev& d, hipStream_t s, size_t shm) {
   const long long max_blocks = (waves_needed + (kPixelThreads / 64) - 1) / (kPixelThreads / 64);
   if (blocks > max_blocks) blocks = max_blocks;
   if (blocks < 1) blocks = 1;
-  if (WALK == kWalkCluster && d.Gmax > 0) {
+  if (phase == 0 && WALK == kWalkCluster && d.Gmax > 0) {
     const int npos = (d.Gmax + kCluster - 1) / kCluster * kCluster;
     hipLaunchKernelGGL(k_clusters, dim3((unsigned)((npos + 255) / 256)), dim3(256), 0, s, d.misc, d.gorder, d.krank,
                        d.sgbb, d.sgcost, d.clk, d.clmb, d.clbb, d.clc, d.Gmax);
   }
   // the work order matters only when some items wait for a free wavefront
   const int* order = nullptr;
+  auto launch_main = [&]() {
+    hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(kPixelThreads), shm, s, d.W, d.H, d.W32, d.Gmax, d.misc,
+                       d.inside, d.sgen, d.sgcost, d.sgbb, d.edges, d.ext, d.chunks, d.E, d.NC, d.clk, d.clmb,
+                       d.clbb, d.clc, d.dist, d.parent, d.strip, d.samples, d.qctr, d.obins, order, d.ocap, d.stats);
+    return hipGetLastError();
+  };
   if (SPM_TILE_ORDER && waves_needed > blocks * (kPixelThreads / 64) && order_fused(d)) {
     order = d.order;   // built in the generator sort's launch
   } else if (SPM_TILE_ORDER && waves_needed > blocks * (kPixelThreads / 64)) {
+    order = d.order;
+    if (phase == 1) return launch_main();
     const dim3 og((unsigned)((waves_needed + kOrderItems - 1) / kOrderItems));
     const size_t osh = (size_t)d.Gmax * (sizeof(int4) + sizeof(float));
     if (osh <= kOrderLdsMax)
@@ -1398,48 +1410,47 @@ static hipError_t launch_variant(const Dev& d, hipStream_t s, size_t shm) {
     else
       hipLaunchKernelGGL((k_tile_order<TW, false>), og, dim3(kOrderThreads), 0, s, d.W, d.H, d.strip, d.Gmax, d.misc,
                          d.sgcost, d.sgbb, d.obins, d.order, d.ocap);
-    order = d.order;
+    return hipGetLastError();
   }
-  hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(kPixelThreads), shm, s, d.W, d.H, d.W32, d.Gmax, d.misc,
-                     d.inside, d.sgen, d.sgcost, d.sgbb, d.edges, d.ext, d.chunks, d.E, d.NC, d.clk, d.clmb, d.clbb,
-                     d.clc,
-                     d.dist, d.parent, d.strip, d.samples, d.qctr, d.obins, order, d.ocap, d.stats);
-  return hipGetLastError();
+  return phase == 1 ? launch_main() : hipGetLastError();
 }
 
 template <int TW, int WALK>
-static hipError_t launch_tw_walk(const Dev& d, hipStream_t s) {
+static hipError_t launch_tw_walk(const Dev& d, hipStream_t s, int phase) {
   const size_t shm = pixel_lds_bytes(d.Gmax, d.E, d.NC);
   const bool lds = shm <= kPixelLdsMax;
   if (!lds && WALK == kWalkCluster) {
     // the cluster walk keeps the packed edges in LDS (at most 8192 edges: 66 KB)
     const size_t pk = packed_edge_lds_bytes(d.E, d.NC);
-    if (pk > kPixelLdsMax) {
+    if (phase == 1 && pk > kPixelLdsMax) {
       auto k0 = d.stats ? k_pixel<TW, true, false, WALK> : k_pixel<TW, false, false, WALK>;
       const hipError_t e = hipFuncSetAttribute((const void*)k0, hipFuncAttributeMaxDynamicSharedMemorySize, (int)pk);
       if (e != hipSuccess) return e;
     }
-    return d.stats ? launch_variant<TW, true, false, WALK>(d, s, pk) : launch_variant<TW, false, false, WALK>(d, s, pk);
+    return d.stats ? launch_variant<TW, true, false, WALK>(d, s, pk, phase)
+                   : launch_variant<TW, false, false, WALK>(d, s, pk, phase);
   }
   if (d.stats)
-    return lds ? launch_variant<TW, true, true, WALK>(d, s, shm) : launch_variant<TW, true, false, WALK>(d, s, 0);
-  return lds ? launch_variant<TW, false, true, WALK>(d, s, shm) : launch_variant<TW, false, false, WALK>(d, s, 0);
+    return lds ? launch_variant<TW, true, true, WALK>(d, s, shm, phase)
+               : launch_variant<TW, true, false, WALK>(d, s, 0, phase);
+  return lds ? launch_variant<TW, false, true, WALK>(d, s, shm, phase)
+             : launch_variant<TW, false, false, WALK>(d, s, 0, phase);
 }
 
 template <int TW>
-static hipError_t launch_tw(const Dev& d, hipStream_t s) {
+static hipError_t launch_tw(const Dev& d, hipStream_t s, int phase) {
   switch (d.walk > 0 ? d.walk - 1 : walk_mode(d.Gmax)) {
-    case kWalkCached: return launch_tw_walk<TW, kWalkCached>(d, s);
-    case kWalkRefill: return launch_tw_walk<TW, kWalkRefill>(d, s);
-    case kWalkCluster: return launch_tw_walk<TW, kWalkCluster>(d, s);
-    default: return launch_tw_walk<TW, kWalkCost>(d, s);
+    case kWalkCached: return launch_tw_walk<TW, kWalkCached>(d, s, phase);
+    case kWalkRefill: return launch_tw_walk<TW, kWalkRefill>(d, s, phase);
+    case kWalkCluster: return launch_tw_walk<TW, kWalkCluster>(d, s, phase);
+    default: return launch_tw_walk<TW, kWalkCost>(d, s, phase);
   }
 }
 
-hipError_t launch_pixel(const Dev& d, hipStream_t s) {
-  if (d.tile_w == 16) return launch_tw<16>(d, s);
-  if (d.tile_w == 4) return launch_tw<4>(d, s);
-  return launch_tw<8>(d, s);
+hipError_t launch_pixel(const Dev& d, hipStream_t s, int phase) {
+  if (d.tile_w == 16) return launch_tw<16>(d, s, phase);
+  if (d.tile_w == 4) return launch_tw<4>(d, s, phase);
+  return launch_tw<8>(d, s, phase);
 }
 
 // Batched pixel stage: one persistent launch for every tile of every scene.

@@ -377,11 +377,13 @@ int check_tile(int tw, int th) {
 }
 
 const char* kStageNames[7] = {"ingest", "edge sort and inside mask", "generator order and chunk boxes",
-                              "generator visibility", "relaxation", "generator sort", "pixel propagation"};
+                              "generator visibility", "relaxation", "generator sort and pixel tables", "pixel propagation"};
 
-// queue the seven stages of a build for a scene source; marks timer events
-template <class S, class PixelFn>
-int run_stages(const S& src, const Plan& p, hipStream_t st, spm_timer* tm, PixelFn pixel) {
+// queue the seven stages of a build for a scene source; marks timer events.
+// prep() queues the pixel kernel's own tables after the generator sort (timed
+// with it), pixel() the pixel kernel alone.
+template <class S, class PrepFn, class PixelFn>
+int run_stages(const S& src, const Plan& p, hipStream_t st, spm_timer* tm, PrepFn prep, PixelFn pixel) {
   hipEvent_t* ev = nullptr;
   if (tm && tm->n < tm->cap) ev = &tm->ev[(size_t)tm->n * SPM_N_STAGES];
   auto mark = [&](int k) -> int {
@@ -398,7 +400,10 @@ int run_stages(const S& src, const Plan& p, hipStream_t st, spm_timer* tm, Pixel
       case 2: e = launch_gorder(src, p, st); break;
       case 3: e = launch_genvis(src, p, st); break;
       case 4: e = launch_relax(src, p, st); break;
-      case 5: e = launch_gsort(src, p, st); break;
+      case 5:
+        e = launch_gsort(src, p, st);
+        if (e == hipSuccess) e = prep();
+        break;
       default: e = pixel(); break;
     }
     if (e != hipSuccess) return fail(SPM_ERR_HIP, "%s launch failed: %s", kStageNames[k], hipGetErrorString(e));
@@ -501,7 +506,8 @@ int spm_build_ex(const spm_scene* s, const spm_out* out, void* d_ws, size_t ws_b
   plan_add(p, src.d);
   hipStream_t st = (hipStream_t)stream;
   const Dev& d = src.d;
-  rc = run_stages(src, p, st, opts ? opts->timer : nullptr, [&]() { return launch_pixel(d, st); });
+  rc = run_stages(src, p, st, opts ? opts->timer : nullptr, [&]() { return launch_pixel(d, st, 0); },
+                  [&]() { return launch_pixel(d, st, 1); });
   if (rc) return rc;
   return ok();
 }
@@ -699,7 +705,8 @@ int spm_build_batch(const spm_batch* b, void* d_ws, size_t ws_bytes, void* strea
   BatchSrc src{(const Dev*)(ws + B.off_tab), (const int*)(ws + B.off_offs), b->n};
   hipStream_t st = (hipStream_t)stream;
   int* ctr = (int*)(ws + B.off_ctr);
-  rc = run_stages(src, p, st, timer, [&]() { return launch_pixel_batch(src, p, ctr, st); });
+  rc = run_stages(src, p, st, timer, [&]() { return hipSuccess; },
+                  [&]() { return launch_pixel_batch(src, p, ctr, st); });
   if (rc) return rc;
   return ok();
 }

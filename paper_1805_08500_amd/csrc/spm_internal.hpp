@@ -359,7 +359,8 @@ template <class S> hipError_t launch_gorder(const S& src, const Plan& p, hipStre
 template <class S> hipError_t launch_genvis(const S& src, const Plan& p, hipStream_t s);
 template <class S> hipError_t launch_relax(const S& src, const Plan& p, hipStream_t s);
 template <class S> hipError_t launch_gsort(const S& src, const Plan& p, hipStream_t s);
-hipError_t launch_pixel(const Dev& d, hipStream_t s);
+// phase 0: the pixel kernel's own tables (clusters, a separate work order); phase 1: the pixel kernel
+hipError_t launch_pixel(const Dev& d, hipStream_t s, int phase);
 hipError_t launch_pixel_batch(const BatchSrc& b, const Plan& p, int* batch_ctr, hipStream_t s);
 size_t pixel_lds_bytes(int Gmax, int E, int NC);
 size_t agent_ws_bytes(int Gmax, int n_agents);
