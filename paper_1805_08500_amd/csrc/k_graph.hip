@@ -472,6 +472,8 @@ __device__ __forceinline__ double arc_len4(int4 u, int vx, int vy) {
 }
 
 constexpr int kRelaxFront = 2048;   // largest frontier kept as a list (push rounds)
+constexpr int kRelaxQueueSlack = 64;   // work-queue ring entries beyond one per generator
+constexpr int kRelaxQueueSpin = 1 << 22;   // spin limit of the work queue's waits (about a second)
 
 // A lower bound, in double, of the arc weight from u (doubled coordinates
 // x, y, x2, y2) to the corner (vx, vy): the hardware float square root with a
@@ -812,6 +814,156 @@ __global__ __launch_bounds__(1024) void k_relax(S src, int Gcap, int RWcap, int 
   }
 }
 
+// Deep graphs (the maze: shortest paths of hundreds of arcs) need as many
+// synchronous rounds as their deepest path has arcs, each a few microseconds
+// of barriers and L2 round trips in k_relax.  This kernel relaxes them without
+// rounds: label-correcting with a FIFO work queue (Bellman-Ford-Moore) in one
+// workgroup, costs in LDS.  Each wavefront takes a corner u off the queue,
+// reads row u of the matrix (corner-corner visibility is symmetric, so its
+// bits are the corners u sees) and lowers each such corner v by an LDS atomic
+// minimum; a v it lowers goes on the queue unless it is already there.  A
+// corner is taken off (its flag cleared) before its cost is read, so a later
+// lowering puts it back.  `pending` counts corners queued and not yet fully
+// relaxed; the workgroup is done when it is zero (no corner can still change,
+// and nothing is in flight).  Every relaxation uses the same double-precision
+// weight and sum as the other kernels, and the minimum over the same candidate
+// values is reached whatever the order (the costs only fall to the one fixed
+// point), so the costs are the same bits as k_relax's.
+// LDS: cost (u64) and corner coordinates (int2) per position, the ring of
+// positions (Gcap + 64 entries, -1 = empty) and the queued flags.
+size_t relax_queue_lds_bytes(int Gcap) {
+  return (size_t)Gcap * 16 + (size_t)(Gcap + kRelaxQueueSlack) * 4 + (size_t)((Gcap + 31) / 32) * 4 + 64;
+}
+
+template <class S>
+__global__ __launch_bounds__(1024) void k_relax_queue(S src, int Gcap, int m0idx, int rounds0) {
+  int sc, one;
+  if (!src.locate(STG_SCENE, blockIdx.x, sc, one)) return;
+  const Dev& d = src.scene(sc);
+  extern __shared__ u64 shm[];
+  __shared__ int head, tail, pending, reached;
+  u64* cost = shm;
+  int2* xy = (int2*)(shm + Gcap);
+  const int cap = Gcap + kRelaxQueueSlack;
+  int* ring = (int*)(xy + Gcap);
+  unsigned* inq = (unsigned*)(ring + cap);
+  const int tid = threadIdx.x, nt = blockDim.x, lane = lane_id();
+  const int G = d.misc[MISC_G];
+  const int RW = d.RW, nsrc = d.np + d.ns;
+  const u64* m0 = d.rmask + m0idx * RW;
+  for (int g = tid; g < G; g += nt) {
+    cost[g] = d.costpos[g];
+    const int4 r = d.gxy[g];
+    xy[g] = make_int2(r.x, r.y);
+  }
+  for (int k = tid; k < cap; k += nt) ring[k] = -1;
+  for (int k = tid; k < (G + 31) / 32; k += nt) inq[k] = 0u;
+  if (tid == 0) { head = 0; tail = 0; pending = 0; reached = 0; }
+  __syncthreads();
+  // the corners the last chip-wide round lowered: their arcs out are still to relax
+  for (int v = nsrc + tid; v < G; v += nt) {
+    if ((m0[v >> 6] >> (v & 63)) & 1ull) {
+      atomicOr(&inq[v >> 5], 1u << (v & 31));
+      const int t = atomicAdd(&tail, 1);
+      ring[t] = v;
+      atomicAdd(&pending, 1);
+    }
+  }
+  __syncthreads();
+  // Both waits below end by construction (a queued corner is always being relaxed by a running wavefront,
+  // and an entry is written right after its position is claimed); their spin limits only guard that
+  // reasoning: a wavefront that reaches one stops and flags the build (MISC_ROUNDS = -1).
+  bool stuck = false;
+  for (;;) {
+    // take a corner: lane 0 claims the next queue position, or sees that all work is done
+    int h = -1;
+    if (lane == 0) {
+      for (int spin = 0; spin < kRelaxQueueSpin; ++spin) {
+        const int hh = __hip_atomic_load(&head, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        const int tt = __hip_atomic_load(&tail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        if (hh < tt) {
+          if (atomicCAS(&head, hh, hh + 1) == hh) { h = hh; break; }
+          continue;
+        }
+        if (__hip_atomic_load(&pending, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) == 0) { h = -2; break; }
+        __builtin_amdgcn_s_sleep(1);
+      }
+    }
+    h = __shfl(h, 0, 64);
+    if (h == -1) stuck = true;
+    if (h < 0) break;
+    int u = -1;
+    if (lane == 0) {
+      // the producer writes the entry right after claiming its position
+      int* slot = &ring[h % cap];
+      for (int spin = 0; spin < kRelaxQueueSpin; ++spin) {
+        u = __hip_atomic_load(slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        if (u >= 0) break;
+        __builtin_amdgcn_s_sleep(1);
+      }
+      if (u >= 0) {
+        __hip_atomic_store(slot, -1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        // off the queue before its cost is read: a later lowering queues it again
+        atomicAnd(&inq[u >> 5], ~(1u << (u & 31)));
+      }
+    }
+    u = __shfl(u, 0, 64);
+    if (u < 0) { stuck = true; break; }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    const double cu = __longlong_as_double((long long)__hip_atomic_load(&cost[u], __ATOMIC_RELAXED,
+                                                                         __HIP_MEMORY_SCOPE_WORKGROUP));
+    const int2 pu2 = xy[u];
+    const int4 pu = make_int4(pu2.x, pu2.y, pu2.x, pu2.y);
+    for (int k0 = 0; k0 < RW; k0 += kWave) {
+      const int k = k0 + lane;
+      u64 m = k < RW ? d.vis[(size_t)u * RW + k] : 0ull;
+      while (m) {
+        const int v = k * 64 + __builtin_ctzll(m);
+        m &= m - 1;
+        if (v < nsrc || v >= G) continue;   // sources keep cost 0
+        const double cv = __longlong_as_double((long long)__hip_atomic_load(&cost[v], __ATOMIC_RELAXED,
+                                                                             __HIP_MEMORY_SCOPE_WORKGROUP));
+        if (!(cu < cv)) continue;
+        const int2 pv = xy[v];
+        if (!(cu + arc_lower(pu, pv.x, pv.y) < cv)) continue;
+        const double cand = cu + arc_len4(pu, pv.x, pv.y);
+        if (!(cand < cv)) continue;
+        const u64 ob = atomicMin(&cost[v], (u64)__double_as_longlong(cand));
+        if (__longlong_as_double((long long)ob) > cand) {
+          const unsigned bit = 1u << (v & 31);
+          if (!(atomicOr(&inq[v >> 5], bit) & bit)) {
+            atomicAdd(&pending, 1);
+            const int t = atomicAdd(&tail, 1);
+            __hip_atomic_store(&ring[t % cap], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+          }
+        }
+      }
+    }
+    // every corner this one lowered is counted before it stops counting
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    if (lane == 0) atomicSub(&pending, 1);
+  }
+  __syncthreads();
+  // outputs by canonical id; parents follow in k_gsort_parents
+  int mine = 0;
+  for (int p = tid; p < G; p += nt) {
+    const double c = __longlong_as_double((long long)cost[p]);
+    const int v = d.gorder[p];
+    d.costpos[p] = cost[p];
+    d.gen_cost[v] = c;
+    d.cost64[v] = c;
+    if (c < INFINITY) ++mine;
+  }
+  atomicAdd(&reached, mine);
+  __syncthreads();
+  if (tid == 0) {
+    d.misc[MISC_REACHED] = reached;
+    d.misc[MISC_ROUNDS] = rounds0;
+  }
+  __syncthreads();
+  if (stuck && lane == 0) d.misc[MISC_ROUNDS] = -1;
+}
+
 // One wavefront per generator: rank by (float cost, id) among all generators;
 // unreached ones (+inf) rank last and are not copied.
 template <class S>
@@ -938,7 +1090,12 @@ hipError_t launch_relax(const S& src, const Plan& p, hipStream_t s) {
                          : hipSuccess;
   };
   hipError_t e = hipSuccess;
-  if (shm_v + static_lds <= lim) {
+  const size_t shm_q = relax_queue_lds_bytes(Gcap);
+  if (kRelaxQueue && kRelaxChaos > 0 && p.maxGmax > kChaosAdaptMinGen && shm_q + 64 <= lim) {
+    // deep graphs: the rest without rounds
+    if ((e = big((const void*)k_relax_queue<S>, shm_q)) != hipSuccess) return e;
+    hipLaunchKernelGGL((k_relax_queue<S>), grid, dim3(kRelaxThreads), shm_q, s, src, Gcap, m0idx, rounds0);
+  } else if (shm_v + static_lds <= lim) {
     if ((e = big((const void*)k_relax<S, true, true>, shm_v)) != hipSuccess) return e;
     hipLaunchKernelGGL((k_relax<S, true, true>), grid, dim3(kRelaxThreads), shm_v, s, src, Gcap, RWcap, m0idx, rounds0);
   } else if (shm + static_lds <= lim) {

@@ -43,6 +43,10 @@ constexpr int kRelaxChaosMax = SPM_RELAX_CHAOS_MAX;   // their cap when they sto
 #endif
 constexpr int kChaosAdaptMinGen = SPM_CHAOS_ADAPT_MIN_GEN;   // above that many generators they do
 constexpr int kChaosSlots = 8;     // progress marks, spread over cache lines to keep atomics apart
+#ifndef SPM_RELAX_QUEUE
+#define SPM_RELAX_QUEUE 1
+#endif
+constexpr int kRelaxQueue = SPM_RELAX_QUEUE;   // large graphs finish their relaxation on a work queue
 constexpr int kIngestFuseMax = 1024;   // scenes up to that many vertices ingest in the generator-table launch
 constexpr int kDefaultStrip = 1;      // tiles per pixel-stage work item
 constexpr int kDefaultSamples = 3;    // seed searches per pixel tile
