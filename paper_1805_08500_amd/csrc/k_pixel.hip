@@ -102,12 +102,20 @@ struct OccCache {
     ab2 = pack16(ey, -ex);
     c2 = mul24(ex, vy) - mul24(ey, vx);
   }
-  // Does some cached edge hide the point g from the whole of U?
-  __device__ __forceinline__ bool umbra_hides(int gx, int gy) const {
-    const int h0 = mad24(lo16(ab0), gx, mad24(hi16(ab0), gy, c0));
-    const int h1 = mad24(lo16(ab1), gx, mad24(hi16(ab1), gy, c1));
-    const int h2 = mad24(lo16(ab2), gx, mad24(hi16(ab2), gy, c2));
-    return ballot(max(max(h0, h1), h2) < 0) != 0ull;
+  // Does some cached edge hide the point g from the whole of U (all three
+  // h_i(g) < 0)?  Tested for the points g = (px, py) of lanes 0..kCluster-1
+  // whose bits are set in pts; the bits of the hidden ones are cleared from
+  // keep.
+  __device__ __forceinline__ void umbra_filter(u64 pts, int px, int py, u64& keep) const {
+    const int A0 = lo16(ab0), B0 = hi16(ab0), A1 = lo16(ab1), B1 = hi16(ab1), A2 = lo16(ab2), B2 = hi16(ab2);
+#pragma unroll
+    for (int j = 0; j < kCluster; ++j) {
+      if (!((pts >> j) & 1ull)) continue;
+      const int gx = readlane(px, j), gy = readlane(py, j);
+      const int h = max(max(mad24(A0, gx, mad24(B0, gy, c0)), mad24(A1, gx, mad24(B1, gy, c1))),
+                        mad24(A2, gx, mad24(B2, gy, c2)));
+      if (ballot(h < 0)) keep &= ~(1ull << j);
+    }
   }
   // Does some cached edge hide the whole box K (kx0..ky1) from the whole of
   // U?  K lies in the (convex) umbra iff the largest value of each h_i over K
@@ -900,6 +908,13 @@ __device__ __forceinline__ int tile_work(int tile, int W, int H, int W32, int G,
         }
         u64 mm = ballot(k >= 0 && ek <= UB);
         if (STATS) st[ST_CL_MEMBERS] += __popcll(mm);
+        if (mm) {
+          // point members that a cached edge hides from the whole tile: all tested in one pass, the
+          // umbra coefficients unpacked once (segment members go on to the full test)
+          const u64 pts = mm & ballot(b.x == b.z && b.y == b.w);
+          oc.umbra_filter(pts, b.x, b.y, mm);
+          if (STATS) st[ST_CL_UMBRA] += __popcll(pts & ~mm);
+        }
         while (mm) {
           // the least estimate first (the likely winner tightens the bounds for the rest)
           const float e_here = ((mm >> lane) & 1ull) ? ek : INFINITY;
@@ -911,11 +926,6 @@ __device__ __forceinline__ int tile_work(int tile, int W, int H, int W32, int G,
           // their uniform float work; try_gen's per-lane bound decides)
           const int gx0 = readlane_i(b.x, jl), gy0 = readlane_i(b.y, jl), gx1 = readlane_i(b.z, jl),
                     gy1 = readlane_i(b.w, jl);
-          // a point or corner that a cached edge hides from the whole tile: nothing to try
-          if (gx0 == gx1 && gy0 == gy1 && oc.umbra_hides(gx0, gy0)) {
-            if (STATS) st[ST_CL_UMBRA] += 1;
-            continue;
-          }
           if (STATS) st[ST_CL_TRIED] += 1;
           try_gen(readlane_i(k, jl), readlane_f(kc, jl), gx0, gy0, gx1, gy1);
         }
