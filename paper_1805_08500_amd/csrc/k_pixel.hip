@@ -874,16 +874,46 @@ __device__ __forceinline__ int tile_work(int tile, int W, int H, int W32, int G,
         const float dx = (float)max(max(b.x - bx1, bx0 - b.z), 0), dy = (float)max(max(b.y - by1, by0 - b.w), 0);
         return (c + 0.5f * fsqrt(dx * dx + dy * dy)) * (1.0f - 4e-6f);
       };
-      float ec[kClSlots];
+      // Lane l holds clusters l + 64 q.  Their keys -- the estimate's bits (non-negative floats order as
+      // unsigned) with the low four replaced by q, which only lowers a lower bound -- are sorted within
+      // the lane once (a bitonic network on registers); the walk then takes the least of the lanes'
+      // first untaken keys.
+      unsigned key[kClSlots];
 #pragma unroll
       for (int q = 0; q < kClSlots; ++q) {
         const int c = lane + 64 * q;
-        ec[q] = c < tab.ncl ? est_of(tab.clbb[c], tab.clc[c]) : INFINITY;
+        const float e = c < tab.ncl ? est_of(tab.clbb[c], tab.clc[c]) : INFINITY;
+        key[q] = (__float_as_uint(e) & ~15u) | (unsigned)q;
       }
+#pragma unroll
+      for (int kk = 2; kk <= kClSlots; kk <<= 1)
+#pragma unroll
+        for (int jj = kk >> 1; jj > 0; jj >>= 1)
+#pragma unroll
+          for (int i = 0; i < kClSlots; ++i) {
+            const int l = i ^ jj;
+            if (l > i) {
+              const unsigned lo = min(key[i], key[l]), hi = max(key[i], key[l]);
+              key[i] = (i & kk) == 0 ? lo : hi;
+              key[l] = (i & kk) == 0 ? hi : lo;
+            }
+          }
+      unsigned hk = key[0];   // this lane's first untaken key
+      int ptr = 0;
       for (;;) {
-        float m;
-        const int c = slot_pop<kClSlots>(ec, m);
-        if (c < 0 || m > UB) break;
+        const unsigned mk = wave_min_u32(hk);
+        if (mk >= 0x7f800000u || __uint_as_float(mk & ~15u) > UB) break;
+        const int wl = first_bit(ballot(hk == mk));
+        const int c = wl + 64 * (int)(mk & 15u);
+        const int np = readlane(ptr, wl) + 1;
+        if (lane == wl) {
+          unsigned nk = 0xffffffffu;
+#pragma unroll
+          for (int q = 1; q < kClSlots; ++q)
+            if (q == np) nk = key[q];
+          hk = nk;
+          ptr = np;
+        }
         if (STATS) st[ST_BATCHES] += 1;
         const int4 kb = tab.clbb[c];
         const int cx0 = uni(kb.x), cy0 = uni(kb.y), cx1 = uni(kb.z), cy1 = uni(kb.w);
