@@ -196,30 +196,6 @@ struct OccCache {
   }
 };
 
-// Takes the least estimate out of a register cache of N slots per lane (lane
-// l, slot q: entry l + 64 q) and returns its entry, or -1 when the cache is
-// empty; v = the estimate.  Ties go to the lower lane, then the lower slot.
-template <int N>
-__device__ __forceinline__ int slot_pop(float (&ec)[N], float& v) {
-  const int lane = lane_id();
-  float bv = INFINITY;
-  int bs = 0;
-#pragma unroll
-  for (int q = 0; q < N; ++q)
-    if (ec[q] < bv) { bv = ec[q]; bs = q; }
-  // estimates are >= 0, so their bits order as unsigned
-  const unsigned key = __float_as_uint(bv);
-  const unsigned mk = wave_min_u32(key);
-  if (mk >= 0x7f800000u) return -1;
-  const int wl = first_bit(ballot(key == mk));
-  const int ws = readlane(bs, wl);
-#pragma unroll
-  for (int q = 0; q < N; ++q)
-    if (lane == wl && q == ws) ec[q] = INFINITY;
-  v = __uint_as_float(mk);
-  return wl + 64 * ws;
-}
-
 // Least unsigned value over lanes 0..7, returned in every lane (the caller
 // reads it from lane 0's group): two quad exchanges, then the half-row mirror
 // (lane i of each group of 8 takes lane 7 - i).
@@ -797,8 +773,10 @@ __device__ __forceinline__ int tile_work(int tile, int W, int H, int W32, int G,
         int4 nb;
         const bool gv = !is_seg && tab.corner(k, nb);
         int found = -1;
+        // no occluder hints: every edge the full test finds goes to the cache, which holds the last 64 and
+        // was just tried on this very box and point
         bl |= wave_blocked_uniform<STATS>(geo, px, py, m, gx, gy, gv, gv ? nb.x : 0, gv ? nb.y : 0, gv ? nb.z : 0,
-                                          gv ? nb.w : 0, false, 0, 0, 0, 0, bx0, by0, bx1, by1, occ, st, &found);
+                                          gv ? nb.w : 0, false, 0, 0, 0, 0, bx0, by0, bx1, by1, nullptr, st, &found);
         if (found >= 0) {
           if constexpr (WALK == kWalkCluster) oc.insert_umbra(geo.edge(found));
           else oc.insert(geo.edge(found));
