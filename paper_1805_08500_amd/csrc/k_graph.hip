@@ -191,8 +191,9 @@ __device__ __forceinline__ bool pair_visible(const Geo& geo, int px, int py, boo
 // segment from g), first the nearby ones, then every edge a full test found
 // blocking.  The pair (P, g) is blocked by a cached edge when P lies strictly
 // on its obstacle side and the line P-g separates its endpoints strictly (a
-// proper crossing into the obstacle: the rule of pair_visible); a hit is
-// exact, a miss falls back to pair_visible.
+// proper crossing into the obstacle: the rule of pair_visible), i.e. when P
+// lies in the edge's shadow from g; a hit is exact, a miss falls back to
+// pair_visible.
 struct PairCache {
   unsigned w, v;   // x | y << 16 of the edge's endpoints; w == v: empty
   int slot;
@@ -240,15 +241,37 @@ struct PairCache {
     }
     ++slot;
   }
-  // is the segment from P to g blocked by a cached edge?
-  __device__ __forceinline__ bool blocks(int px, int py, int gx, int gy) const {
+  // The shadow of this lane's edge w -> v cast by g (strictly outside its
+  // line, E(g) < 0): the points P for which [P, g] properly crosses the edge
+  // into the obstacle, E(P) > 0 and the line P-g separating w and v strictly.
+  // Seen from g the edge runs clockwise from w to v (cross(w - g, v - g) =
+  // E(g) < 0), so with E(P) > 0
+  // that separation is P strictly inside the wedge of rays g->w, g->v:
+  // cross(w - g, P - g) < 0 < cross(v - g, P - g).  Three open half-planes
+  // h_i(P) = A_i Px + B_i Py + C_i < 0 (|A|, |B| <= 2^14, |C| < 2^30: exact in
+  // int32); an empty slot gets h_0 = 1, never.
+  int sa[3], sb[3], sc[3];
+  __device__ __forceinline__ void set_shadow(int gx, int gy) {
     const int wx = (int)(w & 0xffffu), wy = (int)(w >> 16), vx = (int)(v & 0xffffu), vy = (int)(v >> 16);
     const int a = wy - vy, b = vx - wx, c = -(a * wx + b * wy);
-    const int A = py - gy, B = gx - px;
-    const int C = -(mul24(A, px) + mul24(B, py));
-    const int ow = mad24(A, wx, mad24(B, wy, C)), ov = mad24(A, vx, mad24(B, vy, C));
-    const bool blk = mad24(a, px, mad24(b, py, c)) > 0 && (float)ow * (float)ov < 0.0f;
-    return ballot(blk) != 0ull;
+    const bool empty = w == v;
+    sa[0] = empty ? 0 : -a;
+    sb[0] = empty ? 0 : -b;
+    sc[0] = empty ? 1 : -c;
+    sa[1] = -(wy - gy);
+    sb[1] = wx - gx;
+    sc[1] = mul24(wy - gy, gx) - mul24(wx - gx, gy);
+    sa[2] = vy - gy;
+    sb[2] = -(vx - gx);
+    sc[2] = mul24(vx - gx, gy) - mul24(vy - gy, gx);
+  }
+  // lanes hold the points P (px, py): is P in the shadow of the slot-e edge? (e wave-uniform)
+  __device__ __forceinline__ bool in_shadow(int e, int px, int py) const {
+    int h = -1 << 30;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+      h = max(h, mad24(readlane(sa[i], e), px, mad24(readlane(sb[i], e), py, readlane(sc[i], e))));
+    return h < 0;
   }
 };
 
@@ -338,10 +361,12 @@ __device__ __forceinline__ void genvis_pairs(const Dev& d, const Geo& geo, int w
 
 // Point columns by row segments (many generators): wavefront wid takes the
 // kGvSeg pairs (row corner g, columns u in [s kGvSeg, min((s + 1) kGvSeg, r)))
-// of row r, one pair at a time: the corner rules, then the row's occluder
-// cache, then pair_visible (whose blocking edge joins the cache).  On the maze
-// almost every pair is blocked by a wall next to g, so the cache decides
-// nearly all of them.  Bits as in genvis_pairs.
+// of row r, 64 columns at a time, lanes over the columns: the corner rules,
+// then the shadows that the row's cached occluders cast from g, then
+// pair_visible for each column left (its blocking edge joins the cache and is
+// tried at once on the columns still to do).  On the maze almost every pair is
+// blocked by a wall next to g, so the first few cached edges decide nearly all
+// of them.  Bits as in genvis_pairs.
 template <class S>
 __device__ __forceinline__ void genvis_rows(const Dev& d, const Geo& geo, int wid) {
   const int RW = d.RW;
@@ -365,32 +390,49 @@ __device__ __forceinline__ void genvis_rows(const Dev& d, const Geo& geo, int wi
   const int u0 = s * kGvSeg, u1 = min(u0 + kGvSeg, r);
   PairCache pc;
   pc.fill_near(geo, gx, gy);
+  pc.set_shadow(gx, gy);
   for (int ub = u0; ub < u1; ub += kWave) {
     const int u = ub + lane;
     const bool valid = u < u1;
     GenRec gu = {};
     if (valid) gu = d.gens[d.gorder[u]];
-    u64 todo = ballot(valid && gu.kind != SPM_GEN_SEGMENT);
+    // lanes over the columns: the corner rules, then the shadows of the cached edges (nearest first,
+    // stopping once every column is decided), then the full test for each column left
+    const bool pv = gu.kind == SPM_GEN_VERTEX;
+    bool out = !valid || gu.kind == SPM_GEN_SEGMENT;
+    if (!out) {
+      out = into_interior(gux, guy, gx, gy, gnx, gny, gu.x - gx, gu.y - gy) ||
+            (pv && into_interior(gu.ux, gu.uy, gu.x, gu.y, gu.nx, gu.ny, gx - gu.x, gy - gu.y));
+    }
+    const int ncache = min(pc.slot, kWave);
+    for (int e = 0; e < ncache && ballot(!out); e += 4) {
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+        if (e + t < ncache) out = out || pc.in_shadow(e + t, gu.x, gu.y);
+    }
+    u64 todo = ballot(!out);
     bool seen = false;
     while (todo) {
       const int j = first_bit(todo);
       todo &= todo - 1;
       const int px = readlane(gu.x, j), py = readlane(gu.y, j);
-      const bool pv = readlane(gu.kind, j) == SPM_GEN_VERTEX;
       const int pux = readlane(gu.ux, j), puy = readlane(gu.uy, j), pnx = readlane(gu.nx, j),
                 pny = readlane(gu.ny, j);
-      bool vj = false;
-      if (!into_interior(gux, guy, gx, gy, gnx, gny, px - gx, py - gy) &&
-          !(pv && into_interior(pux, puy, px, py, pnx, pny, gx - px, gy - py)) && !pc.blocks(px, py, gx, gy)) {
-        int found = -1;
-        vj = pair_visible(geo, px, py, pv, pux, puy, pnx, pny, gx, gy, gux, guy, gnx, gny, &found);
-        // a blocker found by the vertex rule may face away from g: the cache test holds only for edges g is outside of
-        if (found >= 0) {
-          const EdgeRec fr = geo.edges[found];
-          if (mad24(fr.a, gx, mad24(fr.b, gy, fr.c)) < 0) pc.insert(fr);
+      int found = -1;
+      const bool vj = pair_visible(geo, px, py, readlane((int)pv, j) != 0, pux, puy, pnx, pny, gx, gy, gux, guy, gnx,
+                                   gny, &found);
+      if (lane == j) seen = vj;
+      // a blocker found by the vertex rule may face away from g: the shadow test holds only for edges g is outside
+      // of.  A new one joins the cache and is tried at once on the columns still to do.
+      if (found >= 0) {
+        const EdgeRec fr = geo.edges[found];
+        if (mad24(fr.a, gx, mad24(fr.b, gy, fr.c)) < 0) {
+          const int at = pc.slot & 63;
+          pc.insert(fr);
+          pc.set_shadow(gx, gy);
+          if (todo) todo &= ~ballot(pc.in_shadow(at, gu.x, gu.y));
         }
       }
-      if (lane == j) seen = vj;
     }
     const u64 bits = ballot(seen);
     if (bits && lane == 0) atomicOr(&d.vis[(size_t)r * RW + (ub >> 6)], bits);
