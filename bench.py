@@ -44,11 +44,15 @@ ALG = {
     "accept": 8,         # per accepted candidate: square root, add, compare, select
     "lane_edge": 9,      # per examined (pixel, generator, edge) visibility test
     "segment": 20,       # per (pixel, segment source) closest point q*
+    # per (cached edge, candidate) shadow test against the whole tile (Procedure 2's shadow of one edge): the
+    # candidate in the edge's umbra behind the tile, three exact half-planes (one lane per cached edge)
+    "shadow_point": 8,   # a point or corner: 6 multiply-adds, a three-way max, a compare
+    "shadow_box": 14,    # a cluster's box: per half-plane its largest value over the box (2 selects, 2 multiply-adds)
 }
 # instrumented counters (spm_build_opts.d_stats order)
 STAT_NAMES = ["tiles", "walk_steps", "lane_bound", "wave_vis", "relevance", "lane_edge", "one_edge_hides", "accept",
               "occ_cache_tests", "occ_cache_hits", "segment_lanes", "cluster_members", "cluster_members_tried",
-              "clusters_hidden", "cluster_members_umbra"]
+              "clusters_hidden", "cluster_members_umbra", "cluster_members_umbra_tested"]
 WORKLOADS = {
     "maze2048": "maze-2048: 2048x2048 grid, randomized-DFS maze of 64x64 cells (32 px, 4 px walls, exact union "
                 "boundary), 4 exit segment sources on the outer boundary, seed %d",
@@ -332,8 +336,14 @@ def main():
     scene, b, G, ms_step, stage_avg, counts = _measure(spm, torch, np, args.workload, args.seed, args.tile,
                                                        args.steps, args.warmup)
     W, H = scene.width, scene.height
-    ops = (counts["lane_bound"] * ALG["bound"] + counts["accept"] * ALG["accept"]
-           + counts["lane_edge"] * ALG["lane_edge"] + counts["segment_lanes"] * ALG["segment"])
+    # the cluster walk tests every cluster it takes, and the members of the open ones, against the 64 cached edges
+    cluster_walk = counts["cluster_members"] > 0
+    units = {"bound": counts["lane_bound"], "accept": counts["accept"], "lane_edge": counts["lane_edge"],
+             "segment": counts["segment_lanes"],
+             "shadow_point": 64 * counts["cluster_members_umbra_tested"],
+             "shadow_box": 64 * counts["walk_steps"] if cluster_walk else 0}
+    ops = sum(units[k] * ALG[k] for k in units)
+    ops_pixel_only = sum(units[k] * ALG[k] for k in ("bound", "accept", "lane_edge", "segment"))
     t_pix = stage_avg["pixel"] * 1e-3
     achieved = ops / t_pix / 1e12
     peak = PEAK_LANE_OPS / 1e12
@@ -364,8 +374,8 @@ def main():
                      "traffic": traffic, "kernel": "k_pixel",
                      "algorithmic_lane_ops_per_launch": ops,
                      "ops_per_unit": ALG,
-                     "units_per_launch": {"bound": counts["lane_bound"], "accept": counts["accept"],
-                                          "lane_edge": counts["lane_edge"], "segment": counts["segment_lanes"]},
+                     "units_per_launch": units,
+                     "frac_without_shadow_tests": ops_pixel_only / t_pix / 1e12 / peak,
                      "k_pixel_ms": stage_avg["pixel"],
                      "counters": counters},
         "stages_ms": stage_avg,

@@ -165,7 +165,7 @@ int spm_timer_elapsed(spm_timer* t, float* ms /* [SPM_N_STAGES] */, int32_t* n_b
  * [10] lane closest-point computations for segment sources, [11] cluster
  * members within the bound, [12] cluster members tried, [13] clusters hidden
  * whole, [14] cluster members that a cached edge hides from the whole tile
- * (not tried); the rest stay zero. */
+ * (not tried), [15] cluster members tested against the cached edges' umbrae. */
 #define SPM_N_STATS 16
 typedef struct {
   int32_t tile_w, tile_h;

@@ -28,7 +28,7 @@
 namespace spm {
 
 enum { ST_TILES = 0, ST_BATCHES, ST_BOUND, ST_VISWAVE, ST_RELEV, ST_LANEEDGE, ST_OCCL, ST_ACCEPT, ST_CACHE_TEST,
-       ST_CACHE_HIT, ST_SEG_LANE, ST_CL_MEMBERS, ST_CL_TRIED, ST_CL_HIDDEN, ST_CL_UMBRA, ST_COUNT };
+       ST_CACHE_HIT, ST_SEG_LANE, ST_CL_MEMBERS, ST_CL_TRIED, ST_CL_HIDDEN, ST_CL_UMBRA, ST_CL_UMBRA_TESTS, ST_COUNT };
 
 // Packs two values of magnitude below 2^15 into one register, and back.
 __device__ __forceinline__ int pack16(int lo, int hi) { return (int)(((unsigned)lo & 0xffffu) | ((unsigned)hi << 16)); }
@@ -922,6 +922,7 @@ __device__ __forceinline__ int tile_work(int tile, int W, int H, int W32, int G,
           const u64 pts = mm & ballot(b.x == b.z && b.y == b.w);
           oc.umbra_filter(pts, b.x, b.y, mm);
           if (STATS) st[ST_CL_UMBRA] += __popcll(pts & ~mm);
+          if (STATS) st[ST_CL_UMBRA_TESTS] += __popcll(pts);
         }
         while (mm) {
           // the least estimate first (the likely winner tightens the bounds for the rest)
