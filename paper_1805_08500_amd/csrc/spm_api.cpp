@@ -455,6 +455,14 @@ int batch_devs(const spm_batch* b, const BatchLayout& B, char* ws, std::vector<D
   for (int i = 0; i < n; ++i) {
     const int tw = b->tile_w ? b->tile_w[i] : 8;
     fill_dev(devs[i], &b->scenes[i], &b->outs[i], ws + B.off_scene[i], B.L[i], tw, nullptr);
+  }
+  // Pair visibility by rows with the occluders' shadows does the least work per pair, but one scene of a
+  // few hundred generators gives it too few wavefronts; a batch whose scenes together give enough takes it
+  // for every scene that would test pairs.
+  long long row_waves = 0;
+  for (int i = 0; i < n; ++i) row_waves += rowseg_prefix(devs[i].Gmax);
+  for (int i = 0; i < n; ++i) {
+    if (SPM_GV_ROWS && row_waves >= kGvRowsBatchWaves && devs[i].gv_sub <= 0) devs[i].gv_sub = -2;
     plan_add(p, devs[i]);
   }
   p.pixel_waves = b->pixel_waves;

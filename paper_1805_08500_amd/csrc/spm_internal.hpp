@@ -73,6 +73,7 @@ constexpr int kGvSpreadMaxGen = SPM_GV_SPREAD_MAX_GEN;   // pairs dealt round-ro
 #ifndef SPM_GV_ROWS
 #define SPM_GV_ROWS 1
 #endif
+constexpr long long kGvRowsBatchWaves = 4096;   // a batch uses the row mode when it would give the batch this many wavefronts
 constexpr int kGvSeg = 256;   // beyond: one wavefront per (row, 256 columns) with an occluder cache
 
 // Generator visibility by row segments: row r holds the pairs (r, u < r) in
