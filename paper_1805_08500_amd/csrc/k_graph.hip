@@ -892,7 +892,7 @@ __global__ __launch_bounds__(1024) void k_relax_queue(S src, int Gcap, int m0idx
   const int tid = threadIdx.x, nt = blockDim.x, lane = lane_id();
   const int G = d.misc[MISC_G];
   const int RW = d.RW, nsrc = d.np + d.ns;
-  const u64* m0 = d.rmask + m0idx * RW;
+  const u64* m0 = d.rmask + (m0idx >= 0 ? m0idx : 0) * RW;
   for (int g = tid; g < G; g += nt) {
     cost[g] = d.costpos[g];
     const int4 r = d.gxy[g];
@@ -902,13 +902,38 @@ __global__ __launch_bounds__(1024) void k_relax_queue(S src, int Gcap, int m0idx
   for (int k = tid; k < (G + 31) / 32; k += nt) inq[k] = 0u;
   if (tid == 0) { head = 0; tail = 0; pending = 0; reached = 0; }
   __syncthreads();
-  // the corners the last chip-wide round lowered: their arcs out are still to relax
-  for (int v = nsrc + tid; v < G; v += nt) {
-    if ((m0[v >> 6] >> (v & 63)) & 1ull) {
-      atomicOr(&inq[v >> 5], 1u << (v & 31));
-      const int t = atomicAdd(&tail, 1);
-      ring[t] = v;
-      atomicAdd(&pending, 1);
+  if (m0idx >= 0) {
+    // the corners the last chip-wide round lowered: their arcs out are still to relax
+    for (int v = nsrc + tid; v < G; v += nt) {
+      if ((m0[v >> 6] >> (v & 63)) & 1ull) {
+        atomicOr(&inq[v >> 5], 1u << (v & 31));
+        const int t = atomicAdd(&tail, 1);
+        ring[t] = v;
+        atomicAdd(&pending, 1);
+      }
+    }
+  } else {
+    // from the sources (no chip-wide rounds before): every corner takes its best arc from a source
+    // (sources cost 0; the same double sum as the other kernels), and the corners reached are queued
+    for (int v = nsrc + tid; v < G; v += nt) {
+      const int2 pv = xy[v];
+      double best = INFINITY;
+      for (int k = 0; 64 * k < nsrc; ++k) {
+        u64 m = d.vis[(size_t)v * RW + k];
+        if (nsrc - 64 * k < 64) m &= (1ull << (nsrc - 64 * k)) - 1ull;
+        while (m) {
+          const int u = 64 * k + __builtin_ctzll(m);
+          m &= m - 1;
+          best = fmin(best, 0.0 + arc_len4(d.gxy[u], pv.x, pv.y));
+        }
+      }
+      if (best < INFINITY) {
+        cost[v] = (u64)__double_as_longlong(best);
+        atomicOr(&inq[v >> 5], 1u << (v & 31));
+        const int t = atomicAdd(&tail, 1);
+        ring[t] = v;
+        atomicAdd(&pending, 1);
+      }
     }
   }
   __syncthreads();
@@ -1102,23 +1127,6 @@ template <class S>
 hipError_t launch_relax(const S& src, const Plan& p, hipStream_t s) {
   const long long nw = p.total[STG_RELAXW];
   const unsigned wblocks = (unsigned)((nw + 255) / 256);
-  // the large early rounds chip-wide: without barriers then one exact round, or kRelaxWideRounds rounds
-  int m0idx = kRelaxWideRounds % 3, rounds0 = kRelaxWideRounds;
-  if (kRelaxChaos > 0) {
-    const bool adapt = p.maxGmax > kChaosAdaptMinGen;
-    m0idx = 2;
-    rounds0 = (adapt ? kRelaxChaosMax : kRelaxChaos) + 1;
-    if (nw > 0) {
-      if (adapt)
-        hipLaunchKernelGGL((k_relax_chaos<S, true>), dim3(wblocks), dim3(256), 0, s, src, kRelaxChaosMax);
-      else
-        hipLaunchKernelGGL((k_relax_chaos<S, false>), dim3(wblocks), dim3(256), 0, s, src, kRelaxChaos);
-      hipLaunchKernelGGL(k_relax_wide<S>, dim3(wblocks), dim3(256), 0, s, src, 1);
-    }
-  } else if (nw > 0) {
-    for (int r = 0; r < kRelaxWideRounds; ++r)
-      hipLaunchKernelGGL(k_relax_wide<S>, dim3(wblocks), dim3(256), 0, s, src, r);
-  }
   const int RWcap = p.maxRW > 0 ? p.maxRW : 1;
   const int Gcap = p.maxGmax > 0 ? p.maxGmax : 1;
   const size_t chg = 2 * (size_t)RWcap * sizeof(u64);
@@ -1133,7 +1141,31 @@ hipError_t launch_relax(const S& src, const Plan& p, hipStream_t s) {
   };
   hipError_t e = hipSuccess;
   const size_t shm_q = relax_queue_lds_bytes(Gcap);
-  if (kRelaxQueue && kRelaxChaos > 0 && p.maxGmax > kChaosAdaptMinGen && shm_q + 64 <= lim) {
+  const bool adapt = p.maxGmax > kChaosAdaptMinGen;
+  const bool batch = p.total[STG_SCENE] > 1;
+  if (kRelaxQueueSrc > 0 && (batch || kRelaxQueueSrc > 1) && !adapt && shm_q + 64 <= lim) {
+    // small graphs: the whole relaxation on the work queue, from the sources, one workgroup per scene
+    if ((e = big((const void*)k_relax_queue<S>, shm_q)) != hipSuccess) return e;
+    hipLaunchKernelGGL((k_relax_queue<S>), grid, dim3(kRelaxThreads), shm_q, s, src, Gcap, -1, 0);
+    return hipGetLastError();
+  }
+  // the large early rounds chip-wide: without barriers then one exact round, or kRelaxWideRounds rounds
+  int m0idx = kRelaxWideRounds % 3, rounds0 = kRelaxWideRounds;
+  if (kRelaxChaos > 0) {
+    m0idx = 2;
+    rounds0 = (adapt ? kRelaxChaosMax : kRelaxChaos) + 1;
+    if (nw > 0) {
+      if (adapt)
+        hipLaunchKernelGGL((k_relax_chaos<S, true>), dim3(wblocks), dim3(256), 0, s, src, kRelaxChaosMax);
+      else
+        hipLaunchKernelGGL((k_relax_chaos<S, false>), dim3(wblocks), dim3(256), 0, s, src, kRelaxChaos);
+      hipLaunchKernelGGL(k_relax_wide<S>, dim3(wblocks), dim3(256), 0, s, src, 1);
+    }
+  } else if (nw > 0) {
+    for (int r = 0; r < kRelaxWideRounds; ++r)
+      hipLaunchKernelGGL(k_relax_wide<S>, dim3(wblocks), dim3(256), 0, s, src, r);
+  }
+  if (kRelaxQueue && kRelaxChaos > 0 && adapt && shm_q + 64 <= lim) {
     // deep graphs: the rest without rounds
     if ((e = big((const void*)k_relax_queue<S>, shm_q)) != hipSuccess) return e;
     hipLaunchKernelGGL((k_relax_queue<S>), grid, dim3(kRelaxThreads), shm_q, s, src, Gcap, m0idx, rounds0);

@@ -47,6 +47,10 @@ constexpr int kChaosSlots = 8;     // progress marks, spread over cache lines to
 #define SPM_RELAX_QUEUE 1
 #endif
 constexpr int kRelaxQueue = SPM_RELAX_QUEUE;   // large graphs finish their relaxation on a work queue
+#ifndef SPM_RELAX_QUEUE_SRC
+#define SPM_RELAX_QUEUE_SRC 1
+#endif
+constexpr int kRelaxQueueSrc = SPM_RELAX_QUEUE_SRC;   // small graphs relax on the queue alone: 1 batches, 2 all
 constexpr int kIngestFuseMax = 1024;   // scenes up to that many vertices ingest in the generator-table launch
 constexpr int kDefaultStrip = 1;      // tiles per pixel-stage work item
 constexpr int kDefaultSamples = 3;    // seed searches per pixel tile
