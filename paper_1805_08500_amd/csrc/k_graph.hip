@@ -516,6 +516,7 @@ __device__ __forceinline__ double arc_len4(int4 u, int vx, int vy) {
 constexpr int kRelaxFront = 2048;   // largest frontier kept as a list (push rounds)
 constexpr int kRelaxQueueSlack = 64;   // work-queue ring entries beyond one per generator
 constexpr int kRelaxQueueSpin = 1 << 22;   // spin limit of the work queue's waits (about a second)
+constexpr long long kRelaxListMaxWords = 16384;   // matrix words (corner rows) up to which the queue builds lists
 
 // A lower bound, in double, of the arc weight from u (doubled coordinates
 // x, y, x2, y2) to the corner (vx, vy): the hardware float square root with a
@@ -874,21 +875,25 @@ __global__ __launch_bounds__(1024) void k_relax(S src, int Gcap, int RWcap, int 
 // LDS: cost (u64) and corner coordinates (int2) per position, the ring of
 // positions (Gcap + 64 entries, -1 = empty) and the queued flags.
 size_t relax_queue_lds_bytes(int Gcap) {
-  return (size_t)Gcap * 16 + (size_t)(Gcap + kRelaxQueueSlack) * 4 + (size_t)((Gcap + 31) / 32) * 4 + 64;
+  return (size_t)Gcap * 16 + (size_t)(Gcap + kRelaxQueueSlack) * 4 + (size_t)((Gcap + 31) / 32) * 4 + 64 +
+         (size_t)(Gcap + 1) * 4;
 }
 
 template <class S>
-__global__ __launch_bounds__(1024) void k_relax_queue(S src, int Gcap, int m0idx, int rounds0) {
+__global__ __launch_bounds__(1024) void k_relax_queue(S src, int Gcap, int m0idx, int rounds0, int lds_bytes) {
   int sc, one;
   if (!src.locate(STG_SCENE, blockIdx.x, sc, one)) return;
   const Dev& d = src.scene(sc);
   extern __shared__ u64 shm[];
-  __shared__ int head, tail, pending, reached;
+  __shared__ int head, tail, pending, reached, narcs;
   u64* cost = shm;
   int2* xy = (int2*)(shm + Gcap);
   const int cap = Gcap + kRelaxQueueSlack;
   int* ring = (int*)(xy + Gcap);
   unsigned* inq = (unsigned*)(ring + cap);
+  int* off = (int*)(inq + (Gcap + 31) / 32);   // adjacency list offsets (Gcap + 1), then the lists (u16)
+  unsigned short* adj = (unsigned short*)(off + Gcap + 1);
+  const long long adj_cap = ((long long)lds_bytes - (long long)((char*)adj - (char*)shm)) / 2;
   const int tid = threadIdx.x, nt = blockDim.x, lane = lane_id();
   const int G = d.misc[MISC_G];
   const int RW = d.RW, nsrc = d.np + d.ns;
@@ -900,8 +905,69 @@ __global__ __launch_bounds__(1024) void k_relax_queue(S src, int Gcap, int m0idx
   }
   for (int k = tid; k < cap; k += nt) ring[k] = -1;
   for (int k = tid; k < (G + 31) / 32; k += nt) inq[k] = 0u;
-  if (tid == 0) { head = 0; tail = 0; pending = 0; reached = 0; }
+  for (int g = tid; g <= G; g += nt) off[g] = 0;
+  if (tid == 0) { head = 0; tail = 0; pending = 0; reached = 0; narcs = 0; }
   __syncthreads();
+  // Corner-corner arcs as adjacency lists in LDS for small matrices whose lists fit (16-bit positions): one
+  // pass counts the corners of each row, a scan gives the offsets, a second pass writes them.  Then relaxing
+  // a corner reads no global memory.  Otherwise the rows are read from the matrix (for the maze's 1 MB
+  // matrix the two passes by one workgroup cost more than they save: 0.82 -> 0.92 ms).
+  const int ncr = G - nsrc;
+  const long long nitems = (long long)ncr * RW;
+  auto arc_word = [&](long long it, int& u, int& k) -> u64 {
+    u = nsrc + (int)(it / RW);
+    k = (int)(it - (long long)(u - nsrc) * RW);
+    u64 w = d.vis[(size_t)u * RW + k];
+    const int lo = nsrc - 64 * k, hi = G - 64 * k;   // keep the corners nsrc .. G - 1
+    if (lo > 0) w = lo >= 64 ? 0ull : (w & (~0ull << lo));
+    if (hi < 64) w = hi <= 0 ? 0ull : (w & ((1ull << hi) - 1ull));
+    return w;
+  };
+  const bool short_ids = G <= 65535 && nitems <= kRelaxListMaxWords;
+  if (short_ids) {
+    for (long long it = tid; it < nitems; it += nt) {
+      int u, k;
+      const u64 w = arc_word(it, u, k);
+      if (w) atomicAdd(&off[u + 1], __popcll(w));
+    }
+  }
+  __syncthreads();
+  if (short_ids && tid < 64) {
+    // inclusive scan of off[1..G] by one wavefront, 64 at a time, carried serially
+    int carry = 0;
+    for (int b = 1; b <= G; b += 64) {
+      const int g = b + lane;
+      int x = g <= G ? off[g] : 0;
+#pragma unroll
+      for (int o = 1; o < 64; o <<= 1) {
+        const int y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
+      }
+      if (g <= G) off[g] = carry + x;
+      carry += __shfl(x, 63, 64);
+    }
+    if (lane == 0) narcs = carry;
+  }
+  __syncthreads();
+  const bool lists = short_ids && (long long)narcs <= adj_cap;   // the same in every thread
+  if (lists) {
+    // each row's next free entry, kept in the ring (cleared after)
+    for (int g = tid; g < G; g += nt) ring[g] = off[g];
+    __syncthreads();
+    for (long long it = tid; it < nitems; it += nt) {
+      int u, k;
+      u64 w = arc_word(it, u, k);
+      if (!w) continue;
+      const int at = atomicAdd(&ring[u], __popcll(w));
+      for (int j = 0; w; ++j) {
+        adj[at + j] = (unsigned short)(k * 64 + __builtin_ctzll(w));
+        w &= w - 1;
+      }
+    }
+    __syncthreads();
+    for (int k = tid; k < cap; k += nt) ring[k] = -1;
+    __syncthreads();
+  }
   if (m0idx >= 0) {
     // the corners the last chip-wide round lowered: their arcs out are still to relax
     for (int v = nsrc + tid; v < G; v += nt) {
@@ -981,28 +1047,36 @@ __global__ __launch_bounds__(1024) void k_relax_queue(S src, int Gcap, int m0idx
                                                                          __HIP_MEMORY_SCOPE_WORKGROUP));
     const int2 pu2 = xy[u];
     const int4 pu = make_int4(pu2.x, pu2.y, pu2.x, pu2.y);
-    for (int k0 = 0; k0 < RW; k0 += kWave) {
-      const int k = k0 + lane;
-      u64 m = k < RW ? d.vis[(size_t)u * RW + k] : 0ull;
-      while (m) {
-        const int v = k * 64 + __builtin_ctzll(m);
-        m &= m - 1;
-        if (v < nsrc || v >= G) continue;   // sources keep cost 0
-        const double cv = __longlong_as_double((long long)__hip_atomic_load(&cost[v], __ATOMIC_RELAXED,
-                                                                             __HIP_MEMORY_SCOPE_WORKGROUP));
-        if (!(cu < cv)) continue;
-        const int2 pv = xy[v];
-        if (!(cu + arc_lower(pu, pv.x, pv.y) < cv)) continue;
-        const double cand = cu + arc_len4(pu, pv.x, pv.y);
-        if (!(cand < cv)) continue;
-        const u64 ob = atomicMin(&cost[v], (u64)__double_as_longlong(cand));
-        if (__longlong_as_double((long long)ob) > cand) {
-          const unsigned bit = 1u << (v & 31);
-          if (!(atomicOr(&inq[v >> 5], bit) & bit)) {
-            atomicAdd(&pending, 1);
-            const int t = atomicAdd(&tail, 1);
-            __hip_atomic_store(&ring[t % cap], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-          }
+    // relax u -> v (a corner), queueing v when it is lowered and not queued yet
+    auto relax = [&](int v) {
+      const double cv = __longlong_as_double((long long)__hip_atomic_load(&cost[v], __ATOMIC_RELAXED,
+                                                                           __HIP_MEMORY_SCOPE_WORKGROUP));
+      if (!(cu < cv)) return;
+      const int2 pv = xy[v];
+      if (!(cu + arc_lower(pu, pv.x, pv.y) < cv)) return;
+      const double cand = cu + arc_len4(pu, pv.x, pv.y);
+      if (!(cand < cv)) return;
+      const u64 ob = atomicMin(&cost[v], (u64)__double_as_longlong(cand));
+      if (__longlong_as_double((long long)ob) > cand) {
+        const unsigned bit = 1u << (v & 31);
+        if (!(atomicOr(&inq[v >> 5], bit) & bit)) {
+          atomicAdd(&pending, 1);
+          const int t = atomicAdd(&tail, 1);
+          __hip_atomic_store(&ring[t % cap], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        }
+      }
+    };
+    if (lists) {
+      const int a1 = off[u + 1];
+      for (int i = off[u] + lane; i < a1; i += kWave) relax((int)adj[i]);
+    } else {
+      for (int k0 = 0; k0 < RW; k0 += kWave) {
+        const int k = k0 + lane;
+        u64 m = k < RW ? d.vis[(size_t)u * RW + k] : 0ull;
+        while (m) {
+          const int v = k * 64 + __builtin_ctzll(m);
+          m &= m - 1;
+          if (v >= nsrc && v < G) relax(v);   // sources keep cost 0
         }
       }
     }
@@ -1141,12 +1215,14 @@ hipError_t launch_relax(const S& src, const Plan& p, hipStream_t s) {
   };
   hipError_t e = hipSuccess;
   const size_t shm_q = relax_queue_lds_bytes(Gcap);
+  // the queue kernel takes what LDS a workgroup may have beyond its tables for its adjacency lists
+  const size_t shm_qr = lim > 256 + shm_q ? lim - 256 : shm_q;
   const bool adapt = p.maxGmax > kChaosAdaptMinGen;
   const bool batch = p.total[STG_SCENE] > 1;
   if (kRelaxQueueSrc > 0 && (batch || kRelaxQueueSrc > 1) && !adapt && shm_q + 64 <= lim) {
     // small graphs: the whole relaxation on the work queue, from the sources, one workgroup per scene
-    if ((e = big((const void*)k_relax_queue<S>, shm_q)) != hipSuccess) return e;
-    hipLaunchKernelGGL((k_relax_queue<S>), grid, dim3(kRelaxThreads), shm_q, s, src, Gcap, -1, 0);
+    if ((e = big((const void*)k_relax_queue<S>, shm_qr)) != hipSuccess) return e;
+    hipLaunchKernelGGL((k_relax_queue<S>), grid, dim3(kRelaxThreads), shm_qr, s, src, Gcap, -1, 0, (int)shm_qr);
     return hipGetLastError();
   }
   // the large early rounds chip-wide: without barriers then one exact round, or kRelaxWideRounds rounds
@@ -1167,8 +1243,9 @@ hipError_t launch_relax(const S& src, const Plan& p, hipStream_t s) {
   }
   if (kRelaxQueue && kRelaxChaos > 0 && adapt && shm_q + 64 <= lim) {
     // deep graphs: the rest without rounds
-    if ((e = big((const void*)k_relax_queue<S>, shm_q)) != hipSuccess) return e;
-    hipLaunchKernelGGL((k_relax_queue<S>), grid, dim3(kRelaxThreads), shm_q, s, src, Gcap, m0idx, rounds0);
+    if ((e = big((const void*)k_relax_queue<S>, shm_qr)) != hipSuccess) return e;
+    hipLaunchKernelGGL((k_relax_queue<S>), grid, dim3(kRelaxThreads), shm_qr, s, src, Gcap, m0idx, rounds0,
+                       (int)shm_qr);
   } else if (shm_v + static_lds <= lim) {
     if ((e = big((const void*)k_relax<S, true, true>, shm_v)) != hipSuccess) return e;
     hipLaunchKernelGGL((k_relax<S, true, true>), grid, dim3(kRelaxThreads), shm_v, s, src, Gcap, RWcap, m0idx, rounds0);
