@@ -160,6 +160,36 @@ def test_edge_cases(oracle_mod, spm):
         _full(oracle_mod, spm, sc, name, max_ambiguous=bound.get(name, 0.05))
 
 
+def test_edge_cases_every_walk_bitwise(spm):
+    """The edge-case scenes (ragged tiles, a single pixel, an empty cache, a source on the map's border,
+    unreachable pixels) with every walk of the pixel stage forced: the same map bit for bit."""
+    import torch
+    cases = [
+        Scene(37, 23, [], np.asarray([[5, 9]]), None),
+        Scene(29, 31, [], None, np.asarray([[3, 3, 27, 20]])),
+        Scene(1, 1, [], np.asarray([[0, 0]]), None),
+        Scene(200, 3, [_rect_poly(50, 1, 60, 2)], np.asarray([[0, 0]]), None),
+        Scene(40, 40, [np.asarray([(10, 0), (12, 0), (12, 40), (10, 40)])], np.asarray([[2, 20]]), None),
+        Scene(20, 20, [_rect_poly(12, 12, 16, 16)], None, np.asarray([[0, 0, 10, 10]])),
+        Scene(24, 24, [np.asarray([(4, 4), (14, 4), (14, 14)])], np.asarray([[20, 2]]), None),
+        random_small(11, "blocks"),
+    ]
+    for sc in cases:
+        ds = spm.DeviceScene(sc)
+        ref = None
+        for w in (0, 1, 2, 3, 4):
+            b = spm.Builder(ds, walk=w)
+            b.build()
+            torch.cuda.synchronize()
+            h = b.map.host()
+            if ref is None:
+                ref = h
+            else:
+                assert np.array_equal(ref["dist"], h["dist"]) and np.array_equal(ref["parent"], h["parent"]), \
+                    f"walk {w} on {sc.width}x{sc.height}"
+        _say(f"[parity] every walk {sc.width}x{sc.height}")
+
+
 def test_max_side_sampled(oracle_mod, spm):
     scene = Scene(8192, 8192, [_rect_poly(4000, 100, 4100, 8100), _rect_poly(1000, 3000, 3900, 3050)],
                   np.asarray([[10, 10]]), np.asarray([[8000, 8000, 8190, 7000]]))
