@@ -872,8 +872,13 @@ __global__ __launch_bounds__(1024) void k_relax(S src, int Gcap, int RWcap, int 
 // weight and sum as the other kernels, and the minimum over the same candidate
 // values is reached whatever the order (the costs only fall to the one fixed
 // point), so the costs are the same bits as k_relax's.
+// Two starts: after the chip-wide rounds (m0idx >= 0: the corners that round
+// lowered are queued), or from the sources alone (m0idx < 0, batches of small
+// graphs: every corner takes its best arc from a source and the reached ones
+// are queued; one workgroup per scene).
 // LDS: cost (u64) and corner coordinates (int2) per position, the ring of
-// positions (Gcap + 64 entries, -1 = empty) and the queued flags.
+// positions (Gcap + 64 entries, -1 = empty), the queued flags, the adjacency
+// list offsets (Gcap + 1) and, in the rest of lds_bytes, the lists (u16).
 size_t relax_queue_lds_bytes(int Gcap) {
   return (size_t)Gcap * 16 + (size_t)(Gcap + kRelaxQueueSlack) * 4 + (size_t)((Gcap + 31) / 32) * 4 + 64 +
          (size_t)(Gcap + 1) * 4;
