@@ -8,10 +8,11 @@
 //   k_genvis   every (corner, generator) arc of the visibility graph, as a
 //              bit matrix (exact predicates; by pairs with lanes over edges,
 //              or lanes over generators), and the columns of segment sources;
-//   k_relax_wide, k_relax
+//   k_relax_chaos, k_relax_wide, k_relax, k_relax_queue
 //              Bellman-Ford over that matrix in double precision, iterated to
 //              its fixed point (which Dijkstra also reaches): the first rounds
-//              chip-wide, the rest in one workgroup;
+//              chip-wide, the rest in one workgroup (rounds, or a work queue for
+//              deep graphs; batches of small graphs on the queue alone);
 //   k_gsort_parents
 //              the reached generators ordered by (float cost, id), the order
 //              the pixel stage walks them in; and each corner's parent: the
