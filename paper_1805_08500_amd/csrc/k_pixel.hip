@@ -63,12 +63,14 @@ struct OccCache {
   // so each h_i is an exact int32 value.  A lane whose edge does not have U
   // strictly on its obstacle side (or an empty slot) gets h_1 = 1: never.
   int ab0, c0, ab1, c1, ab2, c2;   // (A_i | B_i << 16, C_i)
+  unsigned pp0, pp1, pp2;          // max(A_i, 0) | max(B_i, 0) << 16
   int ux0, uy0, ux1, uy1;          // U (wave-uniform)
   __device__ __forceinline__ void reset() {
     w = v = 0u;
     slot = 0;
     ux0 = uy0 = ux1 = uy1 = 0;
     ab0 = c0 = ab1 = ab2 = c2 = 0;
+    pp0 = pp1 = pp2 = 0u;
     c1 = 1;
   }
   // Sets this lane's umbra from its edge (every lane; exact integer work).
@@ -101,6 +103,9 @@ struct OccCache {
     // cross(e, g - v) > 0:  ey gx - ex gy + (ex vy - ey vx) < 0
     ab2 = pack16(ey, -ex);
     c2 = mul24(ex, vy) - mul24(ey, vx);
+    pp0 = (unsigned)pack16(max(a, 0), max(b, 0));
+    pp1 = ok ? (unsigned)pack16(max(-dy, 0), max(dx, 0)) : 0u;
+    pp2 = (unsigned)pack16(max(ey, 0), max(-ex, 0));
   }
   // Does some cached edge hide the point g from the whole of U (all three
   // h_i(g) < 0)?  Tested for the points g = (px, py) of lanes 0..kCluster-1
@@ -120,12 +125,16 @@ struct OccCache {
   // Does some cached edge hide the whole box K (kx0..ky1) from the whole of
   // U?  K lies in the (convex) umbra iff the largest value of each h_i over K
   // is negative.
+  // The largest value is the value at the corner (kx0, ky0) plus the positive
+  // parts of A_i and B_i times the box's extent (each partial sum is the value
+  // at a point of K, so every step stays an exact int32).
   __device__ __forceinline__ bool umbra_hides_box(int kx0, int ky0, int kx1, int ky1) const {
-    auto hmax = [&](int ab, int c) {
-      const int A = lo16(ab), B = hi16(ab);
-      return mad24(A, A > 0 ? kx1 : kx0, mad24(B, B > 0 ? ky1 : ky0, c));
+    const int dx = kx1 - kx0, dy = ky1 - ky0;
+    auto hmax = [&](int ab, unsigned pp, int c) {
+      return mad24(lo16(ab), kx0, mad24(hi16(ab), ky0, c)) +
+             mad24((int)(pp & 0xffffu), dx, mul24((int)(pp >> 16), dy));
     };
-    return ballot(max(max(hmax(ab0, c0), hmax(ab1, c1)), hmax(ab2, c2)) < 0) != 0ull;
+    return ballot(max(max(hmax(ab0, pp0, c0), hmax(ab1, pp1, c1)), hmax(ab2, pp2, c2)) < 0) != 0ull;
   }
   // does some cached edge hide the box (bx0..by1) from g?
   __device__ __forceinline__ bool hides(int gx, int gy, int bx0, int by0, int bx1, int by1) const {
@@ -885,11 +894,8 @@ __device__ __forceinline__ int tile_work(int tile, int W, int H, int W32, int G,
         const int c = wl + 64 * (int)(mk & 15u);
         const int np = readlane(ptr, wl) + 1;
         if (lane == wl) {
-          unsigned nk = 0xffffffffu;
-#pragma unroll
-          for (int q = 1; q < kClSlots; ++q)
-            if (q == np) nk = key[q];
-          hk = nk;
+          // np is wave-uniform: one indexed register move
+          hk = np < kClSlots ? key[np & (kClSlots - 1)] : 0xffffffffu;
           ptr = np;
         }
         if (STATS) st[ST_BATCHES] += 1;
@@ -909,10 +915,8 @@ __device__ __forceinline__ int tile_work(int tile, int W, int H, int W32, int G,
           const int2 kk = tab.clk[c * kCluster + lane];
           b = tab.clmb[c * kCluster + lane];
           k = kk.x;
-          if (k >= 0) {
-            kc = __int_as_float(kk.y);
-            ek = est_of(b, kc);
-          }
+          kc = __int_as_float(kk.y);   // +inf (and an empty box) past the end: then ek = +inf
+          ek = est_of(b, kc);
         }
         u64 mm = ballot(k >= 0 && ek <= UB);
         if (STATS) st[ST_CL_MEMBERS] += __popcll(mm);

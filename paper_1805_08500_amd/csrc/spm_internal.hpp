@@ -398,9 +398,10 @@ __device__ __forceinline__ unsigned wave_min_u32(unsigned v) {
   v = min(v, (unsigned)__builtin_amdgcn_update_dpp(-1, (int)v, 0x4E, 0xF, 0xF, false));   // quad_perm 2,3,0,1
   v = min(v, (unsigned)__builtin_amdgcn_update_dpp(-1, (int)v, 0x124, 0xF, 0xF, false));  // row_ror 4
   v = min(v, (unsigned)__builtin_amdgcn_update_dpp(-1, (int)v, 0x128, 0xF, 0xF, false));  // row_ror 8
-  const unsigned r0 = (unsigned)readlane((int)v, 0), r1 = (unsigned)readlane((int)v, 16);
-  const unsigned r2 = (unsigned)readlane((int)v, 32), r3 = (unsigned)readlane((int)v, 48);
-  return min(min(r0, r1), min(r2, r3));
+  // every lane of a row now holds the row's least: fold rows 0 -> 1, 2 -> 3, then 1 -> 3
+  v = min(v, (unsigned)__builtin_amdgcn_update_dpp(-1, (int)v, 0x142, 0xA, 0xF, false));  // row_bcast 15
+  v = min(v, (unsigned)__builtin_amdgcn_update_dpp(-1, (int)v, 0x143, 0xC, 0xF, false));  // row_bcast 31
+  return (unsigned)readlane((int)v, 63);
 }
 __device__ __forceinline__ float unif(float x) {
   return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(x)));
