@@ -205,14 +205,21 @@ struct OccCache {
   }
 };
 
-// Least unsigned value over lanes 0..7, returned in every lane (the caller
-// reads it from lane 0's group): two quad exchanges, then the half-row mirror
-// (lane i of each group of 8 takes lane 7 - i).
-__device__ __forceinline__ unsigned min8_u32(unsigned v) {
+// Least unsigned value over lanes 0..kCluster-1 (a cluster's members),
+// returned through a readlane: two quad exchanges and the half-row mirror
+// (lane i of each group of 8 takes lane 7 - i) give the least of each group of
+// 8, the row mirror that of each row of 16, a broadcast of lane 15 into the
+// next row that of lanes 0..31.
+__device__ __forceinline__ unsigned min_members_u32(unsigned v) {
+  static_assert(kCluster == 8 || kCluster == 16 || kCluster == 32, "cluster size");
   v = min(v, (unsigned)__builtin_amdgcn_update_dpp(-1, (int)v, 0xB1, 0xF, 0xF, false));    // quad_perm 1,0,3,2
   v = min(v, (unsigned)__builtin_amdgcn_update_dpp(-1, (int)v, 0x4E, 0xF, 0xF, false));    // quad_perm 2,3,0,1
   v = min(v, (unsigned)__builtin_amdgcn_update_dpp(-1, (int)v, 0x141, 0xF, 0xF, false));   // row_half_mirror
-  return (unsigned)readlane((int)v, 0);
+  if constexpr (kCluster > 8)
+    v = min(v, (unsigned)__builtin_amdgcn_update_dpp(-1, (int)v, 0x140, 0xF, 0xF, false));   // row_mirror
+  if constexpr (kCluster > 16)
+    v = min(v, (unsigned)__builtin_amdgcn_update_dpp(-1, (int)v, 0x142, 0xA, 0xF, false));   // row_bcast 15
+  return (unsigned)readlane((int)v, kCluster > 16 ? 31 : 0);
 }
 
 // Box (doubled pixel-centre coordinates) of the lanes set in m (m != 0; a
@@ -325,8 +332,13 @@ constexpr int kSeedWide = SPM_SEED_WIDE;   // candidates per round once a seed s
 //                from the whole tile is skipped at once, the members of the
 //                others are tried one by one.
 enum { kWalkCached = 0, kWalkRefill = 1, kWalkCost = 2, kWalkCluster = 3 };
-constexpr int kClSlots = 16;                                   // cluster estimates per lane
-constexpr int kClusterWalkMax = kClSlots * 64 * kCluster;      // 8192 generators
+// Cluster estimates per lane.  Sixteen, even where fewer would do: the walk
+// reads slot np of its sorted keys with a wave-uniform np, which the compiler
+// turns into one indexed register move for sixteen registers but into a chain
+// of compares and selects for eight.
+constexpr int kClSlots = 16;
+constexpr int kClusterWalkMax = 8192;   // generators
+static_assert(kClusterWalkMax <= kClSlots * 64 * kCluster, "cluster slots");
 constexpr int kEstWalkMax = 128 * 64;   // a lane owns up to 128 generators (two 64-bit taken masks)
 #ifndef SPM_REFILL_AUTO_MAX
 #define SPM_REFILL_AUTO_MAX 4096
@@ -931,7 +943,7 @@ __device__ __forceinline__ int tile_work(int tile, int W, int H, int W32, int G,
         while (mm) {
           // the least estimate first (the likely winner tightens the bounds for the rest)
           const float e_here = ((mm >> lane) & 1ull) ? ek : INFINITY;
-          const unsigned mk = min8_u32(__float_as_uint(e_here));
+          const unsigned mk = min_members_u32(__float_as_uint(e_here));
           const int jl = first_bit(ballot(__float_as_uint(e_here) == mk) & mm);
           mm &= ~(1ull << jl);
           if (__uint_as_float(mk) > UB) break;   // the bounds tightened since: the rest are larger still

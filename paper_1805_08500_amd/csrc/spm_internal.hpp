@@ -58,7 +58,10 @@ constexpr int kMaxStrip = 64;
 constexpr int kQueues = 8;         // pixel-stage work queues (one per XCD)
 constexpr int kQueueStride = 32;   // ints between queue counters (one 128-byte line each)
 constexpr int kOrderBins = 32;     // pixel-stage work classes (tiles ranked by a distance lower bound)
-constexpr int kCluster = 8;        // generators per spatial cluster of the pixel stage's cluster walk
+#ifndef SPM_CLUSTER
+#define SPM_CLUSTER 16
+#endif
+constexpr int kCluster = SPM_CLUSTER;   // generators per spatial cluster of the pixel stage's cluster walk (8, 16 or 32)
 #ifndef SPM_SEG_COLS
 #define SPM_SEG_COLS 16
 #endif
