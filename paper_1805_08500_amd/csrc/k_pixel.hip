@@ -692,7 +692,16 @@ struct GeoPacked {
   }
   __device__ __forceinline__ int4 chunk(int c) const { return chunks[c]; }
 };
-size_t packed_edge_lds_bytes(int E, int NC) { return (size_t)NC * 16 + (size_t)E * 8; }
+__host__ __device__ inline size_t packed_edge_lds_bytes(int E, int NC) {
+  return (size_t)NC * 16 + (size_t)((E + 1) / 2) * 16;   // chunk boxes, then the packed edges (16-byte units)
+}
+// The refilled walk also stages the generator boxes and float costs (20 bytes
+// a generator, after the packed edges) when the whole staging keeps two
+// 512-thread workgroups per CU; its refills then read them from LDS.
+constexpr size_t kStageLdsMax = 80 * 1024;
+__host__ __device__ inline bool refill_stages_tables(int Gmax, int E, int NC) {
+  return packed_edge_lds_bytes(E, NC) + (size_t)Gmax * 20 <= kStageLdsMax;
+}
 
 template <int TW, bool STATS, int WALK, class TAB, class GEO>
 __device__ __forceinline__ int tile_work(int tile, int W, int H, int W32, int G, const unsigned* __restrict__ inside,
@@ -1323,14 +1332,23 @@ void k_pixel(int W, int H, int W32, int Gmax, int* misc, const unsigned* __restr
     geo.edges = s_edges;
     geo.chunks = s_chunks;
   }
-  if constexpr (!LDSD && WALK == kWalkCluster) {
-    // chunk boxes, then the packed edges
+  if constexpr (!LDSD && (WALK == kWalkCluster || WALK == kWalkRefill)) {
+    // chunk boxes, then the packed edges (then, for the refilled walk, boxes and costs)
     int4* s_chunks = smem;
     uint2* s_pe = (uint2*)(s_chunks + NC);
     for (int k = t; k < NC; k += nt) s_chunks[k] = chunks_g[k];
     for (int k = t; k < E; k += nt) {
       const EdgeRec r = edges_g[k];
       s_pe[k] = make_uint2((unsigned)r.wx | ((unsigned)r.wy << 16), (unsigned)r.vx | ((unsigned)r.vy << 16));
+    }
+    if constexpr (WALK == kWalkRefill) {
+      if (refill_stages_tables(Gmax, E, NC)) {
+        int4* s_bb = smem + packed_edge_lds_bytes(E, NC) / 16;
+        float* s_cost = (float*)(s_bb + Gmax);
+        for (int k = t; k < G; k += nt) { s_bb[k] = sgbb_g[k]; s_cost[k] = sgcost_g[k]; }
+        tab.bb = s_bb;
+        tab.cost = s_cost;
+      }
     }
     __syncthreads();
     const GeoPacked gp{s_pe, ext, s_chunks, E, NC};
@@ -1454,9 +1472,11 @@ template <int TW, int WALK>
 static hipError_t launch_tw_walk(const Dev& d, hipStream_t s, int phase) {
   const size_t shm = pixel_lds_bytes(d.Gmax, d.E, d.NC);
   const bool lds = shm <= kPixelLdsMax;
-  if (!lds && WALK == kWalkCluster) {
-    // the cluster walk keeps the packed edges in LDS (at most 8192 edges: 66 KB)
-    const size_t pk = packed_edge_lds_bytes(d.E, d.NC);
+  if (!lds && (WALK == kWalkCluster || WALK == kWalkRefill)) {
+    // the cluster and refilled walks keep the packed edges in LDS (at most 8192 edges: 66 KB), the
+    // refilled walk also the boxes and costs when they fit
+    size_t pk = packed_edge_lds_bytes(d.E, d.NC);
+    if (WALK == kWalkRefill && refill_stages_tables(d.Gmax, d.E, d.NC)) pk += (size_t)d.Gmax * 20;
     if (phase == 1 && pk > kPixelLdsMax) {
       auto k0 = d.stats ? k_pixel<TW, true, false, WALK> : k_pixel<TW, false, false, WALK>;
       const hipError_t e = hipFuncSetAttribute((const void*)k0, hipFuncAttributeMaxDynamicSharedMemorySize, (int)pk);
