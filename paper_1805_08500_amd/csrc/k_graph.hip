@@ -682,7 +682,8 @@ __device__ __forceinline__ void parent_wave(const S& src, int wid) {
   int best = 0x7fffffff;
   if (p >= nsrc && c < INFINITY) {
     const int4 pv = d.gxy[p];
-    for (int k0 = 0; k0 < RW; k0 += 4) {
+    const int RWg = min(RW, (G + 63) >> 6);   // words of columns below G
+    for (int k0 = 0; k0 < RWg; k0 += 4) {
       double cu[4];
       int4 pu[4];
       int gu[4];
@@ -903,6 +904,7 @@ __global__ __launch_bounds__(1024) void k_relax_queue(S src, int Gcap, int m0idx
   const int tid = threadIdx.x, nt = blockDim.x, lane = lane_id();
   const int G = d.misc[MISC_G];
   const int RW = d.RW, nsrc = d.np + d.ns;
+  const int RWg = min(RW, (G + 63) >> 6);
   const u64* m0 = d.rmask + (m0idx >= 0 ? m0idx : 0) * RW;
   for (int g = tid; g < G; g += nt) {
     cost[g] = d.costpos[g];
@@ -1076,9 +1078,11 @@ __global__ __launch_bounds__(1024) void k_relax_queue(S src, int Gcap, int m0idx
       const int a1 = off[u + 1];
       for (int i = off[u] + lane; i < a1; i += kWave) relax((int)adj[i]);
     } else {
-      for (int k0 = 0; k0 < RW; k0 += kWave) {
+      // the words of columns below G (the rest of a row is never set): one pass of loads up to 4096
+      // corners, not a second dependent one
+      for (int k0 = 0; k0 < RWg; k0 += kWave) {
         const int k = k0 + lane;
-        u64 m = k < RW ? d.vis[(size_t)u * RW + k] : 0ull;
+        u64 m = k < RWg ? d.vis[(size_t)u * RW + k] : 0ull;
         while (m) {
           const int v = k * 64 + __builtin_ctzll(m);
           m &= m - 1;
