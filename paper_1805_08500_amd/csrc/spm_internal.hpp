@@ -690,12 +690,12 @@ __device__ __forceinline__ u64 wave_blocked_uniform(const GEO& d, int px, int py
     }
     }
   }
-  // exact vertex rule for lanes with an endpoint exactly on their line P-g
+  // exact vertex rule for lanes with an endpoint exactly on their line P-g: every vertex w (the start of
+  // one edge) of the chunks meeting the cone hull, lanes over the chunk's edges, one such lane P at a
+  // time (few lanes need it; on lattice-aligned scenes many tiles have some)
   u64 slow = ballot(dg) & need & ~blocked;
   if (slow) {
-    const bool mine = (slow >> lane) & 1ull;
-    const int len2 = mul24(gx - px, gx - px) + mul24(gy - py, gy - py);
-    for (int cb = 0; cb < d.NC; cb += kWave) {
+    for (int cb = 0; cb < d.NC && slow; cb += kWave) {
       int ci = cb + lane;
       bool hit = false;
       if (ci < d.NC) {
@@ -703,23 +703,33 @@ __device__ __forceinline__ u64 wave_blocked_uniform(const GEO& d, int px, int py
         hit = bb.x <= cx1 && bb.z >= cx0 && bb.y <= cy1 && bb.w >= cy0;
       }
       u64 cm = ballot(hit);
-      while (cm) {
+      while (cm && slow) {
         const int chunk = cb + first_bit(cm);
         cm &= cm - 1;
-        const int e0 = chunk * kChunk, e1 = min(e0 + kChunk, d.E);
-        for (int e = e0; e < e1; ++e) {
-          EdgeRec r = d.edge(e);
-          if (mine && !blk) {
-            int ow = mad24(A, r.wx, mad24(B, r.wy, C));
-            if (ow == 0) {
-              int dot = mul24(r.wx - px, gx - px) + mul24(r.wy - py, gy - py);
-              if (dot > 0 && dot < len2) {
-                EdgeExt x = d.ext[e];
-                if (into_interior(x.ux, x.uy, r.wx, r.wy, r.vx, r.vy, px - r.wx, py - r.wy) ||
-                    into_interior(x.ux, x.uy, r.wx, r.wy, r.vx, r.vy, gx - r.wx, gy - r.wy))
-                  blk = true;
-              }
+        const int e = chunk * kChunk + lane;
+        const bool have = e < d.E;
+        EdgeRec r = {0, 0, 0, 0, 0, 0, 0, 0};
+        if (have) r = d.edge(e);
+        u64 sm = slow;
+        while (sm) {
+          const int j = first_bit(sm);
+          sm &= sm - 1;
+          const int qx = readlane(px, j), qy = readlane(py, j);   // lane j's P
+          const int Aj = qy - gy, Bj = gx - qx;
+          const int Cj = -(mul24(Aj, qx) + mul24(Bj, qy));
+          const int len2 = mul24(gx - qx, gx - qx) + mul24(gy - qy, gy - qy);
+          bool on = false;
+          if (have && mad24(Aj, r.wx, mad24(Bj, r.wy, Cj)) == 0) {
+            const int dot = mul24(r.wx - qx, gx - qx) + mul24(r.wy - qy, gy - qy);
+            if (dot > 0 && dot < len2) {
+              const EdgeExt x = d.ext[e];
+              on = into_interior(x.ux, x.uy, r.wx, r.wy, r.vx, r.vy, qx - r.wx, qy - r.wy) ||
+                   into_interior(x.ux, x.uy, r.wx, r.wy, r.vx, r.vy, gx - r.wx, gy - r.wy);
             }
+          }
+          if (ballot(on)) {
+            slow &= ~(1ull << j);
+            if (lane == j) blk = true;
           }
         }
       }
