@@ -81,9 +81,18 @@ def _parse():
     return ap.parse_args()
 
 
-def _file_hash(path):
-    with open(path, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+def _file_hash(*paths):
+    h = hashlib.sha256()
+    for path in paths:
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def _pixel_source_hash():
+    """The pixel kernel's source: k_pixel.hip and the device header it includes."""
+    csrc = os.path.join(ROOT, "paper_1805_08500_amd", "csrc")
+    return _file_hash(os.path.join(csrc, "k_pixel.hip"), os.path.join(csrc, "spm_internal.hpp"))
 
 
 def _profile(name, kernel_src_hash):
@@ -355,7 +364,7 @@ def main():
     t_pix = stage_avg["pixel"] * 1e-3
     achieved = ops / t_pix / 1e12
     peak = PEAK_LANE_OPS / 1e12
-    src_hash = _file_hash(os.path.join(ROOT, "paper_1805_08500_amd", "csrc", "k_pixel.hip"))
+    src_hash = _pixel_source_hash()
     prof = _profile("k_pixel_%s_counters" % args.workload, src_hash)
     traffic = None
     counters = None
