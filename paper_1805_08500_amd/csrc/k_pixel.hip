@@ -808,7 +808,7 @@ __device__ __forceinline__ int tile_work(int tile, int W, int H, int W32, int G,
         bl |= wave_blocked_uniform<STATS>(geo, px, py, m, gx, gy, gv, gv ? nb.x : 0, gv ? nb.y : 0, gv ? nb.z : 0,
                                           gv ? nb.w : 0, false, 0, 0, 0, 0, bx0, by0, bx1, by1, nullptr, st, &found);
         if (found >= 0) {
-          if constexpr (WALK == kWalkCluster) oc.insert_umbra(geo.edge(found));
+          if constexpr (WALK == kWalkCluster || WALK == kWalkRefill) oc.insert_umbra(geo.edge(found));
           else oc.insert(geo.edge(found));
         }
       }
@@ -977,6 +977,10 @@ __device__ __forceinline__ int tile_work(int tile, int W, int H, int W32, int G,
       // once and no seed search is needed.
       int bx0, by0, bx1, by1;
       mask_box<TW>(act, i0, j0, bx0, by0, bx1, by1);
+      // the occluder cache starts with the edges around the tile; their umbrae hide single candidates
+      oc.fill_near(geo, bx0, by0, bx1, by1);
+      oc.ux0 = bx0; oc.uy0 = by0; oc.ux1 = bx1; oc.uy1 = by1;
+      oc.set_umbra();
       auto est_box = [&](int h) -> float {
         const int4 b = tab.box(h);
         const float dx = (float)max(max(b.x - bx1, bx0 - b.z), 0), dy = (float)max(max(b.y - by1, by0 - b.w), 0);
@@ -1052,6 +1056,8 @@ __device__ __forceinline__ int tile_work(int tile, int W, int H, int W32, int G,
               box_may_win(kc, kx0, ky0, kx1, ky1, qx0, qy1, qx1 - 2, qy1 + TH - 2, ubq[2]) ||
               box_may_win(kc, kx0, ky0, kx1, ky1, qx1, qy1, qx1 + TW - 2, qy1 + TH - 2, ubq[3])))
           continue;
+        // a point that one cached edge hides from the whole tile
+        if (kx0 == kx1 && ky0 == ky1 && oc.umbra_hides_box(kx0, ky0, kx1, ky1)) continue;
         try_gen(k, kc, kx0, ky0, kx1, ky1);
       }
     } else {
