@@ -251,8 +251,11 @@ struct PairCache {
   // cross(w - g, P - g) < 0 < cross(v - g, P - g).  Three open half-planes
   // h_i(P) = A_i Px + B_i Py + C_i < 0 (|A|, |B| <= 2^14, |C| < 2^30: exact in
   // int32); an empty slot gets h_0 = 1, never.
-  int sa[3], sb[3], sc[3];
+  // Every slot's coefficients go to this wavefront's LDS block (3 int4 a
+  // slot), where a test of slot e reads them at one address for all lanes.
+  int4* sh;
   __device__ __forceinline__ void set_shadow(int gx, int gy) {
+    int sa[3], sb[3], sc[3];
     const int wx = (int)(w & 0xffffu), wy = (int)(w >> 16), vx = (int)(v & 0xffffu), vy = (int)(v >> 16);
     const int a = wy - vy, b = vx - wx, c = -(a * wx + b * wy);
     const bool empty = w == v;
@@ -265,14 +268,19 @@ struct PairCache {
     sa[2] = vy - gy;
     sb[2] = -(vx - gx);
     sc[2] = mul24(vx - gx, gy) - mul24(vy - gy, gx);
+    const int l = lane_id();
+    sh[3 * l] = make_int4(sa[0], sb[0], sc[0], sa[1]);
+    sh[3 * l + 1] = make_int4(sb[1], sc[1], sa[2], sb[2]);
+    sh[3 * l + 2] = make_int4(sc[2], 0, 0, 0);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   }
   // lanes hold the points P (px, py): is P in the shadow of the slot-e edge? (e wave-uniform)
   __device__ __forceinline__ bool in_shadow(int e, int px, int py) const {
-    int h = -1 << 30;
-#pragma unroll
-    for (int i = 0; i < 3; ++i)
-      h = max(h, mad24(readlane(sa[i], e), px, mad24(readlane(sb[i], e), py, readlane(sc[i], e))));
-    return h < 0;
+    const int4 p0 = sh[3 * e], p1 = sh[3 * e + 1], p2 = sh[3 * e + 2];   // one address for every lane
+    return max(max(mad24(p0.x, px, mad24(p0.y, py, p0.z)), mad24(p0.w, px, mad24(p1.x, py, p1.y))),
+               mad24(p1.z, px, mad24(p1.w, py, p2.x))) < 0;
   }
 };
 
@@ -390,6 +398,8 @@ __device__ __forceinline__ void genvis_rows(const Dev& d, const Geo& geo, int wi
             gny = uni(d.gens[gpos].ny);
   const int u0 = s * kGvSeg, u1 = min(u0 + kGvSeg, r);
   PairCache pc;
+  __shared__ int4 s_shadow[4][64 * 3];   // 256-thread workgroups: four wavefronts
+  pc.sh = s_shadow[threadIdx.x >> 6];
   pc.fill_near(geo, gx, gy);
   pc.set_shadow(gx, gy);
   for (int ub = u0; ub < u1; ub += kWave) {
