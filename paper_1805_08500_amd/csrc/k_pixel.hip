@@ -34,6 +34,13 @@ enum { ST_TILES = 0, ST_BATCHES, ST_BOUND, ST_VISWAVE, ST_RELEV, ST_LANEEDGE, ST
 __device__ __forceinline__ int pack16(int lo, int hi) { return (int)(((unsigned)lo & 0xffffu) | ((unsigned)hi << 16)); }
 __device__ __forceinline__ int lo16(int x) { return (int)(short)(x & 0xffff); }
 __device__ __forceinline__ int hi16(int x) { return x >> 16; }
+// lo16(a) lo16(b) + hi16(a) hi16(b) + c in one instruction (v_dot2_i32_i16).
+// The products are exact and the sum wraps modulo 2^32, so the result is the
+// exact value whenever that fits an int32.
+typedef short spm_short2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ int dot2(int a, int b, int c) {
+  return __builtin_amdgcn_sdot2(__builtin_bit_cast(spm_short2, a), __builtin_bit_cast(spm_short2, b), c, false);
+}
 
 // Occluder cache of one tile: one obstacle edge per lane.  The exact test of
 // a candidate generator g against a tile first asks whether a single edge hides
@@ -112,13 +119,12 @@ struct OccCache {
   // whose bits are set in pts; the bits of the hidden ones are cleared from
   // keep.
   __device__ __forceinline__ void umbra_filter(u64 pts, int px, int py, u64& keep) const {
-    const int A0 = lo16(ab0), B0 = hi16(ab0), A1 = lo16(ab1), B1 = hi16(ab1), A2 = lo16(ab2), B2 = hi16(ab2);
+    const int pg = pack16(px, py);
 #pragma unroll
     for (int j = 0; j < kCluster; ++j) {
       if (!((pts >> j) & 1ull)) continue;
-      const int gx = readlane(px, j), gy = readlane(py, j);
-      const int h = max(max(mad24(A0, gx, mad24(B0, gy, c0)), mad24(A1, gx, mad24(B1, gy, c1))),
-                        mad24(A2, gx, mad24(B2, gy, c2)));
+      const int g = readlane(pg, j);   // (gx, gy), both below 2^15
+      const int h = max(max(dot2(ab0, g, c0), dot2(ab1, g, c1)), dot2(ab2, g, c2));
       if (ballot(h < 0)) keep &= ~(1ull << j);
     }
   }
@@ -129,11 +135,8 @@ struct OccCache {
   // parts of A_i and B_i times the box's extent (each partial sum is the value
   // at a point of K, so every step stays an exact int32).
   __device__ __forceinline__ bool umbra_hides_box(int kx0, int ky0, int kx1, int ky1) const {
-    const int dx = kx1 - kx0, dy = ky1 - ky0;
-    auto hmax = [&](int ab, unsigned pp, int c) {
-      return mad24(lo16(ab), kx0, mad24(hi16(ab), ky0, c)) +
-             mad24((int)(pp & 0xffffu), dx, mul24((int)(pp >> 16), dy));
-    };
+    const int k0 = pack16(kx0, ky0), ext = pack16(kx1 - kx0, ky1 - ky0);   // wave-uniform
+    auto hmax = [&](int ab, unsigned pp, int c) { return dot2((int)pp, ext, dot2(ab, k0, c)); };
     return ballot(max(max(hmax(ab0, pp0, c0), hmax(ab1, pp1, c1)), hmax(ab2, pp2, c2)) < 0) != 0ull;
   }
   // does some cached edge hide the box (bx0..by1) from g?
