@@ -251,8 +251,9 @@ struct PairCache {
   // cross(w - g, P - g) < 0 < cross(v - g, P - g).  Three open half-planes
   // h_i(P) = A_i Px + B_i Py + C_i < 0 (|A|, |B| <= 2^14, |C| < 2^30: exact in
   // int32); an empty slot gets h_0 = 1, never.
-  // Every slot's coefficients go to this wavefront's LDS block (3 int4 a
-  // slot), where a test of slot e reads them at one address for all lanes.
+  // Every slot's coefficients go to this wavefront's LDS block, (A_i | B_i
+  // << 16, C_i) in 2 int4 a slot, where a test of slot e reads them at one
+  // address for all lanes.
   int4* sh;
   __device__ __forceinline__ void set_shadow(int gx, int gy) {
     int sa[3], sb[3], sc[3];
@@ -269,18 +270,16 @@ struct PairCache {
     sb[2] = -(vx - gx);
     sc[2] = mul24(vx - gx, gy) - mul24(vy - gy, gx);
     const int l = lane_id();
-    sh[3 * l] = make_int4(sa[0], sb[0], sc[0], sa[1]);
-    sh[3 * l + 1] = make_int4(sb[1], sc[1], sa[2], sb[2]);
-    sh[3 * l + 2] = make_int4(sc[2], 0, 0, 0);
+    sh[2 * l] = make_int4(pack16(sa[0], sb[0]), sc[0], pack16(sa[1], sb[1]), sc[1]);
+    sh[2 * l + 1] = make_int4(pack16(sa[2], sb[2]), sc[2], 0, 0);
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   }
-  // lanes hold the points P (px, py): is P in the shadow of the slot-e edge? (e wave-uniform)
-  __device__ __forceinline__ bool in_shadow(int e, int px, int py) const {
-    const int4 p0 = sh[3 * e], p1 = sh[3 * e + 1], p2 = sh[3 * e + 2];   // one address for every lane
-    return max(max(mad24(p0.x, px, mad24(p0.y, py, p0.z)), mad24(p0.w, px, mad24(p1.x, py, p1.y))),
-               mad24(p1.z, px, mad24(p1.w, py, p2.x))) < 0;
+  // lanes hold the points P (pp = px | py << 16): is P in the shadow of the slot-e edge? (e wave-uniform)
+  __device__ __forceinline__ bool in_shadow(int e, int pp) const {
+    const int4 p0 = sh[2 * e], p1 = sh[2 * e + 1];   // one address for every lane
+    return max(max(dot2(p0.x, pp, p0.y), dot2(p0.z, pp, p0.w)), dot2(p1.x, pp, p1.y)) < 0;
   }
 };
 
@@ -398,7 +397,7 @@ __device__ __forceinline__ void genvis_rows(const Dev& d, const Geo& geo, int wi
             gny = uni(d.gens[gpos].ny);
   const int u0 = s * kGvSeg, u1 = min(u0 + kGvSeg, r);
   PairCache pc;
-  __shared__ int4 s_shadow[4][64 * 3];   // 256-thread workgroups: four wavefronts
+  __shared__ int4 s_shadow[4][64 * 2];   // 256-thread workgroups: four wavefronts
   pc.sh = s_shadow[threadIdx.x >> 6];
   pc.fill_near(geo, gx, gy);
   pc.set_shadow(gx, gy);
@@ -416,10 +415,11 @@ __device__ __forceinline__ void genvis_rows(const Dev& d, const Geo& geo, int wi
             (pv && into_interior(gu.ux, gu.uy, gu.x, gu.y, gu.nx, gu.ny, gx - gu.x, gy - gu.y));
     }
     const int ncache = min(pc.slot, kWave);
+    const int gp = pack16(gu.x, gu.y);
     for (int e = 0; e < ncache && ballot(!out); e += 4) {
 #pragma unroll
       for (int t = 0; t < 4; ++t)
-        if (e + t < ncache) out = out || pc.in_shadow(e + t, gu.x, gu.y);
+        if (e + t < ncache) out = out || pc.in_shadow(e + t, gp);
     }
     u64 todo = ballot(!out);
     bool seen = false;
@@ -441,7 +441,7 @@ __device__ __forceinline__ void genvis_rows(const Dev& d, const Geo& geo, int wi
           const int at = pc.slot & 63;
           pc.insert(fr);
           pc.set_shadow(gx, gy);
-          if (todo) todo &= ~ballot(pc.in_shadow(at, gu.x, gu.y));
+          if (todo) todo &= ~ballot(pc.in_shadow(at, gp));
         }
       }
     }

@@ -30,18 +30,6 @@ namespace spm {
 enum { ST_TILES = 0, ST_BATCHES, ST_BOUND, ST_VISWAVE, ST_RELEV, ST_LANEEDGE, ST_OCCL, ST_ACCEPT, ST_CACHE_TEST,
        ST_CACHE_HIT, ST_SEG_LANE, ST_CL_MEMBERS, ST_CL_TRIED, ST_CL_HIDDEN, ST_CL_UMBRA, ST_CL_UMBRA_TESTS, ST_COUNT };
 
-// Packs two values of magnitude below 2^15 into one register, and back.
-__device__ __forceinline__ int pack16(int lo, int hi) { return (int)(((unsigned)lo & 0xffffu) | ((unsigned)hi << 16)); }
-__device__ __forceinline__ int lo16(int x) { return (int)(short)(x & 0xffff); }
-__device__ __forceinline__ int hi16(int x) { return x >> 16; }
-// lo16(a) lo16(b) + hi16(a) hi16(b) + c in one instruction (v_dot2_i32_i16).
-// The products are exact and the sum wraps modulo 2^32, so the result is the
-// exact value whenever that fits an int32.
-typedef short spm_short2 __attribute__((ext_vector_type(2)));
-__device__ __forceinline__ int dot2(int a, int b, int c) {
-  return __builtin_amdgcn_sdot2(__builtin_bit_cast(spm_short2, a), __builtin_bit_cast(spm_short2, b), c, false);
-}
-
 // Occluder cache of one tile: one obstacle edge per lane.  The exact test of
 // a candidate generator g against a tile first asks whether a single edge hides
 // the whole tile box from g (every segment from the box to g properly crosses

@@ -412,6 +412,17 @@ __device__ __forceinline__ float unif(float x) {
 __device__ __forceinline__ int mul24(int a, int b) { return __mul24(a, b); }
 __device__ __forceinline__ int mad24(int a, int b, int c) { return __mul24(a, b) + c; }
 __device__ __forceinline__ int sgn3(int x) { return min(max(x, -1), 1); }
+// 16-bit halves packed in one register (doubled coordinates and coefficients below 2^15)
+__device__ __forceinline__ int pack16(int lo, int hi) { return (int)(((unsigned)lo & 0xffffu) | ((unsigned)hi << 16)); }
+__device__ __forceinline__ int lo16(int x) { return (int)(short)(x & 0xffff); }
+__device__ __forceinline__ int hi16(int x) { return x >> 16; }
+// lo16(a) lo16(b) + hi16(a) hi16(b) + c in one instruction (v_dot2_i32_i16).
+// The products are exact and the sum wraps modulo 2^32, so the result is the
+// exact value whenever that fits an int32.
+typedef short spm_short2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ int dot2(int a, int b, int c) {
+  return __builtin_amdgcn_sdot2(__builtin_bit_cast(spm_short2, a), __builtin_bit_cast(spm_short2, b), c, false);
+}
 
 __device__ __forceinline__ float wave_max(float v) {
 #pragma unroll
