@@ -106,6 +106,15 @@ def test_profiling_grid_sampled(oracle_mod, spm, k, seed):
     _sampled(oracle_mod, spm, scene, f"profiling-{k}x{k}-s{seed}", pix, max_ambiguous=0.08)
 
 
+@pytest.mark.parametrize("k,side,seed", [(6, 192, 1), (12, 384, 2)])
+def test_lattice_grid_full(oracle_mod, spm, k, side, seed):
+    """Squares on a lattice: lines from pixel centres to corners often pass exactly through other
+    corners, so the full visibility test's exact vertex rule decides many pixels.  The 12 x 12 map
+    (577 generators) runs the refilled walk with its edges, boxes and costs staged in LDS."""
+    _full(oracle_mod, spm, profiling_grid(k, side=side, seed=seed), f"lattice-{k}x{k}-{side}-s{seed}",
+          max_ambiguous=0.08)
+
+
 @pytest.mark.parametrize("tile", [(16, 4), (4, 16)])
 def test_tile_shapes_bitwise(spm, tile):
     scene = config2(1)
