@@ -1200,21 +1200,34 @@ __global__ __launch_bounds__(kOrderThreads) void k_tile_order(int W, int H, int 
   const int spr = (ntx + strip - 1) / strip;
   const int nitems = spr * nty;
   const float scale = (float)(2 * kOrderBins) / (float)(W + H);
+  // the wavefront's kPerWave items in one pass over the generators: each generator's record is read
+  // once for all of them
+  int cx[kPerWave], cy[kPerWave];
+  float lb[kPerWave];
+#pragma unroll
   for (int k = 0; k < kPerWave; ++k) {
-    const int li = wv * kPerWave + k;
-    const int item = blockIdx.x * kOrderItems + li;
-    if (item >= nitems) break;
+    const int item = min(blockIdx.x * kOrderItems + wv * kPerWave + k, nitems - 1);
     const int ty = item / spr, sx = item - ty * spr;
     const int t0 = sx * strip, t1 = min(t0 + strip, ntx);
-    const int cx = (t0 + t1) * TW, cy = (2 * ty + 1) * TH;   // item centre, doubled coordinates
-    float lb = INFINITY;
-    for (int h = lane; h < G; h += 64) {
-      const int4 b = sgbb[h];
-      const float dx = (float)max(max(b.x - cx, cx - b.z), 0), dy = (float)max(max(b.y - cy, cy - b.w), 0);
-      lb = fminf(lb, sgcost[h] + 0.5f * fsqrt(dx * dx + dy * dy));
+    cx[k] = (t0 + t1) * TW;   // item centre, doubled coordinates
+    cy[k] = (2 * ty + 1) * TH;
+    lb[k] = INFINITY;
+  }
+  for (int h = lane; h < G; h += 64) {
+    const int4 b = sgbb[h];
+    const float ch = sgcost[h];
+#pragma unroll
+    for (int k = 0; k < kPerWave; ++k) {
+      const float dx = (float)max(max(b.x - cx[k], cx[k] - b.z), 0), dy = (float)max(max(b.y - cy[k], cy[k] - b.w), 0);
+      lb[k] = fminf(lb[k], ch + 0.5f * fsqrt(dx * dx + dy * dy));
     }
+  }
+#pragma unroll
+  for (int k = 0; k < kPerWave; ++k) {
+    const int li = wv * kPerWave + k;
+    if (blockIdx.x * kOrderItems + li >= nitems) break;
     // lb >= 0, so its bits order as unsigned
-    const float f = __uint_as_float(wave_min_u32(__float_as_uint(lb))) * scale;
+    const float f = __uint_as_float(wave_min_u32(__float_as_uint(lb[k]))) * scale;
     const int c = f < (float)(kOrderBins - 1) ? (int)f : kOrderBins - 1;
     if (lane == 0) {
       const int cls = kOrderBins - 1 - c;
