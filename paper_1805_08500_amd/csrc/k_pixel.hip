@@ -1213,7 +1213,17 @@ __global__ __launch_bounds__(kOrderThreads) void k_tile_order(int W, int H, int 
     cy[k] = (2 * ty + 1) * TH;
     lb[k] = INFINITY;
   }
-  for (int h = lane; h < G; h += 64) {
+  for (int h0 = 0; h0 < G; h0 += 64) {
+    // the generators are in cost order: once the least cost of the next 64 reaches every item's bound
+    // found so far, none of the rest can lower one (checked every eighth step)
+    if (h0 > 0 && (h0 & 511) == 0) {
+      float most = 0.0f;
+#pragma unroll
+      for (int k = 0; k < kPerWave; ++k) most = fmaxf(most, __uint_as_float(wave_min_u32(__float_as_uint(lb[k]))));
+      if (unif(sgcost[h0]) >= most) break;
+    }
+    const int h = h0 + lane;
+    if (h >= G) continue;
     const int4 b = sgbb[h];
     const float ch = sgcost[h];
 #pragma unroll
