@@ -382,20 +382,21 @@ __device__ __forceinline__ void genvis_rows(const Dev& d, const Geo& geo, int wi
   const int nsrc = d.np + d.ns;
   const int lane = lane_id();
   relax_init(d, wid, G, nsrc);
-  if ((long long)wid >= rowseg_prefix(d.Gmax)) return;
-  int lo = 0, hi = d.Gmax;   // the row: the largest r with rowseg_prefix(r) <= wid
+  const int seg = d.gv_seg;
+  if ((long long)wid >= rowseg_prefix(d.Gmax, seg)) return;
+  int lo = 0, hi = d.Gmax;   // the row: the largest r with rowseg_prefix(r, seg) <= wid
   while (hi - lo > 1) {
     const int mid = (lo + hi) >> 1;
-    if (rowseg_prefix(mid) <= wid) lo = mid;
+    if (rowseg_prefix(mid, seg) <= wid) lo = mid;
     else hi = mid;
   }
-  const int r = lo, s = wid - (int)rowseg_prefix(r);
+  const int r = lo, s = wid - (int)rowseg_prefix(r, seg);
   if (r >= G || r < nsrc) return;   // only corner rows are read
   const int gpos = uni(d.gorder[r]);
   const int gx = uni(d.gens[gpos].x), gy = uni(d.gens[gpos].y);
   const int gux = uni(d.gens[gpos].ux), guy = uni(d.gens[gpos].uy), gnx = uni(d.gens[gpos].nx),
             gny = uni(d.gens[gpos].ny);
-  const int u0 = s * kGvSeg, u1 = min(u0 + kGvSeg, r);
+  const int u0 = s * seg, u1 = min(u0 + seg, r);
   PairCache pc;
   __shared__ int4 s_shadow[4][64 * 2];   // 256-thread workgroups: four wavefronts
   pc.sh = s_shadow[threadIdx.x >> 6];

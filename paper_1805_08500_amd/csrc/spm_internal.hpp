@@ -81,14 +81,15 @@ constexpr int kGvSpreadMaxGen = SPM_GV_SPREAD_MAX_GEN;   // pairs dealt round-ro
 #define SPM_GV_ROWS 1
 #endif
 constexpr long long kGvRowsBatchWaves = 4096;   // a batch uses the row mode when it would give the batch this many wavefronts
-constexpr int kGvSeg = 256;   // beyond: one wavefront per (row, 256 columns) with an occluder cache
+constexpr int kGvSeg = 256;   // beyond: one wavefront per (row, gv_seg columns) with an occluder cache; the
+                              // batches' segment length
 
-// Generator visibility by row segments: row r holds the pairs (r, u < r) in
-// ceil(r / kGvSeg) items; the items of rows 0 .. N-1 number
-// sum_{r < N} ceil(r / kGvSeg) = L q (q + 1) / 2 + (q + 1) (N - 1 - q L), q = (N - 1) / L.
-__host__ __device__ inline long long rowseg_prefix(long long N) {
+// Generator visibility by row segments of L columns: row r holds the pairs
+// (r, u < r) in ceil(r / L) items; the items of rows 0 .. N-1 number
+// sum_{r < N} ceil(r / L) = L q (q + 1) / 2 + (q + 1) (N - 1 - q L), q = (N - 1) / L.
+__host__ __device__ inline long long rowseg_prefix(long long N, long long L) {
   if (N <= 1) return 0;
-  const long long L = kGvSeg, q = (N - 1) / L;
+  const long long q = (N - 1) / L;
   return L * q * (q + 1) / 2 + (q + 1) * (N - 1 - q * L);
 }
 
@@ -259,7 +260,8 @@ struct Dev {
   int gv_sub;      // generator visibility: columns per wavefront (64, 32 or 16); 0: one pair at a time,
                    // lanes over edges (kGvPairRows x kGvPairRows blocks of the lower triangle);
                    // -1: the same pairs dealt round-robin over the triangle; -2: row segments of
-                   // kGvSeg pairs with an occluder cache
+                   // gv_seg pairs with an occluder cache
+  int gv_seg;      // row segment length (128, 256 or 512)
   u64* stats;
 };
 
@@ -305,7 +307,7 @@ __host__ __device__ inline int stage_count(const Dev& d, int stage) {
     case STG_CHUNK: return d.NC;
     case STG_ROW: return d.H;
     case STG_GVBLK: {
-      if (d.gv_sub == -2) return (int)((rowseg_prefix(d.Gmax) + 3) / 4);
+      if (d.gv_sub == -2) return (int)((rowseg_prefix(d.Gmax, d.gv_seg) + 3) / 4);
       if (d.gv_sub <= 0) {
         const long long B = (d.Gmax + kGvPairRows - 1) / kGvPairRows;
         return (int)((kGvPairRows * (B * (B + 1) / 2) + 3) / 4);
