@@ -81,8 +81,9 @@ constexpr int kGvSpreadMaxGen = SPM_GV_SPREAD_MAX_GEN;   // pairs dealt round-ro
 #define SPM_GV_ROWS 1
 #endif
 constexpr long long kGvRowsBatchWaves = 4096;   // a batch uses the row mode when it would give the batch this many wavefronts
-constexpr int kGvSeg = 256;   // beyond: one wavefront per (row, gv_seg columns) with an occluder cache; the
-                              // batches' segment length
+constexpr int kGvSeg = 512;   // beyond: one wavefront per (row, gv_seg columns) with an occluder cache; the
+                              // batches' segment length (config 4: 1.25-1.27 ms against 1.29 with 256, 1.37
+                              // with 128)
 
 // Generator visibility by row segments of L columns: row r holds the pairs
 // (r, u < r) in ceil(r / L) items; the items of rows 0 .. N-1 number
